@@ -1,0 +1,184 @@
+/*
+ * fipgemm -- GEMM with packing fused into the first computational pass, for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Operation (paper Sec. 2.1: the prototypical product C := A B + C, extended
+ * with the BLAS gemm statement's alpha, beta and op()):
+ *
+ *     C := alpha * op(A) * op(B) + beta * C,     op(A) m x k, op(B) k x n, C m x n
+ *
+ * Method (paper Sec. 3.1-3.3): operand panels are packed into a contiguous,
+ * zero-padded tile layout *during* the first pass that computes with them; a
+ * panel's later passes read only the packed copy.  Which operand is packed
+ * follows the paper's reuse table (Sec. 3.3): A's row panel is packed only
+ * when more than one tile column of C reuses it, B's column panel only when
+ * more than one tile row does.  Four variants of the tile body exist (A and B
+ * each read packed or unpacked, Sec. 3.2); the choice is made per tile and per
+ * k-step at run time.
+ *
+ * Conventions shared by every entry point:
+ *   - All matrix pointers are DEVICE pointers owned by the caller.  alpha and
+ *     beta are host values passed by value.
+ *   - layout is FIP_COL_MAJOR or FIP_ROW_MAJOR.  Stored element (r, c) of a
+ *     matrix with leading dimension ld sits at X[r + c*ld] (column-major) or
+ *     X[r*ld + c] (row-major).
+ *   - trans is one of 'N','n','T','t','C','c'; 'C' equals 'T' for real data.
+ *   - Calls enqueue work on the handle's stream and return before it
+ *     finishes.  A handle is not thread-safe; use one handle per stream.
+ *   - Nothing is allocated on the GEMM path: scratch memory (pack buffers,
+ *     flags) is the caller's workspace, see fip_set_workspace.
+ *
+ * Return codes:
+ *    0   success
+ *   >0   the 1-based position, in the entry point's own signature (handle
+ *        = 1), of the first invalid argument (LAPACK "info" style).  Checked
+ *        before any HIP call.
+ *   <0   FIP_ERR_* below.
+ * No entry point prints, throws or aborts.
+ */
+#ifndef FIPGEMM_H
+#define FIPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fip_handle_s* fip_handle_t;
+
+enum { FIP_COL_MAJOR = 0, FIP_ROW_MAJOR = 1 };
+enum { FIP_F64 = 0, FIP_F32 = 1 };
+
+/* Error codes (negative). */
+#define FIP_ERR_HANDLE (-1)      /* null or destroyed handle */
+#define FIP_ERR_WORKSPACE (-2)   /* packing needed but workspace unset or too small */
+#define FIP_ERR_LAUNCH (-3)      /* a HIP call failed (launch, memset) */
+#define FIP_ERR_UNSUPPORTED (-4) /* unsupported dtype / attribute / value */
+#define FIP_ERR_ALLOC (-5)       /* host allocation of the handle failed */
+
+/* Attributes (fip_set_attr / fip_get_attr). */
+enum {
+    /* Which operands are packed.  Value: one of FIP_PACK_*.  Default AUTO. */
+    FIP_ATTR_PACK_POLICY = 1,
+    /* Force a tile class: -1 = planner's choice (default); 0, 1, 2 = the
+       128x128, 64x64, 32x32 C tile classes. */
+    FIP_ATTR_TILE = 2,
+    /* 1: producers pack but never publish, so every consumer takes the
+       unpacked fallback (a test knob; the result must not change). */
+    FIP_ATTR_NO_PUBLISH = 3,
+    /* 1: count per-chunk events (packed, read packed, read unpacked) into
+       the workspace's statistics block (a diagnostic; costs atomics). */
+    FIP_ATTR_STATS = 4,
+    /* Read only: the epoch stamp of the most recent fused call (claims and
+       publish flags of that call hold this value). */
+    FIP_ATTR_EPOCH = 5,
+};
+
+enum {
+    FIP_PACK_AUTO = 0,         /* paper Sec. 3.3 reuse table */
+    FIP_PACK_ALL = 1,          /* pack both operands whatever the shape */
+    FIP_PACK_NONE = 2,         /* never pack (the unpacked "SUP" path, Sec. 2.3) */
+    FIP_PACK_CONSUME_ONLY = 3, /* read only packed panels written beforehand by
+                                  fip_pack (the pack-then-compute baseline) */
+};
+
+/*
+ * The plan of one call, in the caller's terms (op(A) is m x k, op(B) k x n).
+ * Packed layout (the contract): the pack of op(A) is ceil(m/MT)*ceil(k/KT)
+ * contiguous blocks of KT*MT elements; block (t, q) (tile row t, k-step q) is
+ * block number t*ceil(k/KT) + q, and inside it element (i, p) of op(A) sits
+ * at (p % KT)*MT + (i % MT).  The pack of op(B) is the same with (MT, i)
+ * replaced by (NT, j).  Entries outside the matrix are +0.0.  Element bits are
+ * copied unchanged; alpha is not folded in.
+ * The fused path keeps one copy per XCD (copies = 8), indexed by the
+ * hardware XCC id of the workgroup that packs it; copy c of op(A)'s pack
+ * starts at workspace + a_pack_offset + c * a_copy_bytes.  The standalone
+ * pack (fip_pack) and CONSUME_ONLY use copy 0.
+ */
+typedef struct {
+    int32_t dtype, layout;
+    int64_t m, n, k;
+    int32_t MT, NT, KT;        /* tile extent along m, along n, and the k-step */
+    int32_t tiles_m, tiles_n, ksteps;
+    int32_t tile_class;        /* 0: 128x128, 1: 64x64, 2: 32x32 */
+    int32_t pack_a, pack_b;    /* operand packed under this plan */
+    int32_t copies;            /* pack copies laid out in the workspace */
+    int32_t policy;            /* FIP_PACK_* in effect */
+    int64_t a_pack_offset, a_copy_bytes;
+    int64_t b_pack_offset, b_copy_bytes;
+    int64_t a_flag_offset, b_flag_offset;   /* uint32 [copies][tiles][ksteps] */
+    int64_t a_claim_offset, b_claim_offset; /* uint32 [copies][tiles] */
+    int64_t stats_offset;      /* 3 x uint64: packed, read packed, read unpacked */
+    int64_t workspace_bytes;   /* bytes this call needs */
+} fip_plan_t;
+
+int fip_create(fip_handle_t* handle);
+int fip_destroy(fip_handle_t handle);
+
+/* hip_stream: a hipStream_t (NULL = the default stream). */
+int fip_set_stream(fip_handle_t handle, void* hip_stream);
+
+int fip_set_attr(fip_handle_t handle, int attr, int64_t value);
+int fip_get_attr(fip_handle_t handle, int attr, int64_t* value);
+
+/*
+ * Hand the handle a caller-owned device buffer for pack panels, publish flags
+ * and statistics.  It must stay valid, and must not be used by anyone else,
+ * while calls using it may be in flight.  Setting a (new) workspace clears its
+ * flag area on the handle's stream.  bytes may be 0 (dptr NULL) to detach.
+ */
+int fip_set_workspace(fip_handle_t handle, void* dptr, size_t bytes);
+
+/*
+ * Plan a call without running it: tile class, pack decision and workspace
+ * layout for the given shape under the handle's current attributes.
+ * dtype: FIP_F64 or FIP_F32.  Writes *plan.  No HIP call is made.
+ */
+int fip_plan(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+             char transA, char transB, fip_plan_t* plan);
+
+/* The plan of the most recent successful fip_dgemm / fip_sgemm / fip_pack. */
+int fip_last_plan(fip_handle_t handle, fip_plan_t* plan);
+
+/*
+ * C := alpha*op(A)*op(B) + beta*C in binary64 (argument order follows the
+ * BLAS gemm statement after handle and layout).
+ * Leading dimensions must satisfy (column-major) lda >= max(1, transA=N ? m : k),
+ * ldb >= max(1, transB=N ? k : n), ldc >= max(1, m); row-major swaps the roles
+ * (lda >= max(1, transA=N ? k : m), ldb >= max(1, transB=N ? n : k),
+ * ldc >= max(1, n)).  A pointer is invalid only if it would be read.
+ * Quick returns (BLAS): m = 0 or n = 0 -> nothing; (alpha = 0 or k = 0) and
+ * beta = 1 -> nothing; alpha = 0 or k = 0 -> C := beta*C without reading A, B
+ * (beta = 0 writes zeros and does not read C).  beta = 0 never reads C.
+ */
+int fip_dgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, double alpha,
+              const double* A, int64_t lda, char transA, const double* B, int64_t ldb,
+              char transB, double beta, double* C, int64_t ldc);
+
+/* The same in binary32 (FP32 MFMA, FP32 accumulation). */
+int fip_sgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, float alpha,
+              const float* A, int64_t lda, char transA, const float* B, int64_t ldb,
+              char transB, float beta, float* C, int64_t ldc);
+
+/*
+ * Standalone pack (Sec. 2.1: conventional pack-then-compute): write copy 0 of
+ * the packed op(A) and op(B) that a CONSUME_ONLY call of the same shape,
+ * dtype (FIP_F64 / FIP_F32) and tile class reads.  Both operands are packed
+ * whatever the shape.  Arguments as in fip_dgemm.
+ */
+int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+             const void* A, int64_t lda, char transA, const void* B, int64_t ldb, char transB);
+
+/*
+ * Diagnostic: launch nblocks one-wave workgroups; workgroup b writes the
+ * hardware XCC id it ran on to d_out[b] (device array of nblocks uint32).
+ * The fused path's per-XCD pack copies are indexed by this id.
+ */
+int fip_xcc_map(fip_handle_t handle, uint32_t* d_out, int64_t nblocks);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIPGEMM_H */

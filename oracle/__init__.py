@@ -43,8 +43,14 @@ def lib():
         L.oracle_pack.restype = None
         L.oracle_materialize_op.argtypes = [ctypes.c_int, ch, i64, i64, vp, i64, vp]
         L.oracle_materialize_op.restype = None
+        L.oracle_num_threads.argtypes = []
+        L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def num_threads():
+    return int(lib().oracle_num_threads())
 
 
 def _f64(x):

@@ -35,6 +35,7 @@
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -60,6 +61,9 @@ static int64_t c_index(int layout, int64_t ldc, int64_t i, int64_t j)
 {
     return layout == OR_COL ? i + j * ldc : i * ldc + j;
 }
+
+/* Threads the OpenMP loops below will use. */
+int oracle_num_threads(void) { return omp_get_max_threads(); }
 
 /* Materialise op(X) (rows x cols) as a dense column-major binary64 array. */
 void oracle_materialize_op(int layout, char trans, int64_t rows, int64_t cols,

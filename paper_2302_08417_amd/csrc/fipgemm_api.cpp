@@ -1,0 +1,473 @@
+// C-ABI host layer: argument validation (before any HIP call), the planner
+// (operand normalisation, tile class, the paper's pack-option table, workspace
+// layout) and kernel launches.  See include/fipgemm.h for the contract.
+#include "fipgemm.h"
+
+#include <new>
+#include <string.h>
+
+#include "fip_internal.h"
+
+namespace {
+
+constexpr uint32_t kMagic = 0xF1F6E77u;
+constexpr uint32_t kEpochLimit = 0xFFFFFF00u;  // restart (and clear) before wrapping
+
+}  // namespace
+
+struct fip_handle_s {
+    uint32_t magic;
+    hipStream_t stream;
+    int policy;
+    int tile_override;
+    int no_publish;
+    int stats;
+    void* ws;
+    size_t ws_bytes;
+    uint32_t epoch;
+    int ws_needs_clear;
+    fip_plan_t last;
+    int has_last;
+};
+
+namespace {
+
+bool valid_handle(fip_handle_t h) { return h != nullptr && h->magic == kMagic; }
+bool valid_trans(char t)
+{
+    return t == 'N' || t == 'n' || t == 'T' || t == 't' || t == 'C' || t == 'c';
+}
+bool is_trans(char t) { return t != 'N' && t != 'n'; }
+int64_t max1(int64_t v) { return v > 1 ? v : 1; }
+int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// op(X)[r, c] = X[r*rs + c*cs] for the BLAS (layout, trans, ld) triple.
+void op_strides(int layout, char trans, int64_t ld, int64_t* rs, int64_t* cs)
+{
+    const bool col = layout == FIP_COL_MAJOR;
+    const bool t = is_trans(trans);
+    if (col != t) { *rs = 1; *cs = ld; }  // col-major N, row-major T
+    else { *rs = ld; *cs = 1; }           // col-major T, row-major N
+}
+
+// Kernel view of one call: C is always column-major; for row-major storage
+// the kernel computes C^T = op(B)^T op(A)^T, i.e. the operands swap sides.
+struct KernelShape {
+    int64_t M, N;     // kernel C rows / columns
+    bool swapped;     // kernel A-side is the caller's op(B)
+};
+
+KernelShape kernel_shape(int layout, int64_t m, int64_t n)
+{
+    if (layout == FIP_ROW_MAJOR) return {n, m, true};
+    return {m, n, false};
+}
+
+// Tile class: the largest C tile that still gives the 256 CUs about one tile
+// each.  The class only changes blocking parameters, never the algorithm.
+int choose_tile_class(int64_t M, int64_t N)
+{
+    const int64_t t128 = cdiv(M, 128) * cdiv(N, 128);
+    if (t128 >= 256) return 0;
+    const int64_t t64 = cdiv(M, 64) * cdiv(N, 64);
+    if (t64 >= 128) return 1;
+    return 2;
+}
+
+// Internal plan: kernel-side quantities plus the caller-facing fip_plan_t.
+struct Plan {
+    fip_plan_t pub;
+    KernelShape ks;
+    int elem;
+    int mode;
+    int kpack_a, kpack_b;           // packing in kernel terms
+    int64_t tilesKM, tilesKN, nK;
+    int64_t off_stats, off_aflag, off_bflag, off_aclaim, off_bclaim, off_apack, off_bpack;
+    int64_t apack_copy_elems, bpack_copy_elems;
+};
+
+void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+               bool standalone_pack, Plan* pl)
+{
+    memset(pl, 0, sizeof(*pl));
+    pl->elem = dtype == FIP_F64 ? 8 : 4;
+    pl->ks = kernel_shape(layout, m, n);
+    const int cls = h->tile_override >= 0 ? h->tile_override : choose_tile_class(pl->ks.M, pl->ks.N);
+    const int MT = fip::tile_mt(cls), NT = MT, KT = fip::tile_kt(cls, pl->elem);
+    pl->tilesKM = cdiv(pl->ks.M, MT);
+    pl->tilesKN = cdiv(pl->ks.N, NT);
+    pl->nK = cdiv(k, KT);
+
+    int policy = standalone_pack ? FIP_PACK_CONSUME_ONLY : h->policy;
+    int copies = 0;
+    if (policy == FIP_PACK_CONSUME_ONLY) {
+        pl->mode = fip::kModeConsumePacked;
+        pl->kpack_a = pl->kpack_b = 1;
+        copies = 1;
+    } else if (policy == FIP_PACK_NONE) {
+        pl->mode = fip::kModeUnpacked;
+    } else {
+        pl->mode = fip::kModeFused;
+        if (policy == FIP_PACK_ALL) {
+            pl->kpack_a = pl->kpack_b = 1;
+        } else {
+            // Paper Sec. 3.3: pack A's panel only if several tile columns of C
+            // reuse it (n > n_R), B's panel only if several tile rows do (m > m_R).
+            pl->kpack_a = pl->tilesKN > 1;
+            pl->kpack_b = pl->tilesKM > 1;
+        }
+        if (pl->kpack_a || pl->kpack_b) copies = fip::kCopies;
+    }
+    if (k == 0 || m == 0 || n == 0) { pl->kpack_a = pl->kpack_b = 0; copies = 0; }
+
+    int64_t off = 0;
+    pl->off_stats = off; off = align256(off + 3 * 8);
+    pl->off_aflag = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * pl->nK * 4 : 0));
+    pl->off_bflag = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * pl->nK * 4 : 0));
+    pl->off_aclaim = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * 4 : 0));
+    pl->off_bclaim = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * 4 : 0));
+    pl->apack_copy_elems = pl->kpack_a ? pl->tilesKM * pl->nK * KT * MT : 0;
+    pl->bpack_copy_elems = pl->kpack_b ? pl->tilesKN * pl->nK * KT * NT : 0;
+    pl->off_apack = off; off = align256(off + copies * pl->apack_copy_elems * pl->elem);
+    pl->off_bpack = off; off = align256(off + copies * pl->bpack_copy_elems * pl->elem);
+
+    fip_plan_t& p = pl->pub;
+    p.dtype = dtype; p.layout = layout; p.m = m; p.n = n; p.k = k;
+    p.tile_class = cls;
+    p.MT = MT; p.NT = NT; p.KT = KT;
+    p.ksteps = (int32_t)pl->nK;
+    p.copies = copies;
+    p.policy = policy;
+    p.stats_offset = pl->off_stats;
+    const bool fl = pl->mode == fip::kModeFused;
+    p.workspace_bytes = (pl->kpack_a || pl->kpack_b) ? off : 0;
+    // Report in the caller's terms: op(A) is the kernel's B-side when swapped.
+    if (!pl->ks.swapped) {
+        p.tiles_m = (int32_t)pl->tilesKM; p.tiles_n = (int32_t)pl->tilesKN;
+        p.pack_a = pl->kpack_a; p.pack_b = pl->kpack_b;
+        p.a_pack_offset = pl->off_apack; p.a_copy_bytes = pl->apack_copy_elems * pl->elem;
+        p.b_pack_offset = pl->off_bpack; p.b_copy_bytes = pl->bpack_copy_elems * pl->elem;
+        p.a_flag_offset = fl ? pl->off_aflag : -1; p.b_flag_offset = fl ? pl->off_bflag : -1;
+        p.a_claim_offset = fl ? pl->off_aclaim : -1; p.b_claim_offset = fl ? pl->off_bclaim : -1;
+    } else {
+        p.tiles_m = (int32_t)pl->tilesKN; p.tiles_n = (int32_t)pl->tilesKM;
+        p.pack_a = pl->kpack_b; p.pack_b = pl->kpack_a;
+        p.a_pack_offset = pl->off_bpack; p.a_copy_bytes = pl->bpack_copy_elems * pl->elem;
+        p.b_pack_offset = pl->off_apack; p.b_copy_bytes = pl->apack_copy_elems * pl->elem;
+        p.a_flag_offset = fl ? pl->off_bflag : -1; p.b_flag_offset = fl ? pl->off_aflag : -1;
+        p.a_claim_offset = fl ? pl->off_bclaim : -1; p.b_claim_offset = fl ? pl->off_aclaim : -1;
+        int32_t t = p.MT; p.MT = p.NT; p.NT = t;
+    }
+}
+
+// Validation of the BLAS-style argument list; returns the 1-based position of
+// the first invalid argument (handle = 1, layout = pos0) or 0.  Leading
+// dimensions are only judged once the transposes they depend on are valid.
+int check_args(int pos0, int layout, int64_t m, int64_t n, int64_t k, bool alpha_nonzero,
+               const void* A, int64_t lda, char tA, const void* B, int64_t ldb, char tB,
+               bool check_c, bool beta_one, const void* C, int64_t ldc)
+{
+    // positions relative to layout: m+1, n+2, k+3, alpha+4, A+5, lda+6, tA+7,
+    // B+8, ldb+9, tB+10, beta+11, C+12, ldc+13
+    if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return pos0;
+    if (m < 0) return pos0 + 1;
+    if (n < 0) return pos0 + 2;
+    if (k < 0) return pos0 + 3;
+    const bool tA_ok = valid_trans(tA), tB_ok = valid_trans(tB);
+    const bool col = layout == FIP_COL_MAJOR;
+    const bool reads_ab = m > 0 && n > 0 && k > 0 && alpha_nonzero;
+    const bool writes_c = check_c && m > 0 && n > 0 && !(beta_one && !reads_ab);
+    if (reads_ab && A == nullptr) return pos0 + 5;
+    if (tA_ok) {
+        const int64_t need = col ? (is_trans(tA) ? k : m) : (is_trans(tA) ? m : k);
+        if (lda < max1(need)) return pos0 + 6;
+    }
+    if (!tA_ok) return pos0 + 7;
+    if (reads_ab && B == nullptr) return pos0 + 8;
+    if (tB_ok) {
+        const int64_t need = col ? (is_trans(tB) ? n : k) : (is_trans(tB) ? k : n);
+        if (ldb < max1(need)) return pos0 + 9;
+    }
+    if (!tB_ok) return pos0 + 10;
+    if (check_c) {
+        if (writes_c && C == nullptr) return pos0 + 12;
+        if (ldc < max1(col ? m : n)) return pos0 + 13;
+    }
+    return 0;
+}
+
+// Fill the kernel descriptor's operand fields (kernel A-side/B-side).
+void fill_operands(const Plan& pl, int layout, const void* A, int64_t lda, char tA, const void* B,
+                   int64_t ldb, char tB, fip::LaunchDesc* d)
+{
+    int64_t rsA, csA, rsB, csB;
+    op_strides(layout, tA, lda, &rsA, &csA);
+    op_strides(layout, tB, ldb, &rsB, &csB);
+    // op(A) m x k: (x = i, p) -> smn = rsA, sk = csA.  op(B) k x n: (x = j, p)
+    // -> smn = csB, sk = rsB.
+    if (!pl.ks.swapped) {
+        d->A = A; d->a_smn = rsA; d->a_sk = csA;
+        d->B = B; d->b_smn = csB; d->b_sk = rsB;
+    } else {
+        d->A = B; d->a_smn = csB; d->a_sk = rsB;
+        d->B = A; d->b_smn = rsA; d->b_sk = csA;
+    }
+    // When a dimension has extent 1 both strides may be usable; prefer the
+    // MN-contiguous form when its stride is 1.
+    if (d->a_smn != 1 && d->a_sk != 1) d->a_smn = 0;  // flagged invalid below
+    if (d->b_smn != 1 && d->b_sk != 1) d->b_smn = 0;
+}
+
+void fill_workspace(const fip_handle_s* h, const Plan& pl, fip::LaunchDesc* d)
+{
+    char* ws = static_cast<char*>(h->ws);
+    d->stats_ptr = reinterpret_cast<unsigned long long*>(ws + pl.off_stats);
+    d->aflag = reinterpret_cast<uint32_t*>(ws + pl.off_aflag);
+    d->bflag = reinterpret_cast<uint32_t*>(ws + pl.off_bflag);
+    d->aclaim = reinterpret_cast<uint32_t*>(ws + pl.off_aclaim);
+    d->bclaim = reinterpret_cast<uint32_t*>(ws + pl.off_bclaim);
+    d->apack = ws + pl.off_apack;
+    d->bpack = ws + pl.off_bpack;
+    d->apack_copy_elems = pl.apack_copy_elems;
+    d->bpack_copy_elems = pl.bpack_copy_elems;
+}
+
+int prepare_workspace(fip_handle_s* h, const Plan& pl)
+{
+    if (pl.pub.workspace_bytes == 0) return 0;
+    if (h->ws == nullptr || (int64_t)h->ws_bytes < pl.pub.workspace_bytes) return FIP_ERR_WORKSPACE;
+    if (h->ws_needs_clear || h->epoch >= kEpochLimit) {
+        if (hipMemsetAsync(h->ws, 0, h->ws_bytes, h->stream) != hipSuccess) return FIP_ERR_LAUNCH;
+        h->ws_needs_clear = 0;
+        h->epoch = 0;
+    }
+    return 0;
+}
+
+template <typename T>
+int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64_t k, T alpha,
+              const T* A, int64_t lda, char tA, const T* B, int64_t ldb, char tB, T beta, T* C,
+              int64_t ldc)
+{
+    try {
+        if (!valid_handle(h)) return FIP_ERR_HANDLE;
+        const int bad = check_args(2, layout, m, n, k, alpha != T(0), A, lda, tA, B, ldb, tB, true,
+                                   beta == T(1), C, ldc);
+        if (bad) return bad;
+        if (m == 0 || n == 0) return 0;
+        if ((alpha == T(0) || k == 0) && beta == T(1)) return 0;
+        const KernelShape ks = kernel_shape(layout, m, n);
+        if (alpha == T(0) || k == 0) {
+            if (fip::launch_scale(sizeof(T), ks.M, ks.N, C, ldc, (double)beta, h->stream) != hipSuccess)
+                return FIP_ERR_LAUNCH;
+            return 0;
+        }
+        Plan pl;
+        make_plan(h, dtype, layout, m, n, k, false, &pl);
+        const int ws = prepare_workspace(h, pl);
+        if (ws) return ws;
+        fip::LaunchDesc d;
+        memset(&d, 0, sizeof(d));
+        d.elem = sizeof(T);
+        d.tile_class = pl.pub.tile_class;
+        d.mode = pl.mode;
+        d.pack_a = pl.kpack_a; d.pack_b = pl.kpack_b;
+        d.no_publish = h->no_publish;
+        d.stats = h->stats;
+        d.M = ks.M; d.N = ks.N; d.K = k;
+        fill_operands(pl, layout, A, lda, tA, B, ldb, tB, &d);
+        if (d.a_smn == 0 || d.b_smn == 0) return FIP_ERR_UNSUPPORTED;
+        d.C = C; d.ldc = ldc;
+        d.alpha = (double)alpha; d.beta = (double)beta;
+        if (pl.pub.workspace_bytes > 0) {
+            fill_workspace(h, pl, &d);
+            if (pl.mode == fip::kModeFused) d.epoch = ++h->epoch;
+        } else {
+            d.stats = 0;
+        }
+        d.stream = h->stream;
+        if (fip::launch_gemm(d) != hipSuccess) return FIP_ERR_LAUNCH;
+        h->last = pl.pub;
+        h->has_last = 1;
+        return 0;
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int fip_create(fip_handle_t* handle)
+{
+    if (handle == nullptr) return 1;
+    fip_handle_s* h = new (std::nothrow) fip_handle_s;
+    if (h == nullptr) return FIP_ERR_ALLOC;
+    memset(h, 0, sizeof(*h));
+    h->magic = kMagic;
+    h->stream = nullptr;
+    h->policy = FIP_PACK_AUTO;
+    h->tile_override = -1;
+    *handle = h;
+    return 0;
+}
+
+int fip_destroy(fip_handle_t handle)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    handle->magic = 0;
+    delete handle;
+    return 0;
+}
+
+int fip_set_stream(fip_handle_t handle, void* hip_stream)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    handle->stream = static_cast<hipStream_t>(hip_stream);
+    return 0;
+}
+
+int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    switch (attr) {
+    case FIP_ATTR_PACK_POLICY:
+        if (value < FIP_PACK_AUTO || value > FIP_PACK_CONSUME_ONLY) return 3;
+        handle->policy = (int)value;
+        return 0;
+    case FIP_ATTR_TILE:
+        if (value < -1 || value >= fip::kNumTileClasses) return 3;
+        handle->tile_override = (int)value;
+        return 0;
+    case FIP_ATTR_NO_PUBLISH:
+        if (value != 0 && value != 1) return 3;
+        handle->no_publish = (int)value;
+        return 0;
+    case FIP_ATTR_STATS:
+        if (value != 0 && value != 1) return 3;
+        handle->stats = (int)value;
+        return 0;
+    default:
+        return 2;
+    }
+}
+
+int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    if (value == nullptr) return 3;
+    switch (attr) {
+    case FIP_ATTR_PACK_POLICY: *value = handle->policy; return 0;
+    case FIP_ATTR_TILE: *value = handle->tile_override; return 0;
+    case FIP_ATTR_NO_PUBLISH: *value = handle->no_publish; return 0;
+    case FIP_ATTR_STATS: *value = handle->stats; return 0;
+    case FIP_ATTR_EPOCH: *value = handle->epoch; return 0;
+    default: return 2;
+    }
+}
+
+int fip_set_workspace(fip_handle_t handle, void* dptr, size_t bytes)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    if (dptr == nullptr && bytes != 0) return 2;
+    if (dptr != nullptr && ((uintptr_t)dptr & 255) != 0) return 2;  // 256-byte aligned
+    handle->ws = dptr;
+    handle->ws_bytes = dptr ? bytes : 0;
+    handle->ws_needs_clear = dptr != nullptr;
+    handle->epoch = 0;
+    return 0;
+}
+
+int fip_plan(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+             char transA, char transB, fip_plan_t* plan)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    if (dtype != FIP_F64 && dtype != FIP_F32) return 2;
+    if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 3;
+    if (m < 0) return 4;
+    if (n < 0) return 5;
+    if (k < 0) return 6;
+    if (!valid_trans(transA)) return 7;
+    if (!valid_trans(transB)) return 8;
+    if (plan == nullptr) return 9;
+    Plan pl;
+    make_plan(handle, dtype, layout, m, n, k, false, &pl);
+    *plan = pl.pub;
+    return 0;
+}
+
+int fip_last_plan(fip_handle_t handle, fip_plan_t* plan)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    if (plan == nullptr) return 2;
+    if (!handle->has_last) return FIP_ERR_UNSUPPORTED;
+    *plan = handle->last;
+    return 0;
+}
+
+int fip_dgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, double alpha,
+              const double* A, int64_t lda, char transA, const double* B, int64_t ldb,
+              char transB, double beta, double* C, int64_t ldc)
+{
+    return gemm_impl<double>(handle, FIP_F64, layout, m, n, k, alpha, A, lda, transA, B, ldb,
+                             transB, beta, C, ldc);
+}
+
+int fip_sgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, float alpha,
+              const float* A, int64_t lda, char transA, const float* B, int64_t ldb, char transB,
+              float beta, float* C, int64_t ldc)
+{
+    return gemm_impl<float>(handle, FIP_F32, layout, m, n, k, alpha, A, lda, transA, B, ldb,
+                            transB, beta, C, ldc);
+}
+
+int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+             const void* A, int64_t lda, char transA, const void* B, int64_t ldb, char transB)
+{
+    try {
+        if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+        if (dtype != FIP_F64 && dtype != FIP_F32) return 2;
+        // positions: layout 3, m 4, n 5, k 6, A 7, lda 8, transA 9, B 10, ldb 11, transB 12
+        const int bad = check_args(3, layout, m, n, k, true, A, lda, transA, B, ldb, transB, false,
+                                   false, nullptr, 1);
+        if (bad) {
+            // check_args numbers alpha as an argument; fip_pack has none, so
+            // positions after k shift down by one.
+            return bad > 6 ? bad - 1 : bad;
+        }
+        Plan pl;
+        make_plan(handle, dtype, layout, m, n, k, true, &pl);
+        if (pl.pub.workspace_bytes == 0) { handle->last = pl.pub; handle->has_last = 1; return 0; }
+        const int ws = prepare_workspace(handle, pl);
+        if (ws) return ws;
+        fip::LaunchDesc d;
+        memset(&d, 0, sizeof(d));
+        d.elem = pl.elem;
+        d.tile_class = pl.pub.tile_class;
+        d.mode = pl.mode;
+        d.M = pl.ks.M; d.N = pl.ks.N; d.K = k;
+        fill_operands(pl, layout, A, lda, transA, B, ldb, transB, &d);
+        if (d.a_smn == 0 || d.b_smn == 0) return FIP_ERR_UNSUPPORTED;
+        fill_workspace(handle, pl, &d);
+        d.stream = handle->stream;
+        if (fip::launch_pack(d) != hipSuccess) return FIP_ERR_LAUNCH;
+        handle->last = pl.pub;
+        handle->has_last = 1;
+        return 0;
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+int fip_xcc_map(fip_handle_t handle, uint32_t* d_out, int64_t nblocks)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    if (d_out == nullptr) return 2;
+    if (nblocks < 0 || nblocks > (int64_t)1 << 30) return 3;
+    if (nblocks == 0) return 0;
+    return fip::launch_xcc_map(d_out, nblocks, handle->stream) == hipSuccess ? 0 : FIP_ERR_LAUNCH;
+}
+
+}  // extern "C"

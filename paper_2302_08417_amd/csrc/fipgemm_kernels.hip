@@ -1,0 +1,576 @@
+// HIP kernels of the fused-pack GEMM for gfx950 (CDNA4).
+//
+// One tile kernel serves every problem size (paper Sec. 3: a single code path
+// from which the unpacked "SUP" algorithm and conventional pack-then-compute
+// fall out as special cases).  A workgroup computes one MT x NT tile of C,
+// stepping through k in chunks of KT.  For each k-step it stages the A-side
+// chunk (MT x KT) and B-side chunk (NT x KT) in LDS, double buffered, and runs
+// 16x16x4 MFMAs on them (FP64 or FP32 accumulate).
+//
+// Fused packing (Sec. 3.2): the first workgroup (per XCD) that touches an
+// operand panel claims it and becomes its producer: for every k-step it loads
+// the unpacked chunk from HBM (coalesced along whichever stride is 1, masked
+// with zero fill at the fringes, Sec. 2.2), and stores the same registers both
+// to LDS for its own MFMAs and to the HBM pack buffer at the chunk's canonical
+// position.  Once a chunk's pack stores are complete the producer publishes a
+// per-(panel, k-step) flag stamped with the call's epoch.  Every other
+// workgroup on that XCD needing the panel checks the flag per k-step: if set,
+// it reads the packed, contiguous, aligned chunk (16-byte vector loads, no
+// masks); otherwise it reads the unpacked operand itself.  Nobody ever waits,
+// so the schedule cannot deadlock, and both sources hold identical bits, so
+// the result does not depend on timing.
+//
+// Which panels are packed follows the paper's reuse table (Sec. 3.3), decided
+// on the host.  The paper's shared-A, private-B multithreading scheme
+// (Sec. 3.5) maps to per-XCD pack copies: each XCD has its own L2, so a copy
+// written and read by one XCD needs no cross-L2 cache maintenance.
+#include "fip_internal.h"
+
+namespace fip {
+namespace {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Types;
+template <> struct Types<double> { typedef d2 vec; typedef d4 acc; static constexpr int VEC = 2; };
+template <> struct Types<float> { typedef f4 vec; typedef f4 acc; static constexpr int VEC = 4; };
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Hardware id of the XCD (XCC) running this wave: hwreg XCC_ID, bits [3:0].
+__device__ __forceinline__ unsigned xcc_id()
+{
+    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11));
+}
+
+// Wait until every memory operation this wave issued has completed; for
+// global stores that means the XCD's L2 has acknowledged them.
+__device__ __forceinline__ void wait_all_memory()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <typename T>
+struct Params {
+    const T* A; const T* B; T* C;
+    int64_t a_smn, a_sk, b_smn, b_sk, ldc;
+    int64_t M, N, K;
+    T alpha, beta;
+    T* apack; T* bpack;
+    int64_t apack_copy, bpack_copy;
+    uint32_t* aflag; uint32_t* bflag; uint32_t* aclaim; uint32_t* bclaim;
+    unsigned long long* stats;
+    uint32_t epoch;
+    int tilesM, tilesN, nK, group_m;
+    int mode, pack_a, pack_b, no_publish, do_stats;
+    int a_vec, b_vec, c_vec;
+};
+
+// LDS row pitch in elements: the tile extent plus padding so that the four
+// k-rows one MFMA fragment read touches start 16 elements apart modulo the 64
+// 4-byte banks (conflict-free ds_read of a 16x4 fragment).  Rows stay 16-byte
+// aligned.
+template <typename T, int MNT>
+constexpr int lds_pitch()
+{
+    constexpr int mod = 256 / (int)sizeof(T);
+    return MNT + (((16 - MNT) % mod) + mod) % mod;
+}
+
+// One operand chunk (MNT x KT) held in registers while it moves from HBM to
+// LDS (and, for a producer, to the pack buffer).
+//   Linear mapping: register vector i covers packed positions o .. o+VEC-1 with
+//     o = (tid + i*NTHR)*VEC, i.e. k-row pp = o / MNT, columns xx = o % MNT ...
+//     Used for packed sources and for unpacked operands contiguous along MN.
+//   Transposed mapping (unpacked operand contiguous along k): vector i covers
+//     k-rows pp .. pp+VEC-1 of column xx, with v = tid + i*NTHR, xx = v / KV,
+//     pp = (v % KV)*VEC.
+template <typename T, int MNT, int KT, int NTHR, bool KC>
+struct Chunk {
+    typedef typename Types<T>::vec V;
+    static constexpr int VEC = Types<T>::VEC;
+    static constexpr int NV = MNT * KT / (NTHR * VEC);
+    static constexpr int LDP = lds_pitch<T, MNT>();
+    static constexpr int KV = KT / VEC;
+    static_assert(NV * NTHR * VEC == MNT * KT, "chunk must split evenly over the threads");
+    static_assert(MNT % VEC == 0 && KT % VEC == 0, "vector width must divide the chunk");
+
+    V r[NV];
+
+    // Unpacked source: element (x, p) at X[x*smn + p*sk]; one of smn, sk is 1.
+    __device__ __forceinline__ void load_unpacked(const T* __restrict__ X, int64_t smn, int64_t sk,
+                                                  int64_t MN, int64_t K, int64_t x0, int64_t p0,
+                                                  bool vec_ok, int tid)
+    {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (!KC) {
+                const int o = (tid + i * NTHR) * VEC;
+                const int64_t x = x0 + o % MNT, p = p0 + o / MNT;
+                const T* src = X + x + p * sk;
+                if (vec_ok && p < K && x + VEC <= MN) {
+                    r[i] = *reinterpret_cast<const V*>(src);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) r[i][e] = (p < K && x + e < MN) ? src[e] : T(0);
+                }
+            } else {
+                const int v = tid + i * NTHR;
+                const int64_t x = x0 + v / KV, p = p0 + (v % KV) * VEC;
+                const T* src = X + x * smn + p;
+                if (vec_ok && x < MN && p + VEC <= K) {
+                    r[i] = *reinterpret_cast<const V*>(src);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) r[i][e] = (x < MN && p + e < K) ? src[e] : T(0);
+                }
+            }
+        }
+    }
+
+    // Packed source: one contiguous, zero-padded chunk; always vector loads.
+    __device__ __forceinline__ void load_packed(const T* __restrict__ chunk, int tid)
+    {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            r[i] = *reinterpret_cast<const V*>(chunk + (tid + i * NTHR) * VEC);
+    }
+
+    __device__ __forceinline__ void store_lds(T* lds, bool linear, int tid) const
+    {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (!KC || linear) {
+                const int o = (tid + i * NTHR) * VEC;
+                *reinterpret_cast<V*>(lds + (o / MNT) * LDP + o % MNT) = r[i];
+            } else {
+                const int v = tid + i * NTHR;
+                const int xx = v / KV, pp = (v % KV) * VEC;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) lds[(pp + e) * LDP + xx] = r[i][e];
+            }
+        }
+    }
+
+    // Pack store of registers loaded from the unpacked source.
+    __device__ __forceinline__ void store_pack(T* __restrict__ chunk, int tid) const
+    {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (!KC) {
+                *reinterpret_cast<V*>(chunk + (tid + i * NTHR) * VEC) = r[i];
+            } else {
+                const int v = tid + i * NTHR;
+                const int xx = v / KV, pp = (v % KV) * VEC;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) chunk[(pp + e) * MNT + xx] = r[i][e];
+            }
+        }
+    }
+};
+
+// Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs,
+// so w % 8 is (normally) the XCD.  Each XCD gets one contiguous run of the
+// grouped tile order (GROUP_M tile rows swept column by column), which keeps
+// the tiles running together on an XCD compact for its L2 and keeps most of
+// the panels an XCD packs private to it.
+__device__ __forceinline__ void tile_coords(int w, int tilesM, int tilesN, int group_m, int& tm,
+                                            int& tn)
+{
+    const int T = tilesM * tilesN;
+    const int xcd = w & 7, local = w >> 3;
+    const int q = T >> 3, rr = T & 7;
+    const int t = xcd * q + min(xcd, rr) + local;
+    const int per_group = group_m * tilesN;
+    const int g = t / per_group;
+    const int first_m = g * group_m;
+    const int gsize = min(tilesM - first_m, group_m);
+    const int rem = t - g * per_group;
+    tm = first_m + rem % gsize;
+    tn = rem / gsize;
+}
+
+template <typename T, int NTHR>
+__device__ __forceinline__ void load4(const T* p, bool vec, T out[4])
+{
+    typedef typename Types<T>::vec V;
+    constexpr int VEC = Types<T>::VEC;
+    if (vec) {
+#pragma unroll
+        for (int h = 0; h < 4 / VEC; ++h) {
+            const V v = *reinterpret_cast<const V*>(p + h * VEC);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) out[h * VEC + e] = v[e];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[e] = p[e];
+    }
+}
+
+template <typename T, int MT, int NT, int KT, int WM, int WN, bool AKC, bool BKC>
+__global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P)
+{
+    constexpr int NTHR = WM * WN * 64;
+    typedef Chunk<T, MT, KT, NTHR, AKC> ChA;
+    typedef Chunk<T, NT, KT, NTHR, BKC> ChB;
+    typedef typename Types<T>::acc Acc;
+    typedef typename Types<T>::vec V;
+    constexpr int VEC = Types<T>::VEC;
+    constexpr int WTM = MT / WM, WTN = NT / WN;  // per-wave C sub-tile
+    constexpr int FM = WTM / 16, FN = WTN / 16;  // MFMA blocks per wave
+    static_assert(FM >= 1 && FN >= 1 && KT % 4 == 0, "tile shape");
+
+    __shared__ __attribute__((aligned(16))) T sA[2][KT * ChA::LDP];
+    __shared__ __attribute__((aligned(16))) T sB[2][KT * ChB::LDP];
+    __shared__ int s_role;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    int tm, tn;
+    tile_coords(blockIdx.x, P.tilesM, P.tilesN, P.group_m, tm, tn);
+    const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * NT;
+    const int nK = P.nK;
+    const uint32_t epoch = P.epoch;
+
+    const bool consume = P.mode == kModeConsumePacked;
+    bool fused = P.mode == kModeFused;
+    int copy = 0;
+    if (fused) {
+        const unsigned x = xcc_id();
+        if (x < (unsigned)kCopies) copy = (int)x;
+        else fused = false;  // unknown XCD id: this workgroup stays unpacked
+    }
+    const bool useA = fused && P.pack_a, useB = fused && P.pack_b;
+
+    T* apanel = nullptr;
+    T* bpanel = nullptr;
+    if (useA || consume) apanel = P.apack + (int64_t)copy * P.apack_copy + (int64_t)tm * nK * KT * MT;
+    if (useB || consume) bpanel = P.bpack + (int64_t)copy * P.bpack_copy + (int64_t)tn * nK * KT * NT;
+    uint32_t* aflags = useA ? P.aflag + ((int64_t)copy * P.tilesM + tm) * nK : nullptr;
+    uint32_t* bflags = useB ? P.bflag + ((int64_t)copy * P.tilesN + tn) * nK : nullptr;
+
+    if (tid == 0) {
+        int role = 0;
+        if (useA && __hip_atomic_exchange(P.aclaim + copy * P.tilesM + tm, epoch, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) != epoch)
+            role |= 1;
+        if (useB && __hip_atomic_exchange(P.bclaim + copy * P.tilesN + tn, epoch, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) != epoch)
+            role |= 2;
+        s_role = role;
+    }
+    __syncthreads();
+    const bool prodA = s_role & 1, prodB = s_role & 2;
+    const bool producer = prodA || prodB;
+
+    // Source of chunk q: packed copy (true) or the unpacked operand (false).
+    auto published = [&](const uint32_t* flags, int q) -> bool {
+        const uint32_t f = __hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        return __builtin_amdgcn_readfirstlane(f) == epoch;
+    };
+    auto a_packed = [&](int q) -> bool {
+        if (consume) return true;
+        if (!useA || prodA) return false;
+        return published(aflags, q);
+    };
+    auto b_packed = [&](int q) -> bool {
+        if (consume) return true;
+        if (!useB || prodB) return false;
+        return published(bflags, q);
+    };
+
+    unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0;
+    ChA ra;
+    ChB rb;
+    auto load_chunks = [&](int q, bool apk, bool bpk) {
+        if (apk) ra.load_packed(apanel + (int64_t)q * KT * MT, tid);
+        else ra.load_unpacked(P.A, P.a_smn, P.a_sk, P.M, P.K, x0a, (int64_t)q * KT, P.a_vec, tid);
+        if (bpk) rb.load_packed(bpanel + (int64_t)q * KT * NT, tid);
+        else rb.load_unpacked(P.B, P.b_smn, P.b_sk, P.N, P.K, x0b, (int64_t)q * KT, P.b_vec, tid);
+        if (P.do_stats) {
+            n_prod += (int)prodA + (int)prodB;
+            n_pk += (int)apk + (int)bpk;
+            n_unpk += (int)(useA && !prodA && !apk) + (int)(useB && !prodB && !bpk);
+        }
+    };
+
+    Acc acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
+
+    // Prologue: chunk 0.
+    {
+        const bool apk = a_packed(0), bpk = b_packed(0);
+        load_chunks(0, apk, bpk);
+        ra.store_lds(sA[0], apk, tid);
+        rb.store_lds(sB[0], bpk, tid);
+        if (prodA) ra.store_pack(apanel, tid);
+        if (prodB) rb.store_pack(bpanel, tid);
+    }
+    __syncthreads();
+
+    for (int q = 0; q < nK; ++q) {
+        const int cur = q & 1;
+        const bool more = q + 1 < nK;
+        bool apk = false, bpk = false;
+        if (more) {
+            apk = a_packed(q + 1);
+            bpk = b_packed(q + 1);
+            load_chunks(q + 1, apk, bpk);
+        }
+        // MFMAs on chunk q.
+        const T* la = sA[cur] + wm * WTM + (lane & 15);
+        const T* lb = sB[cur] + wn * WTN + (lane & 15);
+#pragma unroll
+        for (int s = 0; s < KT / 4; ++s) {
+            const int kr = 4 * s + (lane >> 4);
+            T af[FM], bf[FN];
+#pragma unroll
+            for (int a = 0; a < FM; ++a) af[a] = la[kr * ChA::LDP + a * 16];
+#pragma unroll
+            for (int b = 0; b < FN; ++b) bf[b] = lb[kr * ChB::LDP + b * 16];
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(af[a], bf[b], acc[a][b]);
+        }
+        // Pack stores of chunk q (issued one step earlier) must be complete
+        // before chunk q is published below.
+        if (producer) wait_all_memory();
+        if (more) {
+            ra.store_lds(sA[cur ^ 1], apk, tid);
+            rb.store_lds(sB[cur ^ 1], bpk, tid);
+            if (prodA) ra.store_pack(apanel + (int64_t)(q + 1) * KT * MT, tid);
+            if (prodB) rb.store_pack(bpanel + (int64_t)(q + 1) * KT * NT, tid);
+        }
+        __syncthreads();
+        if (tid == 0 && producer && !P.no_publish) {
+            if (prodA) __hip_atomic_store(aflags + q, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prodB) __hip_atomic_store(bflags + q, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    if (P.do_stats && tid == 0) {
+        atomicAdd(P.stats + 0, n_prod);
+        atomicAdd(P.stats + 1, n_pk);
+        atomicAdd(P.stats + 2, n_unpk);
+    }
+
+    // Epilogue: C = alpha*acc + beta*C (C not read when beta == 0).  MFMA
+    // 16x16 output layout: lane l holds column l%16, rows 4*(l/16) .. +3.
+    const T alpha = P.alpha, beta = P.beta;
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+        const int64_t i0 = x0a + wm * WTM + a * 16 + 4 * (lane >> 4);
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int64_t j = x0b + wn * WTN + b * 16 + (lane & 15);
+            if (j >= P.N || i0 >= P.M) continue;
+            T* cp = P.C + i0 + j * P.ldc;
+            const bool full = i0 + 4 <= P.M;
+            const bool vec = full && P.c_vec;
+            T out[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[r] = alpha * acc[a][b][r];
+            if (beta != T(0)) {
+                T c0[4];
+                if (full) load4<T, NTHR>(cp, vec, c0);
+                else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) c0[r] = (i0 + r < P.M) ? cp[r] : T(0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) out[r] = out[r] + beta * c0[r];
+            }
+            if (vec) {
+#pragma unroll
+                for (int h = 0; h < 4 / VEC; ++h) {
+                    V v;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[e] = out[h * VEC + e];
+                    *reinterpret_cast<V*>(cp + h * VEC) = v;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (i0 + r < P.M) cp[r] = out[r];
+            }
+        }
+    }
+}
+
+// Standalone pack of both operands into copy 0 (the first half of the
+// conventional pack-then-compute baseline).  Same register mapping and
+// stores as a producer of the tile kernel, one chunk per workgroup.
+template <typename T, int MT, int NT, int KT, int NTHR, bool AKC, bool BKC>
+__global__ void __launch_bounds__(NTHR) pack_kernel(const Params<T> P)
+{
+    const int tid = threadIdx.x;
+    const int nK = P.nK;
+    const int64_t nA = (int64_t)P.tilesM * nK;
+    const int64_t b = blockIdx.x;
+    if (b < nA) {
+        const int64_t t = b / nK, q = b % nK;
+        Chunk<T, MT, KT, NTHR, AKC> r;
+        r.load_unpacked(P.A, P.a_smn, P.a_sk, P.M, P.K, t * MT, q * KT, P.a_vec, tid);
+        r.store_pack(P.apack + (t * nK + q) * KT * MT, tid);
+    } else {
+        const int64_t bb = b - nA;
+        const int64_t t = bb / nK, q = bb % nK;
+        Chunk<T, NT, KT, NTHR, BKC> r;
+        r.load_unpacked(P.B, P.b_smn, P.b_sk, P.N, P.K, t * NT, q * KT, P.b_vec, tid);
+        r.store_pack(P.bpack + (t * nK + q) * KT * NT, tid);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) scale_kernel(T* C, int64_t M, int64_t N, int64_t ldc, T beta)
+{
+    const int64_t total = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t i = idx % M, j = idx / M;
+        T* p = C + i + j * ldc;
+        *p = beta == T(0) ? T(0) : beta * *p;
+    }
+}
+
+__global__ void __launch_bounds__(64) xcc_map_kernel(uint32_t* out)
+{
+    if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
+}
+
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+template <typename T>
+Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
+{
+    constexpr int VEC = Types<T>::VEC;
+    Params<T> P{};
+    P.A = static_cast<const T*>(d.A);
+    P.B = static_cast<const T*>(d.B);
+    P.C = static_cast<T*>(d.C);
+    P.a_smn = d.a_smn; P.a_sk = d.a_sk; P.b_smn = d.b_smn; P.b_sk = d.b_sk; P.ldc = d.ldc;
+    P.M = d.M; P.N = d.N; P.K = d.K;
+    P.alpha = (T)d.alpha; P.beta = (T)d.beta;
+    P.apack = static_cast<T*>(d.apack); P.bpack = static_cast<T*>(d.bpack);
+    P.apack_copy = d.apack_copy_elems; P.bpack_copy = d.bpack_copy_elems;
+    P.aflag = d.aflag; P.bflag = d.bflag; P.aclaim = d.aclaim; P.bclaim = d.bclaim;
+    P.stats = d.stats_ptr;
+    P.epoch = d.epoch;
+    P.tilesM = (int)((d.M + MT - 1) / MT);
+    P.tilesN = (int)((d.N + NT - 1) / NT);
+    P.nK = (int)((d.K + KT - 1) / KT);
+    P.group_m = 8;
+    P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
+    P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
+    const int64_t a_far = d.a_smn == 1 ? d.a_sk : d.a_smn;  // the non-unit stride
+    const int64_t b_far = d.b_smn == 1 ? d.b_sk : d.b_smn;
+    P.a_vec = aligned16(d.A) && a_far % VEC == 0;
+    P.b_vec = aligned16(d.B) && b_far % VEC == 0;
+    P.c_vec = aligned16(d.C) && d.ldc % VEC == 0;
+    return P;
+}
+
+template <typename T, int MT, int NT, int WM, int WN>
+hipError_t launch_tile(const LaunchDesc& d)
+{
+    constexpr int KT = sizeof(T) == 8 ? 16 : 32;
+    const Params<T> P = make_params<T>(d, MT, NT, KT);
+    const bool akc = d.a_smn != 1, bkc = d.b_smn != 1;
+    const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN)), block(WM * WN * 64);
+    if (!akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, false><<<grid, block, 0, d.stream>>>(P);
+    else if (!akc && bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, true><<<grid, block, 0, d.stream>>>(P);
+    else if (akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, true, false><<<grid, block, 0, d.stream>>>(P);
+    else gemm_kernel<T, MT, NT, KT, WM, WN, true, true><<<grid, block, 0, d.stream>>>(P);
+    return hipGetLastError();
+}
+
+template <typename T, int MT, int NT, int WM, int WN>
+hipError_t launch_pack_t(const LaunchDesc& d)
+{
+    constexpr int KT = sizeof(T) == 8 ? 16 : 32;
+    constexpr int NTHR = WM * WN * 64;
+    const Params<T> P = make_params<T>(d, MT, NT, KT);
+    const bool akc = d.a_smn != 1, bkc = d.b_smn != 1;
+    const int64_t blocks = ((int64_t)P.tilesM + P.tilesN) * P.nK;
+    const dim3 grid((unsigned)blocks), block(NTHR);
+    if (!akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, false, false><<<grid, block, 0, d.stream>>>(P);
+    else if (!akc && bkc) pack_kernel<T, MT, NT, KT, NTHR, false, true><<<grid, block, 0, d.stream>>>(P);
+    else if (akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, true, false><<<grid, block, 0, d.stream>>>(P);
+    else pack_kernel<T, MT, NT, KT, NTHR, true, true><<<grid, block, 0, d.stream>>>(P);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_gemm(const LaunchDesc& d)
+{
+    switch (d.tile_class) {
+    case 0: return launch_tile<T, 128, 128, 2, 2>(d);
+    case 1: return launch_tile<T, 64, 64, 2, 2>(d);
+    case 2: return launch_tile<T, 32, 32, 2, 2>(d);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t dispatch_pack(const LaunchDesc& d)
+{
+    switch (d.tile_class) {
+    case 0: return launch_pack_t<T, 128, 128, 2, 2>(d);
+    case 1: return launch_pack_t<T, 64, 64, 2, 2>(d);
+    case 2: return launch_pack_t<T, 32, 32, 2, 2>(d);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const LaunchDesc& d)
+{
+    return d.elem == 8 ? dispatch_gemm<double>(d) : dispatch_gemm<float>(d);
+}
+
+hipError_t launch_pack(const LaunchDesc& d)
+{
+    return d.elem == 8 ? dispatch_pack<double>(d) : dispatch_pack<float>(d);
+}
+
+hipError_t launch_xcc_map(uint32_t* out, int64_t nblocks, hipStream_t stream)
+{
+    xcc_map_kernel<<<dim3((unsigned)nblocks), dim3(64), 0, stream>>>(out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(int elem, int64_t M, int64_t N, void* C, int64_t ldc, double beta,
+                        hipStream_t stream)
+{
+    const int64_t total = M * N;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    if (elem == 8)
+        scale_kernel<double><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(
+            static_cast<double*>(C), M, N, ldc, beta);
+    else
+        scale_kernel<float><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(
+            static_cast<float*>(C), M, N, ldc, (float)beta);
+    return hipGetLastError();
+}
+
+}  // namespace fip

@@ -1,0 +1,245 @@
+"""Thin Python binding of libfipgemm.so (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch is used only to own device
+memory (tensors' data pointers) and to supply the HIP stream.  If the shared
+object is missing this module raises at import time: there is no fallback.
+
+The functions keep the C names and argument order of include/fipgemm.h.
+Matrix arguments may be torch tensors (their data_ptr() is passed) or plain
+integer device addresses.
+"""
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfipgemm.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "fipgemm.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2302_08417_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FIP_COL_MAJOR, FIP_ROW_MAJOR = 0, 1
+FIP_F64, FIP_F32 = 0, 1
+FIP_ERR_HANDLE, FIP_ERR_WORKSPACE, FIP_ERR_LAUNCH, FIP_ERR_UNSUPPORTED, FIP_ERR_ALLOC = -1, -2, -3, -4, -5
+FIP_ATTR_PACK_POLICY, FIP_ATTR_TILE, FIP_ATTR_NO_PUBLISH, FIP_ATTR_STATS, FIP_ATTR_EPOCH = 1, 2, 3, 4, 5
+FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
+COPIES = 8
+
+
+class fip_plan_t(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32), ("layout", ctypes.c_int32),
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+        ("MT", ctypes.c_int32), ("NT", ctypes.c_int32), ("KT", ctypes.c_int32),
+        ("tiles_m", ctypes.c_int32), ("tiles_n", ctypes.c_int32), ("ksteps", ctypes.c_int32),
+        ("tile_class", ctypes.c_int32),
+        ("pack_a", ctypes.c_int32), ("pack_b", ctypes.c_int32),
+        ("copies", ctypes.c_int32), ("policy", ctypes.c_int32),
+        ("a_pack_offset", ctypes.c_int64), ("a_copy_bytes", ctypes.c_int64),
+        ("b_pack_offset", ctypes.c_int64), ("b_copy_bytes", ctypes.c_int64),
+        ("a_flag_offset", ctypes.c_int64), ("b_flag_offset", ctypes.c_int64),
+        ("a_claim_offset", ctypes.c_int64), ("b_claim_offset", ctypes.c_int64),
+        ("stats_offset", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_vp, _i64, _i32, _ch = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_char
+_SIGS = {
+    "fip_create": [ctypes.POINTER(_vp)],
+    "fip_destroy": [_vp],
+    "fip_set_stream": [_vp, _vp],
+    "fip_set_attr": [_vp, _i32, _i64],
+    "fip_get_attr": [_vp, _i32, ctypes.POINTER(_i64)],
+    "fip_set_workspace": [_vp, _vp, ctypes.c_size_t],
+    "fip_plan": [_vp, _i32, _i32, _i64, _i64, _i64, _ch, _ch, ctypes.POINTER(fip_plan_t)],
+    "fip_last_plan": [_vp, ctypes.POINTER(fip_plan_t)],
+    "fip_dgemm": [_vp, _i32, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _ch, _vp, _i64, _ch,
+                  ctypes.c_double, _vp, _i64],
+    "fip_sgemm": [_vp, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64, _ch,
+                  ctypes.c_float, _vp, _i64],
+    "fip_pack": [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _ch, _vp, _i64, _ch],
+    "fip_xcc_map": [_vp, _vp, _i64],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+
+
+def header_symbols():
+    """Names of the entry points include/fipgemm.h declares."""
+    with open(HEADER) as f:
+        return re.findall(r"^int\s+(fip_\w+)\s*\(", f.read(), flags=re.M)
+
+
+class FipError(RuntimeError):
+    def __init__(self, func, code):
+        super().__init__(f"{func} returned {code}")
+        self.func, self.code = func, code
+
+
+def _addr(x):
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return int(x)
+
+
+def _trans(t):
+    return t.encode() if isinstance(t, str) else bytes([t]) if isinstance(t, int) else t
+
+
+# ---- raw entry points (return the C code) ---------------------------------------------
+
+def fip_create():
+    h = _vp()
+    rc = _lib.fip_create(ctypes.byref(h))
+    return rc, h
+
+
+def fip_destroy(h):
+    return _lib.fip_destroy(h)
+
+
+def fip_set_stream(h, stream):
+    return _lib.fip_set_stream(h, _addr(stream))
+
+
+def fip_set_attr(h, attr, value):
+    return _lib.fip_set_attr(h, attr, value)
+
+
+def fip_get_attr(h, attr):
+    v = _i64()
+    rc = _lib.fip_get_attr(h, attr, ctypes.byref(v))
+    return rc, v.value
+
+
+def fip_set_workspace(h, ptr, nbytes):
+    return _lib.fip_set_workspace(h, _addr(ptr), nbytes)
+
+
+def fip_plan(h, dtype, layout, m, n, k, transA, transB):
+    p = fip_plan_t()
+    rc = _lib.fip_plan(h, dtype, layout, m, n, k, _trans(transA), _trans(transB), ctypes.byref(p))
+    return rc, p
+
+
+def fip_last_plan(h):
+    p = fip_plan_t()
+    rc = _lib.fip_last_plan(h, ctypes.byref(p))
+    return rc, p
+
+
+def fip_dgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+    return _lib.fip_dgemm(h, layout, m, n, k, alpha, _addr(A), lda, _trans(transA), _addr(B), ldb,
+                          _trans(transB), beta, _addr(C), ldc)
+
+
+def fip_sgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+    return _lib.fip_sgemm(h, layout, m, n, k, alpha, _addr(A), lda, _trans(transA), _addr(B), ldb,
+                          _trans(transB), beta, _addr(C), ldc)
+
+
+def fip_pack(h, dtype, layout, m, n, k, A, lda, transA, B, ldb, transB):
+    return _lib.fip_pack(h, dtype, layout, m, n, k, _addr(A), lda, _trans(transA), _addr(B), ldb,
+                         _trans(transB))
+
+
+def fip_xcc_map(h, out, nblocks):
+    return _lib.fip_xcc_map(h, _addr(out), nblocks)
+
+
+# ---- convenience handle (torch owns the workspace and the stream) ----------------------
+
+class Handle:
+    """A library handle bound to the current torch stream, with a growable workspace."""
+
+    def __init__(self, policy=FIP_PACK_AUTO, tile=-1):
+        rc, self.h = fip_create()
+        if rc:
+            raise FipError("fip_create", rc)
+        self.workspace = None
+        self.set_attr(FIP_ATTR_PACK_POLICY, policy)
+        self.set_attr(FIP_ATTR_TILE, tile)
+
+    def close(self):
+        if self.h:
+            fip_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, name, rc):
+        if rc != 0:
+            raise FipError(name, rc)
+
+    def set_attr(self, attr, value):
+        self._check("fip_set_attr", fip_set_attr(self.h, attr, value))
+
+    def get_attr(self, attr):
+        rc, v = fip_get_attr(self.h, attr)
+        self._check("fip_get_attr", rc)
+        return v
+
+    def plan(self, dtype, layout, m, n, k, transA="N", transB="N"):
+        rc, p = fip_plan(self.h, dtype, layout, m, n, k, transA, transB)
+        self._check("fip_plan", rc)
+        return p
+
+    def last_plan(self):
+        rc, p = fip_last_plan(self.h)
+        self._check("fip_last_plan", rc)
+        return p
+
+    def bind_stream(self):
+        import torch
+        self._check("fip_set_stream", fip_set_stream(self.h, torch.cuda.current_stream().cuda_stream))
+
+    def ensure_workspace(self, nbytes):
+        """Make sure a workspace of at least nbytes is attached (grows, never shrinks)."""
+        import torch
+        if nbytes <= 0:
+            return
+        if self.workspace is None or self.workspace.numel() < nbytes:
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            self._check("fip_set_workspace",
+                        fip_set_workspace(self.h, self.workspace.data_ptr(), self.workspace.numel()))
+
+    def attach_workspace(self, tensor):
+        self.workspace = tensor
+        self._check("fip_set_workspace", fip_set_workspace(self.h, tensor.data_ptr(), tensor.numel()))
+
+    def gemm(self, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+        """Dispatch on C's dtype (float64 -> fip_dgemm, float32 -> fip_sgemm)."""
+        import torch
+        dt = FIP_F64 if C.dtype == torch.float64 else FIP_F32
+        p = self.plan(dt, layout, m, n, k, transA, transB)
+        self.ensure_workspace(p.workspace_bytes)
+        self.bind_stream()
+        fn = fip_dgemm if dt == FIP_F64 else fip_sgemm
+        rc = fn(self.h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc)
+        self._check(fn.__name__, rc)
+
+    def pack(self, layout, m, n, k, A, lda, transA, B, ldb, transB):
+        import torch
+        dt = FIP_F64 if A.dtype == torch.float64 else FIP_F32
+        old = self.get_attr(FIP_ATTR_PACK_POLICY)
+        self.set_attr(FIP_ATTR_PACK_POLICY, FIP_PACK_CONSUME_ONLY)
+        p = self.plan(dt, layout, m, n, k, transA, transB)
+        self.set_attr(FIP_ATTR_PACK_POLICY, old)
+        self.ensure_workspace(p.workspace_bytes)
+        self.bind_stream()
+        self._check("fip_pack", fip_pack(self.h, dt, layout, m, n, k, A, lda, transA, B, ldb, transB))

@@ -1,0 +1,151 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol,
+validates arguments before any HIP call, and plans per the paper's pack table."""
+import ctypes
+
+import pytest
+
+from paper_2302_08417_amd import fipgemm as F
+
+
+@pytest.fixture()
+def h():
+    rc, hh = F.fip_create()
+    assert rc == 0
+    yield hh
+    assert F.fip_destroy(hh) == 0
+
+
+def test_every_declared_symbol_is_exported():
+    names = F.header_symbols()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(F.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_null_handle():
+    for rc in [F.fip_destroy(None), F.fip_set_stream(None, 0), F.fip_set_attr(None, 1, 0),
+               F.fip_set_workspace(None, 0, 0),
+               F.fip_dgemm(None, 0, 1, 1, 1, 1.0, 0, 1, "N", 0, 1, "N", 0.0, 0, 1),
+               F.fip_sgemm(None, 0, 1, 1, 1, 1.0, 0, 1, "N", 0, 1, "N", 0.0, 0, 1),
+               F.fip_pack(None, 0, 0, 1, 1, 1, 0, 1, "N", 0, 1, "N"),
+               F.fip_xcc_map(None, 0, 1)]:
+        assert rc == F.FIP_ERR_HANDLE
+    assert F.fip_plan(None, 0, 0, 1, 1, 1, "N", "N")[0] == F.FIP_ERR_HANDLE
+    assert F.fip_last_plan(None)[0] == F.FIP_ERR_HANDLE
+
+
+FAKE = 0x1000  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("fn", [F.fip_dgemm, F.fip_sgemm])
+def test_argument_positions(h, fn):
+    def call(layout=0, m=4, n=5, k=6, alpha=1.0, A=FAKE, lda=4, tA="N", B=FAKE, ldb=6, tB="N",
+             beta=0.5, C=FAKE, ldc=4):
+        return fn(h, layout, m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc)
+    assert call(layout=2) == 2
+    assert call(m=-1) == 3
+    assert call(n=-1) == 4
+    assert call(k=-1) == 5
+    assert call(A=None) == 7
+    assert call(lda=3) == 8
+    assert call(tA="X") == 9
+    assert call(B=None) == 10
+    assert call(ldb=5) == 11
+    assert call(tB="Q") == 12
+    assert call(C=None) == 14
+    assert call(ldc=3) == 15
+    # transposed / row-major leading-dimension rules
+    assert call(tA="T", lda=5) == 8 and call(tA="t", lda=5, k=5) != 8
+    assert call(layout=1, lda=5) == 8          # row-major N: lda >= k = 6
+    assert call(layout=1, lda=6, ldb=4) == 11  # row-major N: ldb >= n = 5
+    assert call(layout=1, lda=6, ldb=5, ldc=4) == 15
+    # null pointers that would not be read are fine: alpha = 0 skips A and B ...
+    assert call(alpha=0.0, A=None, B=None, beta=1.0, C=None) == 0  # full no-op
+    assert call(m=0, A=None, B=None, C=None) == 0
+    # lowercase and 'C' transposes are accepted
+    assert call(tA="n", tB="c", ldb=5, k=6) in (0, F.FIP_ERR_LAUNCH, F.FIP_ERR_WORKSPACE)
+
+
+def test_pack_argument_positions(h):
+    def call(dtype=0, layout=0, m=4, n=5, k=6, A=FAKE, lda=4, tA="N", B=FAKE, ldb=6, tB="N"):
+        return F.fip_pack(h, dtype, layout, m, n, k, A, lda, tA, B, ldb, tB)
+    assert call(dtype=7) == 2
+    assert call(layout=9) == 3
+    assert call(m=-1) == 4
+    assert call(n=-2) == 5
+    assert call(k=-3) == 6
+    assert call(A=None) == 7
+    assert call(lda=1) == 8
+    assert call(tA="x") == 9
+    assert call(B=None) == 10
+    assert call(ldb=2) == 11
+    assert call(tB="z") == 12
+
+
+def test_attributes(h):
+    assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, 9) == 3
+    assert F.fip_set_attr(h, F.FIP_ATTR_TILE, 3) == 3
+    assert F.fip_set_attr(h, 77, 0) == 2
+    assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_NONE) == 0
+    assert F.fip_get_attr(h, F.FIP_ATTR_PACK_POLICY) == (0, F.FIP_PACK_NONE)
+    assert F.fip_set_workspace(h, 0x1001, 10) == 2  # misaligned
+    assert F.fip_set_workspace(h, None, 10) == 2
+
+
+def plan(h, m, n, k, layout=0, dtype=F.FIP_F64, policy=F.FIP_PACK_AUTO, tile=-1, t="NN"):
+    assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, policy) == 0
+    assert F.fip_set_attr(h, F.FIP_ATTR_TILE, tile) == 0
+    rc, p = F.fip_plan(h, dtype, layout, m, n, k, t[0], t[1])
+    assert rc == 0
+    return p
+
+
+def test_pack_table_of_the_paper(h):
+    """Sec. 3.3: n <= n_R -> do not pack A; m <= m_R -> do not pack B (tile = MT x NT)."""
+    for tile, T in [(0, 128), (1, 64), (2, 32)]:
+        for m, n, pa, pb in [(T, T, 0, 0), (T, T + 1, 1, 0), (T + 1, T, 0, 1), (5 * T, 3 * T, 1, 1)]:
+            for layout in (0, 1):
+                p = plan(h, m, n, 64, layout=layout, tile=tile)
+                assert (p.pack_a, p.pack_b) == (pa, pb), (tile, m, n, layout)
+                assert p.MT == T and p.NT == T
+                if not pa and not pb:
+                    assert p.workspace_bytes == 0 and p.copies == 0
+
+
+def test_plan_layout_and_sizes(h):
+    p = plan(h, 300, 200, 77, policy=F.FIP_PACK_ALL, tile=2)
+    assert (p.tiles_m, p.tiles_n, p.ksteps, p.KT) == (10, 7, 5, 16)
+    assert p.copies == 8
+    assert p.a_copy_bytes == 10 * 5 * 16 * 32 * 8
+    assert p.b_copy_bytes == 7 * 5 * 16 * 32 * 8
+    offs = sorted([p.a_pack_offset, p.b_pack_offset, p.a_flag_offset, p.b_flag_offset,
+                   p.a_claim_offset, p.b_claim_offset])
+    assert all(o % 256 == 0 for o in offs)
+    assert p.a_pack_offset + 8 * p.a_copy_bytes <= p.workspace_bytes
+    assert p.b_pack_offset + 8 * p.b_copy_bytes <= p.workspace_bytes
+    # row-major: the kernel swaps operand sides; the plan still speaks of op(A), op(B)
+    q = plan(h, 300, 200, 77, layout=1, policy=F.FIP_PACK_ALL, tile=2)
+    assert (q.tiles_m, q.tiles_n) == (10, 7)
+    assert q.a_copy_bytes == p.a_copy_bytes and q.b_copy_bytes == p.b_copy_bytes
+    # FP32 uses a 32-deep k-step
+    r = plan(h, 300, 200, 77, dtype=F.FIP_F32, policy=F.FIP_PACK_ALL, tile=2)
+    assert r.KT == 32 and r.ksteps == 3 and r.a_copy_bytes == 10 * 3 * 32 * 32 * 4
+    # pack-then-compute keeps a single copy
+    s = plan(h, 300, 200, 77, policy=F.FIP_PACK_CONSUME_ONLY, tile=2)
+    assert s.copies == 1 and s.pack_a and s.pack_b
+    assert plan(h, 300, 200, 77, policy=F.FIP_PACK_NONE).workspace_bytes == 0
+
+
+def test_tile_class_choice(h):
+    assert plan(h, 8192, 8192, 8192).tile_class == 0
+    assert plan(h, 2048, 2048, 2048).tile_class == 0
+    assert plan(h, 1024, 1024, 1024).tile_class == 1
+    assert plan(h, 256, 256, 256).tile_class == 2
+    assert plan(h, 16, 16, 16).tile_class == 2
+
+
+def test_missing_workspace_is_an_error_not_a_fallback(h):
+    assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_ALL) == 0
+    rc = F.fip_dgemm(h, 0, 300, 300, 300, 1.0, FAKE, 300, "N", FAKE, 300, "N", 0.0, FAKE, 300)
+    assert rc == F.FIP_ERR_WORKSPACE
