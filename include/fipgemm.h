@@ -71,8 +71,9 @@ enum {
     /* 1: count per-chunk events (packed, read packed, read unpacked) into
        the workspace's statistics block (a diagnostic; costs atomics). */
     FIP_ATTR_STATS = 4,
-    /* Read only: the epoch stamp of the most recent fused call (claims and
-       publish flags of that call hold this value). */
+    /* Read only: the 64-bit epoch stamp of the most recent fused call
+       (claims and publish flags of that call hold this value; stamps are
+       unique within the process). */
     FIP_ATTR_EPOCH = 5,
 };
 
@@ -108,8 +109,8 @@ typedef struct {
     int32_t policy;            /* FIP_PACK_* in effect */
     int64_t a_pack_offset, a_copy_bytes;
     int64_t b_pack_offset, b_copy_bytes;
-    int64_t a_flag_offset, b_flag_offset;   /* uint32 [copies][tiles][ksteps] */
-    int64_t a_claim_offset, b_claim_offset; /* uint32 [copies][tiles] */
+    int64_t a_flag_offset, b_flag_offset;   /* uint64 [copies][tiles][ksteps] */
+    int64_t a_claim_offset, b_claim_offset; /* uint64 [copies][tiles] */
     int64_t stats_offset;      /* 3 x uint64: packed, read packed, read unpacked */
     int64_t workspace_bytes;   /* bytes this call needs */
 } fip_plan_t;
@@ -124,10 +125,12 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value);
 int fip_get_attr(fip_handle_t handle, int attr, int64_t* value);
 
 /*
- * Hand the handle a caller-owned device buffer for pack panels, publish flags
- * and statistics.  It must stay valid, and must not be used by anyone else,
- * while calls using it may be in flight.  Setting a (new) workspace clears its
- * flag area on the handle's stream.  bytes may be 0 (dptr NULL) to detach.
+ * Hand the handle a caller-owned device buffer (256-byte aligned) for pack
+ * panels, publish flags and statistics.  It must stay valid, and must not be
+ * used by anyone else, while calls using it may be in flight.  Its initial
+ * contents do not matter: flags and claims only count when they carry the
+ * current call's unique stamp.  No HIP call is made.  bytes may be 0 (dptr
+ * NULL) to detach.
  */
 int fip_set_workspace(fip_handle_t handle, void* dptr, size_t bytes);
 

@@ -41,10 +41,10 @@ struct LaunchDesc {
     // workspace pieces (device pointers; null when unused)
     void* apack; int64_t apack_copy_elems;
     void* bpack; int64_t bpack_copy_elems;
-    uint32_t* aflag; uint32_t* bflag;   // [copies][tiles][ksteps]
-    uint32_t* aclaim; uint32_t* bclaim; // [copies][tiles]
+    uint64_t* aflag; uint64_t* bflag;   // [copies][tiles][ksteps]
+    uint64_t* aclaim; uint64_t* bclaim; // [copies][tiles]
     unsigned long long* stats_ptr;      // 3 counters
-    uint32_t epoch;
+    uint64_t epoch;                     // unique per fused call in this process
     hipStream_t stream;
 };
 

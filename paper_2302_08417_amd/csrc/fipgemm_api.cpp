@@ -3,7 +3,10 @@
 // layout) and kernel launches.  See include/fipgemm.h for the contract.
 #include "fipgemm.h"
 
+#include <atomic>
+#include <chrono>
 #include <new>
+#include <random>
 #include <string.h>
 
 #include "fip_internal.h"
@@ -11,7 +14,23 @@
 namespace {
 
 constexpr uint32_t kMagic = 0xF1F6E77u;
-constexpr uint32_t kEpochLimit = 0xFFFFFF00u;  // restart (and clear) before wrapping
+
+// Epoch stamps of fused calls.  Claims and publish flags in a workspace are
+// compared for equality with the current call's stamp, so a stamp must never
+// repeat for the same memory: not across calls, handles, workspaces that
+// reuse freed memory, nor lines a cache still holds from earlier calls.  A
+// process-wide 64-bit counter started at a random point gives that without
+// ever clearing the workspace.
+uint64_t next_epoch()
+{
+    static std::atomic<uint64_t> counter([] {
+        std::random_device rd;
+        uint64_t r = ((uint64_t)rd() << 32) ^ (uint64_t)rd() ^
+                     (uint64_t)std::chrono::high_resolution_clock::now().time_since_epoch().count();
+        return (r & 0x0000FFFFFFFFFFFFull) | 0x0001000000000000ull;  // nonzero, far from ~0
+    }());
+    return counter.fetch_add(1, std::memory_order_relaxed);
+}
 
 }  // namespace
 
@@ -24,8 +43,7 @@ struct fip_handle_s {
     int stats;
     void* ws;
     size_t ws_bytes;
-    uint32_t epoch;
-    int ws_needs_clear;
+    uint64_t epoch;   // stamp of the most recent fused call
     fip_plan_t last;
     int has_last;
 };
@@ -123,10 +141,10 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
 
     int64_t off = 0;
     pl->off_stats = off; off = align256(off + 3 * 8);
-    pl->off_aflag = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * pl->nK * 4 : 0));
-    pl->off_bflag = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * pl->nK * 4 : 0));
-    pl->off_aclaim = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * 4 : 0));
-    pl->off_bclaim = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * 4 : 0));
+    pl->off_aflag = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * pl->nK * 8 : 0));
+    pl->off_bflag = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * pl->nK * 8 : 0));
+    pl->off_aclaim = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * 8 : 0));
+    pl->off_bclaim = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * 8 : 0));
     pl->apack_copy_elems = pl->kpack_a ? pl->tilesKM * pl->nK * KT * MT : 0;
     pl->bpack_copy_elems = pl->kpack_b ? pl->tilesKN * pl->nK * KT * NT : 0;
     pl->off_apack = off; off = align256(off + copies * pl->apack_copy_elems * pl->elem);
@@ -223,10 +241,10 @@ void fill_workspace(const fip_handle_s* h, const Plan& pl, fip::LaunchDesc* d)
 {
     char* ws = static_cast<char*>(h->ws);
     d->stats_ptr = reinterpret_cast<unsigned long long*>(ws + pl.off_stats);
-    d->aflag = reinterpret_cast<uint32_t*>(ws + pl.off_aflag);
-    d->bflag = reinterpret_cast<uint32_t*>(ws + pl.off_bflag);
-    d->aclaim = reinterpret_cast<uint32_t*>(ws + pl.off_aclaim);
-    d->bclaim = reinterpret_cast<uint32_t*>(ws + pl.off_bclaim);
+    d->aflag = reinterpret_cast<uint64_t*>(ws + pl.off_aflag);
+    d->bflag = reinterpret_cast<uint64_t*>(ws + pl.off_bflag);
+    d->aclaim = reinterpret_cast<uint64_t*>(ws + pl.off_aclaim);
+    d->bclaim = reinterpret_cast<uint64_t*>(ws + pl.off_bclaim);
     d->apack = ws + pl.off_apack;
     d->bpack = ws + pl.off_bpack;
     d->apack_copy_elems = pl.apack_copy_elems;
@@ -237,11 +255,6 @@ int prepare_workspace(fip_handle_s* h, const Plan& pl)
 {
     if (pl.pub.workspace_bytes == 0) return 0;
     if (h->ws == nullptr || (int64_t)h->ws_bytes < pl.pub.workspace_bytes) return FIP_ERR_WORKSPACE;
-    if (h->ws_needs_clear || h->epoch >= kEpochLimit) {
-        if (hipMemsetAsync(h->ws, 0, h->ws_bytes, h->stream) != hipSuccess) return FIP_ERR_LAUNCH;
-        h->ws_needs_clear = 0;
-        h->epoch = 0;
-    }
     return 0;
 }
 
@@ -282,7 +295,7 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.alpha = (double)alpha; d.beta = (double)beta;
         if (pl.pub.workspace_bytes > 0) {
             fill_workspace(h, pl, &d);
-            if (pl.mode == fip::kModeFused) d.epoch = ++h->epoch;
+            if (pl.mode == fip::kModeFused) d.epoch = h->epoch = next_epoch();
         } else {
             d.stats = 0;
         }
@@ -363,7 +376,7 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_TILE: *value = handle->tile_override; return 0;
     case FIP_ATTR_NO_PUBLISH: *value = handle->no_publish; return 0;
     case FIP_ATTR_STATS: *value = handle->stats; return 0;
-    case FIP_ATTR_EPOCH: *value = handle->epoch; return 0;
+    case FIP_ATTR_EPOCH: *value = (int64_t)handle->epoch; return 0;
     default: return 2;
     }
 }
@@ -375,8 +388,7 @@ int fip_set_workspace(fip_handle_t handle, void* dptr, size_t bytes)
     if (dptr != nullptr && ((uintptr_t)dptr & 255) != 0) return 2;  // 256-byte aligned
     handle->ws = dptr;
     handle->ws_bytes = dptr ? bytes : 0;
-    handle->ws_needs_clear = dptr != nullptr;
-    handle->epoch = 0;
+
     return 0;
 }
 

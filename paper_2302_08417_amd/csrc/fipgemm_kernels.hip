@@ -37,9 +37,16 @@ template <typename T> struct Types;
 template <> struct Types<double> { typedef d2 vec; typedef d4 acc; static constexpr int VEC = 2; };
 template <> struct Types<float> { typedef f4 vec; typedef f4 acc; static constexpr int VEC = 4; };
 
+// One 16x16x4 MFMA on fragments a (lane l: A[i = l%16][k = l/16]) and b (lane l:
+// B[k = l/16][j = l%16]) of a 16x16 C block.  Output layouts differ by type:
+//   f32 (v_mfma_f32_16x16x4_f32): item r of lane l is C[4*(l/16) + r][l%16];
+//   f64 (v_mfma_f64_16x16x4_f64): item r of lane l would be C[4*r + l/16][l%16].
+// For f64 the operands are swapped so the instruction produces the transposed
+// block: item r of lane l is then C[l%16][4*r + l/16], i.e. each lane keeps one
+// row and 16 consecutive lanes cover 16 consecutive rows of a column-major C.
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
 {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c, 0, 0, 0);
 }
 __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
 {
@@ -69,9 +76,9 @@ struct Params {
     T alpha, beta;
     T* apack; T* bpack;
     int64_t apack_copy, bpack_copy;
-    uint32_t* aflag; uint32_t* bflag; uint32_t* aclaim; uint32_t* bclaim;
+    uint64_t* aflag; uint64_t* bflag; uint64_t* aclaim; uint64_t* bclaim;
     unsigned long long* stats;
-    uint32_t epoch;
+    uint64_t epoch;
     int tilesM, tilesN, nK, group_m;
     int mode, pack_a, pack_b, no_publish, do_stats;
     int a_vec, b_vec, c_vec;
@@ -235,6 +242,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     __shared__ __attribute__((aligned(16))) T sA[2][KT * ChA::LDP];
     __shared__ __attribute__((aligned(16))) T sB[2][KT * ChB::LDP];
     __shared__ int s_role;
+    __shared__ int s_src[2];  // per chunk parity: bit 0 A packed, bit 1 B packed
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -242,7 +250,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     tile_coords(blockIdx.x, P.tilesM, P.tilesN, P.group_m, tm, tn);
     const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * NT;
     const int nK = P.nK;
-    const uint32_t epoch = P.epoch;
+    const uint64_t epoch = P.epoch;
 
     const bool consume = P.mode == kModeConsumePacked;
     bool fused = P.mode == kModeFused;
@@ -258,8 +266,26 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     T* bpanel = nullptr;
     if (useA || consume) apanel = P.apack + (int64_t)copy * P.apack_copy + (int64_t)tm * nK * KT * MT;
     if (useB || consume) bpanel = P.bpack + (int64_t)copy * P.bpack_copy + (int64_t)tn * nK * KT * NT;
-    uint32_t* aflags = useA ? P.aflag + ((int64_t)copy * P.tilesM + tm) * nK : nullptr;
-    uint32_t* bflags = useB ? P.bflag + ((int64_t)copy * P.tilesN + tn) * nK : nullptr;
+    uint64_t* aflags = useA ? P.aflag + ((int64_t)copy * P.tilesM + tm) * nK : nullptr;
+    uint64_t* bflags = useB ? P.bflag + ((int64_t)copy * P.tilesN + tn) * nK : nullptr;
+
+    // Thread 0 decides, for the whole workgroup, where each chunk comes from
+    // (packed copy or unpacked operand) and broadcasts it through LDS behind
+    // the next barrier.  The decision must be workgroup-uniform: for an operand
+    // contiguous along k the two sources are staged by different
+    // thread-to-element assignments, so waves that chose differently would
+    // each fill a different part of the LDS tile.
+    auto published = [&](const uint64_t* flags, int q) -> bool {
+        return __hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+    };
+    bool prodA = false, prodB = false;
+    auto decide = [&](int q) -> int {  // thread 0 only
+        int src = 0;
+        if (consume) return 3;
+        if (useA && !prodA && published(aflags, q)) src |= 1;
+        if (useB && !prodB && published(bflags, q)) src |= 2;
+        return src;
+    };
 
     if (tid == 0) {
         int role = 0;
@@ -270,37 +296,25 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
                                           __HIP_MEMORY_SCOPE_AGENT) != epoch)
             role |= 2;
         s_role = role;
+        prodA = role & 1;
+        prodB = role & 2;
+        s_src[0] = decide(0);
     }
     __syncthreads();
-    const bool prodA = s_role & 1, prodB = s_role & 2;
+    prodA = s_role & 1;
+    prodB = s_role & 2;
     const bool producer = prodA || prodB;
-
-    // Source of chunk q: packed copy (true) or the unpacked operand (false).
-    auto published = [&](const uint32_t* flags, int q) -> bool {
-        const uint32_t f = __hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        return __builtin_amdgcn_readfirstlane(f) == epoch;
-    };
-    auto a_packed = [&](int q) -> bool {
-        if (consume) return true;
-        if (!useA || prodA) return false;
-        return published(aflags, q);
-    };
-    auto b_packed = [&](int q) -> bool {
-        if (consume) return true;
-        if (!useB || prodB) return false;
-        return published(bflags, q);
-    };
 
     unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0;
     ChA ra;
     ChB rb;
-    auto load_chunks = [&](int q, bool apk, bool bpk) {
+    auto load_chunks = [&](int q, int src) {
+        const bool apk = src & 1, bpk = src & 2;
         if (apk) ra.load_packed(apanel + (int64_t)q * KT * MT, tid);
         else ra.load_unpacked(P.A, P.a_smn, P.a_sk, P.M, P.K, x0a, (int64_t)q * KT, P.a_vec, tid);
         if (bpk) rb.load_packed(bpanel + (int64_t)q * KT * NT, tid);
         else rb.load_unpacked(P.B, P.b_smn, P.b_sk, P.N, P.K, x0b, (int64_t)q * KT, P.b_vec, tid);
-        if (P.do_stats) {
+        if (P.do_stats && tid == 0) {
             n_prod += (int)prodA + (int)prodB;
             n_pk += (int)apk + (int)bpk;
             n_unpk += (int)(useA && !prodA && !apk) + (int)(useB && !prodB && !bpk);
@@ -313,12 +327,13 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
 
-    // Prologue: chunk 0.
+    // Prologue: chunk 0; thread 0 decides chunk 1.
     {
-        const bool apk = a_packed(0), bpk = b_packed(0);
-        load_chunks(0, apk, bpk);
-        ra.store_lds(sA[0], apk, tid);
-        rb.store_lds(sB[0], bpk, tid);
+        const int src = s_src[0];
+        load_chunks(0, src);
+        if (tid == 0 && nK > 1) s_src[1] = decide(1);
+        ra.store_lds(sA[0], src & 1, tid);
+        rb.store_lds(sB[0], src & 2, tid);
         if (prodA) ra.store_pack(apanel, tid);
         if (prodB) rb.store_pack(bpanel, tid);
     }
@@ -327,12 +342,14 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     for (int q = 0; q < nK; ++q) {
         const int cur = q & 1;
         const bool more = q + 1 < nK;
-        bool apk = false, bpk = false;
+        int src = 0;
         if (more) {
-            apk = a_packed(q + 1);
-            bpk = b_packed(q + 1);
-            load_chunks(q + 1, apk, bpk);
+            src = s_src[(q + 1) & 1];  // decided before the previous barrier
+            load_chunks(q + 1, src);
         }
+        // Thread 0 reads the flags of chunk q+2 now; the loads complete under the MFMAs.
+        int next_src = 0;
+        if (tid == 0 && q + 2 < nK) next_src = decide(q + 2);
         // MFMAs on chunk q.
         const T* la = sA[cur] + wm * WTM + (lane & 15);
         const T* lb = sB[cur] + wn * WTN + (lane & 15);
@@ -353,11 +370,14 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         // before chunk q is published below.
         if (producer) wait_all_memory();
         if (more) {
-            ra.store_lds(sA[cur ^ 1], apk, tid);
-            rb.store_lds(sB[cur ^ 1], bpk, tid);
+            ra.store_lds(sA[cur ^ 1], src & 1, tid);
+            rb.store_lds(sB[cur ^ 1], src & 2, tid);
             if (prodA) ra.store_pack(apanel + (int64_t)(q + 1) * KT * MT, tid);
             if (prodB) rb.store_pack(bpanel + (int64_t)(q + 1) * KT * NT, tid);
         }
+        // s_src[q & 1] was last read at the top of iteration q-1, before the
+        // previous barrier, so it is free for chunk q+2.
+        if (tid == 0 && q + 2 < nK) s_src[q & 1] = next_src;
         __syncthreads();
         if (tid == 0 && producer && !P.no_publish) {
             if (prodA) __hip_atomic_store(aflags + q, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -371,44 +391,60 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         atomicAdd(P.stats + 2, n_unpk);
     }
 
-    // Epilogue: C = alpha*acc + beta*C (C not read when beta == 0).  MFMA
-    // 16x16 output layout: lane l holds column l%16, rows 4*(l/16) .. +3.
+    // Epilogue: C = alpha*acc + beta*C (C not read when beta == 0).
     const T alpha = P.alpha, beta = P.beta;
 #pragma unroll
     for (int a = 0; a < FM; ++a) {
-        const int64_t i0 = x0a + wm * WTM + a * 16 + 4 * (lane >> 4);
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
-            const int64_t j = x0b + wn * WTN + b * 16 + (lane & 15);
-            if (j >= P.N || i0 >= P.M) continue;
-            T* cp = P.C + i0 + j * P.ldc;
-            const bool full = i0 + 4 <= P.M;
-            const bool vec = full && P.c_vec;
-            T out[4];
+            const int64_t r0 = x0a + wm * WTM + a * 16, c0 = x0b + wn * WTN + b * 16;
+            if constexpr (sizeof(T) == 8) {
+                // lane holds row r0 + l%16, columns c0 + 4*r + l/16
+                const int64_t i = r0 + (lane & 15);
+                if (i >= P.M) continue;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[r] = alpha * acc[a][b][r];
-            if (beta != T(0)) {
-                T c0[4];
-                if (full) load4<T, NTHR>(cp, vec, c0);
-                else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) c0[r] = (i0 + r < P.M) ? cp[r] : T(0);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) out[r] = out[r] + beta * c0[r];
-            }
-            if (vec) {
-#pragma unroll
-                for (int h = 0; h < 4 / VEC; ++h) {
-                    V v;
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) v[e] = out[h * VEC + e];
-                    *reinterpret_cast<V*>(cp + h * VEC) = v;
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t j = c0 + 4 * r + (lane >> 4);
+                    if (j >= P.N) continue;
+                    T* cp = P.C + i + j * P.ldc;
+                    T v = alpha * acc[a][b][r];
+                    if (beta != T(0)) v = v + beta * *cp;
+                    *cp = v;
                 }
             } else {
+                // lane holds column c0 + l%16, rows r0 + 4*(l/16) .. +3
+                const int64_t i0 = r0 + 4 * (lane >> 4);
+                const int64_t j = c0 + (lane & 15);
+                if (j >= P.N || i0 >= P.M) continue;
+                T* cp = P.C + i0 + j * P.ldc;
+                const bool full = i0 + 4 <= P.M;
+                const bool vec = full && P.c_vec;
+                T out[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (i0 + r < P.M) cp[r] = out[r];
+                for (int r = 0; r < 4; ++r) out[r] = alpha * acc[a][b][r];
+                if (beta != T(0)) {
+                    T cv[4];
+                    if (full) load4<T, NTHR>(cp, vec, cv);
+                    else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) cv[r] = (i0 + r < P.M) ? cp[r] : T(0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) out[r] = out[r] + beta * cv[r];
+                }
+                if (vec) {
+#pragma unroll
+                    for (int h = 0; h < 4 / VEC; ++h) {
+                        V v;
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) v[e] = out[h * VEC + e];
+                        *reinterpret_cast<V*>(cp + h * VEC) = v;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i0 + r < P.M) cp[r] = out[r];
+                }
             }
         }
     }

@@ -191,8 +191,41 @@ def test_modes_bitwise_identical(F, dtype, layout, tA, tB):
         assert np.array_equal(out.view(np.uint8), ref.view(np.uint8)), (pol, nopub)
 
 
-def _ws_u32(ws, off, count):
-    return ws[off: off + 4 * count].cpu().numpy().view(np.uint32)
+@pytest.mark.parametrize("dtype,shape,tile", [(F64, (700, 600, 333), -1), (F32, (700, 600, 333), -1),
+                                              (F64, (2048, 2048, 256), 1)])
+def test_fused_repeated_calls_bitwise(F, dtype, shape, tile):
+    """Regression: the packed/unpacked choice per chunk must be workgroup-uniform.  Repeated
+    fused calls (with packed reads actually happening) must equal the unpacked path bit for
+    bit every time; the workspace is poisoned before each call."""
+    import torch
+    m, n, k = shape
+    c = synth.make_case(COL, m, n, k, "N", "N", dtype=dtype, seed=7)
+    ref, _ = _run_policy(F, c, F.FIP_PACK_NONE)
+    check_full(c, ref)
+    A, B = to_dev(c.A), to_dev(c.B)
+    h = handle(F, policy=F.FIP_PACK_ALL, tile=tile)
+    h.set_attr(F.FIP_ATTR_STATS, 1)
+    dt = F.FIP_F64 if dtype == F64 else F.FIP_F32
+    p = h.plan(dt, COL, m, n, k, "N", "N")
+    h.ensure_workspace(p.workspace_bytes)
+    total_packed_reads = 0
+    for trial in range(4):
+        say("repeat", dtype.__name__, shape, trial)
+        h.workspace.fill_(0xFF)
+        h.workspace[:64].zero_()
+        C = to_dev(c.C)
+        h.gemm(COL, m, n, k, c.alpha, A, c.lda, "N", B, c.ldb, "N", c.beta, C, c.ldc)
+        torch.cuda.synchronize()
+        out = C.cpu().numpy()
+        st = h.workspace[p.stats_offset: p.stats_offset + 24].cpu().numpy().view(np.uint64)
+        total_packed_reads += int(st[1])
+        assert np.array_equal(out.view(np.uint8), ref.view(np.uint8)), (trial, st.tolist())
+    say("packed-chunk reads over the trials:", total_packed_reads)
+    assert total_packed_reads > 0
+
+
+def _ws_u64(ws, off, count):
+    return ws[off: off + 8 * count].cpu().numpy().view(np.uint64)
 
 
 @pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
@@ -208,7 +241,7 @@ def test_packed_buffers_bit_exact(F, dtype, layout, tA, tB, pad):
     check_full(c, out)
     p = h.last_plan()
     ws = h.workspace
-    epoch = h.get_attr(F.FIP_ATTR_EPOCH)
+    epoch = np.uint64(h.get_attr(F.FIP_ATTR_EPOCH))
     assert p.pack_a and p.pack_b and p.copies == F.COPIES
     nk = p.ksteps
     for which, ntiles, mnt, off_pack, copy_bytes, off_claim, off_flag, X, ld, t, mn in [
@@ -218,8 +251,8 @@ def test_packed_buffers_bit_exact(F, dtype, layout, tA, tB, pad):
              p.b_flag_offset, c.B, c.ldb, tB, n)]:
         ref = oracle.pack(X, which == "B", layout, t, mn, k, ld, mnt, p.KT)
         ref_u8 = ref.view(np.uint8)
-        claims = _ws_u32(ws, off_claim, F.COPIES * ntiles).reshape(F.COPIES, ntiles)
-        flags = _ws_u32(ws, off_flag, F.COPIES * ntiles * nk).reshape(F.COPIES, ntiles, nk)
+        claims = _ws_u64(ws, off_claim, F.COPIES * ntiles).reshape(F.COPIES, ntiles)
+        flags = _ws_u64(ws, off_flag, F.COPIES * ntiles * nk).reshape(F.COPIES, ntiles, nk)
         assert np.all((claims == epoch).any(axis=0)), f"{which}: a panel was never packed"
         panel_bytes = nk * p.KT * mnt * c.A.itemsize
         for cp in range(F.COPIES):
