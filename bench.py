@@ -57,14 +57,15 @@ def load_traffic(name):
 class Gemm:
     """One prepared GEMM (device operands + a handle per policy) timed with HIP events."""
 
-    def __init__(self, F, torch, n, dtype, seed, layout=0, tA="N", tB="N", m=None, k=None):
+    def __init__(self, F, torch, n, dtype, seed, layout=0, tA="N", tB="N", m=None, k=None,
+                 ld_pad=0):
         import numpy as np
         from paper_2302_08417_amd import synth
         self.F, self.torch = F, torch
         self.m, self.n, self.k = (m or n), n, (k or n)
         np_dt = np.float64 if dtype == "f64" else np.float32
-        c = synth.make_case(layout, self.m, self.n, self.k, tA, tB, alpha=1.5, beta=0.5,
-                            dtype=np_dt, seed=seed)
+        c = synth.make_case(layout, self.m, self.n, self.k, tA, tB, ld_pad=ld_pad, alpha=1.5,
+                            beta=0.5, dtype=np_dt, seed=seed)
         self.case = c
         self.A = torch.from_numpy(c.A).to("cuda")
         self.B = torch.from_numpy(c.B).to("cuda")
@@ -155,6 +156,9 @@ def main():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-sizes", default=None,
+                    help="comma-separated sizes for the sweep (default: 16..8192 powers of two)")
+    ap.add_argument("--sweep-dtypes", default="f64,f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -217,8 +221,9 @@ def main():
 
     if not args.no_sweep:
         sweep = []
-        for sdt in ("f64", "f32"):
-            for s in SWEEP_SIZES:
+        sizes = [int(x) for x in args.sweep_sizes.split(",")] if args.sweep_sizes else SWEEP_SIZES
+        for sdt in args.sweep_dtypes.split(","):
+            for s in sizes:
                 gs = Gemm(F, torch, s, sdt, seed=synth.BASE_SEED + 17 * s)
                 reps = max(5, min(200, int(2e11 / gs.flops()) if sdt == "f64" else int(4e11 / gs.flops())))
                 row = {"dtype": sdt, "m": s, "n": s, "k": s}

@@ -68,9 +68,22 @@ enum {
     /* 1: producers pack but never publish, so every consumer takes the
        unpacked fallback (a test knob; the result must not change). */
     FIP_ATTR_NO_PUBLISH = 3,
-    /* 1: count per-chunk events (packed, read packed, read unpacked) into
-       the workspace's statistics block (a diagnostic; costs atomics). */
+    /* 1: count per-chunk events (packed, read packed, read unpacked, polls)
+       into the workspace's statistics block (a diagnostic; costs atomics). */
     FIP_ATTR_STATS = 4,
+    /* Polls a follower (a workgroup that packs nothing) may spend waiting for
+       a chunk its producer has not yet published before it reads the
+       unpacked operand instead.  0 = never wait.  Default 2000. */
+    FIP_ATTR_SPIN_LIMIT = 6,
+    /* Tile order inside an XCD's run: 0 = GROUP_M tiles of a column
+       consecutive, 1 = consecutive tiles in distinct columns.  Default 0. */
+    FIP_ATTR_ORDER = 7,
+    /* 1: tile row t starts its k-loop at k-step (t % 8) * ceil(k/KT) / 8 and
+       wraps around, so tile rows read different k-ranges at any moment.  The
+       order depends only on the tile, and is used by every pack policy, so
+       results stay identical across policies; it does change the summation
+       order relative to 0.  Default 0. */
+    FIP_ATTR_STAGGER = 8,
     /* Read only: the 64-bit epoch stamp of the most recent fused call
        (claims and publish flags of that call hold this value; stamps are
        unique within the process). */
@@ -89,10 +102,14 @@ enum {
  * The plan of one call, in the caller's terms (op(A) is m x k, op(B) k x n).
  * Packed layout (the contract): the pack of op(A) is ceil(m/MT)*ceil(k/KT)
  * contiguous blocks of KT*MT elements; block (t, q) (tile row t, k-step q) is
- * block number t*ceil(k/KT) + q, and inside it element (i, p) of op(A) sits
- * at (p % KT)*MT + (i % MT).  The pack of op(B) is the same with (MT, i)
- * replaced by (NT, j).  Entries outside the matrix are +0.0.  Element bits are
- * copied unchanged; alpha is not folded in.
+ * block number t*ceil(k/KT) + q.  Inside a block the tile keeps the
+ * orientation op(A) has in storage: if A's storage runs along m (column-major
+ * 'N', row-major 'T'), element (i, p) sits at (p % KT)*MT + (i % MT), each
+ * k-slice contiguous; otherwise (column-major 'T', row-major 'N') at
+ * (i % MT)*KT + (p % KT), each row's k-run contiguous.  The pack of op(B) is
+ * the same with (MT, i) replaced by (NT, j): its storage runs along n for
+ * column-major 'T' and row-major 'N'.  Entries outside the matrix are +0.0.
+ * Element bits are copied unchanged; alpha is not folded in.
  * The fused path keeps one copy per XCD (copies = 8), indexed by the
  * hardware XCC id of the workgroup that packs it; copy c of op(A)'s pack
  * starts at workspace + a_pack_offset + c * a_copy_bytes.  The standalone
@@ -107,11 +124,13 @@ typedef struct {
     int32_t pack_a, pack_b;    /* operand packed under this plan */
     int32_t copies;            /* pack copies laid out in the workspace */
     int32_t policy;            /* FIP_PACK_* in effect */
+    int32_t a_kmajor, b_kmajor;/* packed block orientation: 1 = k-runs contiguous */
     int64_t a_pack_offset, a_copy_bytes;
     int64_t b_pack_offset, b_copy_bytes;
     int64_t a_flag_offset, b_flag_offset;   /* uint64 [copies][tiles][ksteps] */
     int64_t a_claim_offset, b_claim_offset; /* uint64 [copies][tiles] */
-    int64_t stats_offset;      /* 3 x uint64: packed, read packed, read unpacked */
+    int64_t stats_offset;      /* 4 x uint64: chunks packed, read packed, read
+                                  unpacked by followers, follower polls */
     int64_t workspace_bytes;   /* bytes this call needs */
 } fip_plan_t;
 

@@ -43,6 +43,8 @@ def lib():
         L.oracle_pack.restype = None
         L.oracle_materialize_op.argtypes = [ctypes.c_int, ch, i64, i64, vp, i64, vp]
         L.oracle_materialize_op.restype = None
+        L.oracle_mn_contiguous.argtypes = [ctypes.c_int, ctypes.c_int, ch]
+        L.oracle_mn_contiguous.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -115,6 +117,11 @@ def materialize_op(layout, trans, rows, cols, X, ld):
     out = np.empty(rows * cols if rows * cols else 1, dtype=np.float64)
     lib().oracle_materialize_op(layout, _t(trans), rows, cols, _ptr(X64), ld, _ptr(out))
     return out[: rows * cols].reshape(cols, rows).T.copy()
+
+
+def mn_contiguous(is_b, layout, trans):
+    """True when op(X)'s storage runs along its M (for A) or N (for B) index."""
+    return bool(lib().oracle_mn_contiguous(int(bool(is_b)), layout, _t(trans)))
 
 
 def pack(X, is_b, layout, trans, mn, k, ld, MNT, KT):

@@ -239,15 +239,34 @@ int oracle_freivalds(int layout, int64_t m, int64_t n, int64_t k, double alpha,
 }
 
 /*
+ * Which index of op(X) is contiguous in X's storage.  op(X)[r, c] is stored
+ * element (r, c) for 'N' and (c, r) for 'T'/'C'; a column-major matrix is
+ * contiguous along its row index, a row-major one along its column index.
+ * For op(A) (m x k) the MN index is the row index r; for op(B) (k x n) it is
+ * the column index c.  Returns 1 when storage runs along the MN index.
+ */
+int oracle_mn_contiguous(int is_b, int layout, char trans)
+{
+    /* index of op(X) (0 = row r, 1 = column c) that runs along storage:
+       column-major N -> r, column-major T -> c, row-major N -> c, row-major T -> r */
+    const int contiguous_index = (layout == OR_ROW) ^ is_trans(trans);
+    const int mn_index = is_b ? 1 : 0; /* op(A): rows are M; op(B): columns are N */
+    return contiguous_index == mn_index;
+}
+
+/*
  * Reference pack (a bit copy).  X holds elements of elem_size bytes; the
  * operand is op(X) with extent mn along its M (for A) or N (for B) index and
  * k along the contraction index.  is_b selects which index of op(X) is the
  * contraction index: op(A) is mn x k (contraction = column), op(B) is k x mn
  * (contraction = row).  The packed buffer holds ceil(mn/MNT) * ceil(k/KT)
  * contiguous blocks of KT * MNT elements, block (t, q) at position
- * t * ceil(k/KT) + q; inside a block, element (x, p) sits at
- * (p % KT) * MNT + (x % MNT).  Entries outside op(X) are all-zero bytes.
- * Element bits are copied untouched (NaN payloads, -0.0, subnormals).
+ * t * ceil(k/KT) + q.  Inside a block the tile keeps the orientation op(X) has
+ * in storage: if storage runs along the MN index, element (x, p) sits at
+ * (p % KT) * MNT + (x % MNT) (each k-slice contiguous); otherwise at
+ * (x % MNT) * KT + (p % KT) (each MN-row's k-run contiguous).  Entries outside
+ * op(X) are all-zero bytes.  Element bits are copied untouched (NaN payloads,
+ * -0.0, subnormals).
  */
 void oracle_pack(int elem_size, int is_b, int layout, char trans,
                  int64_t mn, int64_t k, const void* X, int64_t ld,
@@ -257,12 +276,14 @@ void oracle_pack(int elem_size, int is_b, int layout, char trans,
     unsigned char* dst = (unsigned char*)out;
     const int64_t nt = (mn + MNT - 1) / MNT, nk = (k + KT - 1) / KT;
     const int tr = is_trans(trans);
+    const int mn_major = oracle_mn_contiguous(is_b, layout, trans);
     for (int64_t t = 0; t < nt; ++t)
         for (int64_t q = 0; q < nk; ++q)
             for (int64_t pp = 0; pp < KT; ++pp)
                 for (int64_t xx = 0; xx < MNT; ++xx) {
                     const int64_t x = t * MNT + xx, p = q * KT + pp;
-                    unsigned char* d = dst + (((t * nk + q) * KT + pp) * MNT + xx) * elem_size;
+                    const int64_t inner = mn_major ? pp * MNT + xx : xx * KT + pp;
+                    unsigned char* d = dst + ((t * nk + q) * KT * MNT + inner) * elem_size;
                     if (x >= mn || p >= k) { memset(d, 0, (size_t)elem_size); continue; }
                     /* op(X)[r, c] with (r, c) = (x, p) for A, (p, x) for B */
                     const int64_t r = is_b ? p : x, c = is_b ? x : p;

@@ -25,17 +25,20 @@ inline int tile_kt(int cls, int elem) { (void)cls; return elem == 8 ? 16 : 32; }
 
 // One launch of the tile kernel, in kernel terms: C is column-major M x N
 // (C[x_a + x_b*ldc]); A-side element (x_a, p) at A[x_a*a_smn + p*a_sk];
-// B-side element (x_b, p) at B[x_b*b_smn + p*b_sk].  One of each operand's
-// strides is 1 (the host swaps operands for row-major C).
+// B-side element (x_b, p) at B[x_b*b_smn + p*b_sk].  A K-major operand has
+// s_k = 1, an MN-major one s_mn = 1 (the host swaps operands for row-major C).
 struct LaunchDesc {
     int elem;              // 8 (binary64) or 4 (binary32)
     int tile_class;
     int mode;              // Mode
     int pack_a, pack_b;    // fused mode: operand packed on first touch
     int no_publish, stats;
+    int spin_limit;        // follower polls per chunk before reading unpacked
+    int order;             // tile order inside an XCD's run (0 grouped, 1 rounds)
+    int stagger;           // k-loop start offset by tile row
     int64_t M, N, K;
-    const void* A; int64_t a_smn, a_sk;
-    const void* B; int64_t b_smn, b_sk;
+    const void* A; int64_t a_smn, a_sk; int a_kmajor;
+    const void* B; int64_t b_smn, b_sk; int b_kmajor;
     void* C; int64_t ldc;
     double alpha, beta;
     // workspace pieces (device pointers; null when unused)
@@ -43,7 +46,7 @@ struct LaunchDesc {
     void* bpack; int64_t bpack_copy_elems;
     uint64_t* aflag; uint64_t* bflag;   // [copies][tiles][ksteps]
     uint64_t* aclaim; uint64_t* bclaim; // [copies][tiles]
-    unsigned long long* stats_ptr;      // 3 counters
+    unsigned long long* stats_ptr;      // 4 counters
     uint64_t epoch;                     // unique per fused call in this process
     hipStream_t stream;
 };

@@ -41,6 +41,9 @@ struct fip_handle_s {
     int tile_override;
     int no_publish;
     int stats;
+    int spin_limit;
+    int order;
+    int stagger;
     void* ws;
     size_t ws_bytes;
     uint64_t epoch;   // stamp of the most recent fused call
@@ -105,8 +108,10 @@ struct Plan {
     int64_t apack_copy_elems, bpack_copy_elems;
 };
 
+bool mn_major(bool is_b, int layout, char trans);
+
 void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
-               bool standalone_pack, Plan* pl)
+               char tA, char tB, bool standalone_pack, Plan* pl)
 {
     memset(pl, 0, sizeof(*pl));
     pl->elem = dtype == FIP_F64 ? 8 : 4;
@@ -140,7 +145,7 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     if (k == 0 || m == 0 || n == 0) { pl->kpack_a = pl->kpack_b = 0; copies = 0; }
 
     int64_t off = 0;
-    pl->off_stats = off; off = align256(off + 3 * 8);
+    pl->off_stats = off; off = align256(off + 4 * 8);
     pl->off_aflag = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * pl->nK * 8 : 0));
     pl->off_bflag = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * pl->nK * 8 : 0));
     pl->off_aclaim = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * 8 : 0));
@@ -158,6 +163,8 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     p.copies = copies;
     p.policy = policy;
     p.stats_offset = pl->off_stats;
+    p.a_kmajor = !mn_major(false, layout, tA);
+    p.b_kmajor = !mn_major(true, layout, tB);
     const bool fl = pl->mode == fip::kModeFused;
     p.workspace_bytes = (pl->kpack_a || pl->kpack_b) ? off : 0;
     // Report in the caller's terms: op(A) is the kernel's B-side when swapped.
@@ -215,26 +222,36 @@ int check_args(int pos0, int layout, int64_t m, int64_t n, int64_t k, bool alpha
     return 0;
 }
 
-// Fill the kernel descriptor's operand fields (kernel A-side/B-side).
+// Whether op(X)'s storage runs along its MN index (M for op(A), N for op(B)).
+// op(X)[r, c] is stored element (r, c) for 'N' and (c, r) for 'T'/'C'; column-
+// major storage runs along the stored row index, row-major along the column.
+bool mn_major(bool is_b, int layout, char trans)
+{
+    const int runs_along = (layout == FIP_ROW_MAJOR) ^ (int)is_trans(trans);  // 0 = r, 1 = c
+    return runs_along == (is_b ? 1 : 0);
+}
+
+// Fill the kernel descriptor's operand fields (kernel A-side/B-side).  An
+// MN-major operand has element (x, p) at X[x + p*ld], a K-major one at
+// X[x*ld + p].
 void fill_operands(const Plan& pl, int layout, const void* A, int64_t lda, char tA, const void* B,
                    int64_t ldb, char tB, fip::LaunchDesc* d)
 {
-    int64_t rsA, csA, rsB, csB;
-    op_strides(layout, tA, lda, &rsA, &csA);
-    op_strides(layout, tB, ldb, &rsB, &csB);
-    // op(A) m x k: (x = i, p) -> smn = rsA, sk = csA.  op(B) k x n: (x = j, p)
-    // -> smn = csB, sk = rsB.
+    const bool a_mn = mn_major(false, layout, tA), b_mn = mn_major(true, layout, tB);
+    auto set = [](bool mn, const void* X, int64_t ld, const void** P, int64_t* smn, int64_t* sk,
+                  int* kmajor) {
+        *P = X;
+        *smn = mn ? 1 : ld;
+        *sk = mn ? ld : 1;
+        *kmajor = !mn;
+    };
     if (!pl.ks.swapped) {
-        d->A = A; d->a_smn = rsA; d->a_sk = csA;
-        d->B = B; d->b_smn = csB; d->b_sk = rsB;
+        set(a_mn, A, lda, &d->A, &d->a_smn, &d->a_sk, &d->a_kmajor);
+        set(b_mn, B, ldb, &d->B, &d->b_smn, &d->b_sk, &d->b_kmajor);
     } else {
-        d->A = B; d->a_smn = csB; d->a_sk = rsB;
-        d->B = A; d->b_smn = rsA; d->b_sk = csA;
+        set(b_mn, B, ldb, &d->A, &d->a_smn, &d->a_sk, &d->a_kmajor);
+        set(a_mn, A, lda, &d->B, &d->b_smn, &d->b_sk, &d->b_kmajor);
     }
-    // When a dimension has extent 1 both strides may be usable; prefer the
-    // MN-contiguous form when its stride is 1.
-    if (d->a_smn != 1 && d->a_sk != 1) d->a_smn = 0;  // flagged invalid below
-    if (d->b_smn != 1 && d->b_sk != 1) d->b_smn = 0;
 }
 
 void fill_workspace(const fip_handle_s* h, const Plan& pl, fip::LaunchDesc* d)
@@ -277,7 +294,7 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
             return 0;
         }
         Plan pl;
-        make_plan(h, dtype, layout, m, n, k, false, &pl);
+        make_plan(h, dtype, layout, m, n, k, tA, tB, false, &pl);
         const int ws = prepare_workspace(h, pl);
         if (ws) return ws;
         fip::LaunchDesc d;
@@ -288,9 +305,11 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.pack_a = pl.kpack_a; d.pack_b = pl.kpack_b;
         d.no_publish = h->no_publish;
         d.stats = h->stats;
+        d.spin_limit = h->spin_limit;
+        d.order = h->order;
+        d.stagger = h->stagger;
         d.M = ks.M; d.N = ks.N; d.K = k;
         fill_operands(pl, layout, A, lda, tA, B, ldb, tB, &d);
-        if (d.a_smn == 0 || d.b_smn == 0) return FIP_ERR_UNSUPPORTED;
         d.C = C; d.ldc = ldc;
         d.alpha = (double)alpha; d.beta = (double)beta;
         if (pl.pub.workspace_bytes > 0) {
@@ -323,6 +342,8 @@ int fip_create(fip_handle_t* handle)
     h->stream = nullptr;
     h->policy = FIP_PACK_AUTO;
     h->tile_override = -1;
+    h->spin_limit = 2000;
+    h->order = 0;
     *handle = h;
     return 0;
 }
@@ -362,6 +383,18 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
         if (value != 0 && value != 1) return 3;
         handle->stats = (int)value;
         return 0;
+    case FIP_ATTR_SPIN_LIMIT:
+        if (value < 0 || value > (1 << 24)) return 3;
+        handle->spin_limit = (int)value;
+        return 0;
+    case FIP_ATTR_ORDER:
+        if (value != 0 && value != 1) return 3;
+        handle->order = (int)value;
+        return 0;
+    case FIP_ATTR_STAGGER:
+        if (value != 0 && value != 1) return 3;
+        handle->stagger = (int)value;
+        return 0;
     default:
         return 2;
     }
@@ -376,6 +409,9 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_TILE: *value = handle->tile_override; return 0;
     case FIP_ATTR_NO_PUBLISH: *value = handle->no_publish; return 0;
     case FIP_ATTR_STATS: *value = handle->stats; return 0;
+    case FIP_ATTR_SPIN_LIMIT: *value = handle->spin_limit; return 0;
+    case FIP_ATTR_ORDER: *value = handle->order; return 0;
+    case FIP_ATTR_STAGGER: *value = handle->stagger; return 0;
     case FIP_ATTR_EPOCH: *value = (int64_t)handle->epoch; return 0;
     default: return 2;
     }
@@ -405,7 +441,7 @@ int fip_plan(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
     if (!valid_trans(transB)) return 8;
     if (plan == nullptr) return 9;
     Plan pl;
-    make_plan(handle, dtype, layout, m, n, k, false, &pl);
+    make_plan(handle, dtype, layout, m, n, k, transA, transB, false, &pl);
     *plan = pl.pub;
     return 0;
 }
@@ -450,7 +486,7 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
             return bad > 6 ? bad - 1 : bad;
         }
         Plan pl;
-        make_plan(handle, dtype, layout, m, n, k, true, &pl);
+        make_plan(handle, dtype, layout, m, n, k, transA, transB, true, &pl);
         if (pl.pub.workspace_bytes == 0) { handle->last = pl.pub; handle->has_last = 1; return 0; }
         const int ws = prepare_workspace(handle, pl);
         if (ws) return ws;
@@ -461,7 +497,6 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
         d.mode = pl.mode;
         d.M = pl.ks.M; d.N = pl.ks.N; d.K = k;
         fill_operands(pl, layout, A, lda, transA, B, ldb, transB, &d);
-        if (d.a_smn == 0 || d.b_smn == 0) return FIP_ERR_UNSUPPORTED;
         fill_workspace(handle, pl, &d);
         d.stream = handle->stream;
         if (fip::launch_pack(d) != hipSuccess) return FIP_ERR_LAUNCH;

@@ -82,50 +82,83 @@ struct Params {
     int tilesM, tilesN, nK, group_m;
     int mode, pack_a, pack_b, no_publish, do_stats;
     int a_vec, b_vec, c_vec;
+    int a_fast, b_fast;  // interior chunks may use the 32-bit-offset vector loader
+    int spin_limit;  // polls a follower spends waiting for a publish flag (0: never wait)
+    int order;       // tile order inside an XCD's run: 0 grouped, 1 column-distinct rounds
+    int stagger;     // 1: start the k-loop of tile row tm at chunk (tm % 8) * nK / 8
 };
 
-// LDS row pitch in elements: the tile extent plus padding so that the four
-// k-rows one MFMA fragment read touches start 16 elements apart modulo the 64
-// 4-byte banks (conflict-free ds_read of a 16x4 fragment).  Rows stay 16-byte
-// aligned.
+// LDS pitch of an MN-major tile ([k][mn]): the tile extent plus padding so
+// that the four k-rows one MFMA fragment read touches start 16 elements apart
+// modulo the 64 4-byte banks (conflict-free 16x4 fragment reads).
 template <typename T, int MNT>
-constexpr int lds_pitch()
+constexpr int lds_pitch_mn()
 {
     constexpr int mod = 256 / (int)sizeof(T);
     return MNT + (((16 - MNT) % mod) + mod) % mod;
 }
-
+// LDS pitch of a K-major tile ([mn][k]): KT plus padding so that the 16 rows
+// one fragment read touches land on distinct banks: a row stride of 36 banks
+// (f64: KT + 2 = 18 elements, f32: KT + 4 = 36); rows stay 16-byte aligned.
 // One operand chunk (MNT x KT) held in registers while it moves from HBM to
-// LDS (and, for a producer, to the pack buffer).
-//   Linear mapping: register vector i covers packed positions o .. o+VEC-1 with
-//     o = (tid + i*NTHR)*VEC, i.e. k-row pp = o / MNT, columns xx = o % MNT ...
-//     Used for packed sources and for unpacked operands contiguous along MN.
-//   Transposed mapping (unpacked operand contiguous along k): vector i covers
-//     k-rows pp .. pp+VEC-1 of column xx, with v = tid + i*NTHR, xx = v / KV,
-//     pp = (v % KV)*VEC.
+// LDS (and, for a producer, to the pack buffer).  KC: the operand is K-major
+// (contiguous along k); otherwise MN-major.  The chunk keeps that orientation
+// everywhere: in the unpacked operand, in LDS and in the packed copy, so no
+// step transposes it.  Register vector i holds chunk elements o .. o+VEC-1,
+// o = (tid + i*NTHR)*VEC, in the orientation's linear order:
+//   MN-major: (x, p) = (o % MNT, o / MNT),  packed position p*MNT + x
+//   K-major:  (x, p) = (o / KT, o % KT),    packed position x*KT + p
+// so the packed position of register vector i is always o.
 template <typename T, int MNT, int KT, int NTHR, bool KC>
 struct Chunk {
     typedef typename Types<T>::vec V;
     static constexpr int VEC = Types<T>::VEC;
     static constexpr int NV = MNT * KT / (NTHR * VEC);
-    static constexpr int LDP = lds_pitch<T, MNT>();
-    static constexpr int KV = KT / VEC;
+    static constexpr int LDP = KC ? (sizeof(T) == 8 ? KT + 2 : KT + 4) : lds_pitch_mn<T, MNT>();
+    static constexpr int LDS_ELEMS = KC ? MNT * LDP : KT * LDP;
     static_assert(NV * NTHR * VEC == MNT * KT, "chunk must split evenly over the threads");
     static_assert(MNT % VEC == 0 && KT % VEC == 0, "vector width must divide the chunk");
 
     V r[NV];
 
-    // Unpacked source: element (x, p) at X[x*smn + p*sk]; one of smn, sk is 1.
-    __device__ __forceinline__ void load_unpacked(const T* __restrict__ X, int64_t smn, int64_t sk,
-                                                  int64_t MN, int64_t K, int64_t x0, int64_t p0,
-                                                  bool vec_ok, int tid)
+    __device__ __forceinline__ static int elem_o(int i, int tid) { return (tid + i * NTHR) * VEC; }
+    __device__ __forceinline__ static int x_of(int o) { return KC ? o / KT : o % MNT; }
+    __device__ __forceinline__ static int p_of(int o) { return KC ? o % KT : o / MNT; }
+    // LDS element index of chunk element (x, p)
+    __device__ __forceinline__ static int lds_at(int x, int p) { return KC ? x * LDP + p : p * LDP + x; }
+
+    // Unpacked source, interior chunk: every element exists and vector loads
+    // are aligned.  Element (x, p) sits at X[x + p*ld] (MN-major) or
+    // X[x*ld + p] (K-major).  The chunk origin is uniform across the
+    // workgroup; each lane adds loop-invariant 32-bit byte offsets (the host
+    // guarantees they fit), so loads use the scalar-base addressing form and
+    // the code is straight-line with no masks.
+    __device__ __forceinline__ static uint32_t fast_offset(int i, int tid, int64_t ld)
+    {
+        const int o = elem_o(i, tid);
+        const int64_t x = x_of(o), p = p_of(o);
+        return (uint32_t)((KC ? x * ld + p : x + p * ld) * (int64_t)sizeof(T));
+    }
+    __device__ __forceinline__ void load_fast(const T* __restrict__ origin, const uint32_t* off)
+    {
+        const char* base = reinterpret_cast<const char*>(origin);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) r[i] = *reinterpret_cast<const V*>(base + off[i]);
+    }
+
+    // Unpacked source, fringe chunk (Sec. 2.2 zero padding done in registers):
+    // elements outside the MN x K operand read as +0.0; vector loads only where
+    // a whole aligned vector exists.
+    __device__ __forceinline__ void load_edge(const T* __restrict__ X, int64_t ld, int64_t MN,
+                                              int64_t K, int64_t x0, int64_t p0, bool vec_ok,
+                                              int tid)
     {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
+            const int o = elem_o(i, tid);
+            const int64_t x = x0 + x_of(o), p = p0 + p_of(o);
             if (!KC) {
-                const int o = (tid + i * NTHR) * VEC;
-                const int64_t x = x0 + o % MNT, p = p0 + o / MNT;
-                const T* src = X + x + p * sk;
+                const T* src = X + x + p * ld;
                 if (vec_ok && p < K && x + VEC <= MN) {
                     r[i] = *reinterpret_cast<const V*>(src);
                 } else {
@@ -133,9 +166,7 @@ struct Chunk {
                     for (int e = 0; e < VEC; ++e) r[i][e] = (p < K && x + e < MN) ? src[e] : T(0);
                 }
             } else {
-                const int v = tid + i * NTHR;
-                const int64_t x = x0 + v / KV, p = p0 + (v % KV) * VEC;
-                const T* src = X + x * smn + p;
+                const T* src = X + x * ld + p;
                 if (vec_ok && x < MN && p + VEC <= K) {
                     r[i] = *reinterpret_cast<const V*>(src);
                 } else {
@@ -150,50 +181,37 @@ struct Chunk {
     __device__ __forceinline__ void load_packed(const T* __restrict__ chunk, int tid)
     {
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-            r[i] = *reinterpret_cast<const V*>(chunk + (tid + i * NTHR) * VEC);
+        for (int i = 0; i < NV; ++i) r[i] = *reinterpret_cast<const V*>(chunk + elem_o(i, tid));
     }
 
-    __device__ __forceinline__ void store_lds(T* lds, bool linear, int tid) const
+    __device__ __forceinline__ void store_lds(T* lds, int tid) const
     {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            if (!KC || linear) {
-                const int o = (tid + i * NTHR) * VEC;
-                *reinterpret_cast<V*>(lds + (o / MNT) * LDP + o % MNT) = r[i];
-            } else {
-                const int v = tid + i * NTHR;
-                const int xx = v / KV, pp = (v % KV) * VEC;
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) lds[(pp + e) * LDP + xx] = r[i][e];
-            }
+            const int o = elem_o(i, tid);
+            *reinterpret_cast<V*>(lds + lds_at(x_of(o), p_of(o))) = r[i];
         }
     }
 
-    // Pack store of registers loaded from the unpacked source.
     __device__ __forceinline__ void store_pack(T* __restrict__ chunk, int tid) const
     {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            if (!KC) {
-                *reinterpret_cast<V*>(chunk + (tid + i * NTHR) * VEC) = r[i];
-            } else {
-                const int v = tid + i * NTHR;
-                const int xx = v / KV, pp = (v % KV) * VEC;
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) chunk[(pp + e) * MNT + xx] = r[i][e];
-            }
-        }
+        for (int i = 0; i < NV; ++i) *reinterpret_cast<V*>(chunk + elem_o(i, tid)) = r[i];
     }
 };
 
 // Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs,
-// so w % 8 is (normally) the XCD.  Each XCD gets one contiguous run of the
-// grouped tile order (GROUP_M tile rows swept column by column), which keeps
-// the tiles running together on an XCD compact for its L2 and keeps most of
-// the panels an XCD packs private to it.
-__device__ __forceinline__ void tile_coords(int w, int tilesM, int tilesN, int group_m, int& tm,
-                                            int& tn)
+// so w % 8 is (normally) the XCD.  Each XCD gets one contiguous run of a
+// grouped tile order: bands of GROUP_M tile rows, swept column by column.
+// That keeps the tiles running together on an XCD compact for its L2 and most
+// of the panels an XCD packs private to it.
+//   order 0: inside a band, the GROUP_M tiles of one column are consecutive;
+//   order 1: inside a band, consecutive tiles take distinct columns (round r,
+//            slot s -> column s, row (s + r) mod GROUP_M), so the first round of
+//            workgroups touches every column panel of the band once and later
+//            rounds find them all packed.
+__device__ __forceinline__ void tile_coords(int w, int tilesM, int tilesN, int group_m, int order,
+                                            int& tm, int& tn)
 {
     const int T = tilesM * tilesN;
     const int xcd = w & 7, local = w >> 3;
@@ -204,8 +222,14 @@ __device__ __forceinline__ void tile_coords(int w, int tilesM, int tilesN, int g
     const int first_m = g * group_m;
     const int gsize = min(tilesM - first_m, group_m);
     const int rem = t - g * per_group;
-    tm = first_m + rem % gsize;
-    tn = rem / gsize;
+    if (order == 0) {
+        tm = first_m + rem % gsize;
+        tn = rem / gsize;
+    } else {
+        const int round = rem / tilesN, slot = rem - round * tilesN;
+        tn = slot;
+        tm = first_m + (slot + round) % gsize;
+    }
 }
 
 template <typename T, int NTHR>
@@ -239,18 +263,31 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     constexpr int FM = WTM / 16, FN = WTN / 16;  // MFMA blocks per wave
     static_assert(FM >= 1 && FN >= 1 && KT % 4 == 0, "tile shape");
 
-    __shared__ __attribute__((aligned(16))) T sA[2][KT * ChA::LDP];
-    __shared__ __attribute__((aligned(16))) T sB[2][KT * ChB::LDP];
+    __shared__ __attribute__((aligned(16))) T sA[2][ChA::LDS_ELEMS];
+    __shared__ __attribute__((aligned(16))) T sB[2][ChB::LDS_ELEMS];
     __shared__ int s_role;
     __shared__ int s_src[2];  // per chunk parity: bit 0 A packed, bit 1 B packed
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
     int tm, tn;
-    tile_coords(blockIdx.x, P.tilesM, P.tilesN, P.group_m, tm, tn);
+    tile_coords(blockIdx.x, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
     const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * NT;
     const int nK = P.nK;
     const uint64_t epoch = P.epoch;
+    // Unpacked operands: the non-unit stride, and whether this tile lies fully
+    // inside (only the last k-step can then still be a fringe chunk).
+    const int64_t lda = AKC ? P.a_smn : P.a_sk, ldb = BKC ? P.b_smn : P.b_sk;
+    const bool a_in = P.a_fast && x0a + MT <= P.M, b_in = P.b_fast && x0b + NT <= P.N;
+    uint32_t a_off[ChA::NV], b_off[ChB::NV];
+#pragma unroll
+    for (int i = 0; i < ChA::NV; ++i) a_off[i] = ChA::fast_offset(i, tid, lda);
+#pragma unroll
+    for (int i = 0; i < ChB::NV; ++i) b_off[i] = ChB::fast_offset(i, tid, ldb);
+    // origin of the unpacked chunk (x0, p0): X + x0*s_mn + p0*s_k
+    const int64_t a_step = AKC ? KT : KT * lda, b_step = BKC ? KT : KT * ldb;
+    const T* a_org = P.A + (AKC ? x0a * lda : x0a);
+    const T* b_org = P.B + (BKC ? x0b * ldb : x0b);
 
     const bool consume = P.mode == kModeConsumePacked;
     bool fused = P.mode == kModeFused;
@@ -275,16 +312,24 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     // contiguous along k the two sources are staged by different
     // thread-to-element assignments, so waves that chose differently would
     // each fill a different part of the LDS tile.
-    auto published = [&](const uint64_t* flags, int q) -> bool {
-        return __hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+    //
+    // A producer never waits.  A workgroup that produces nothing ("follower")
+    // may wait a bounded number of polls for a chunk its producer has not yet
+    // published (the paper's "one synchronization", Sec. 3.5): the producer is
+    // resident (it claimed the panel at its start) and never waits itself, so
+    // the wait cannot form a cycle, and after spin_limit polls the follower
+    // reads the unpacked operand instead.  Either way the bits are the same.
+    // Logical k-step q works on chunk c(q) = (q + rot) mod nK.  With
+    // staggering, tiles of different tile rows start their k-loops at
+    // different chunks (rot depends on the tile row only, so tiles sharing an
+    // A panel stay in step, and the same order is used in every mode).
+    const int rot = P.stagger ? (int)(((int64_t)(tm & 7) * nK) >> 3) : 0;
+    auto chunk_of = [&](int q) -> int {
+        const int c = q + rot;
+        return c >= nK ? c - nK : c;
     };
-    bool prodA = false, prodB = false;
-    auto decide = [&](int q) -> int {  // thread 0 only
-        int src = 0;
-        if (consume) return 3;
-        if (useA && !prodA && published(aflags, q)) src |= 1;
-        if (useB && !prodB && published(bflags, q)) src |= 2;
-        return src;
+    auto flag_of = [&](const uint64_t* flags, int c) -> uint64_t {
+        return __hip_atomic_load(flags + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
 
     if (tid == 0) {
@@ -296,28 +341,84 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
                                           __HIP_MEMORY_SCOPE_AGENT) != epoch)
             role |= 2;
         s_role = role;
-        prodA = role & 1;
-        prodB = role & 2;
-        s_src[0] = decide(0);
     }
     __syncthreads();
-    prodA = s_role & 1;
-    prodB = s_role & 2;
+    const bool prodA = s_role & 1, prodB = s_role & 2;
     const bool producer = prodA || prodB;
+    const bool wantA = useA && !prodA, wantB = useB && !prodB;  // would read a packed copy
+    const bool follower = !producer && (wantA || wantB);
 
-    unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0;
+    // Wave 0 decides, for the whole workgroup, where each chunk comes from
+    // (packed copy or unpacked operand) and broadcasts it through LDS behind
+    // the next barrier.  The decision must be workgroup-uniform: for an operand
+    // contiguous along k the two sources are staged by different
+    // thread-to-element assignments, so waves that chose differently would
+    // each fill a different part of the LDS tile.
+    //
+    // Wave 0 keeps, per operand, the first logical step not yet known to be
+    // published (flags only ever go from unpublished to published within a
+    // call, so this knowledge never goes stale).  One poll reads the flags of
+    // the next 8 unknown steps at once (lanes 0-7 for A, 8-15 for B).
+    //
+    // A producer never waits.  A follower (it produces nothing) may wait a
+    // bounded number of polls for a chunk its producer has not yet published
+    // (the paper's "one synchronization", Sec. 3.5): the producer is resident
+    // (it claimed the panel at its start) and never waits itself, so the wait
+    // cannot form a cycle, and after spin_limit polls the follower reads the
+    // unpacked operand instead.  Either way the bits are the same.
+    int knownA = 0, knownB = 0;
+    uint64_t pf = 0;
+    auto poll_issue = [&]() {  // wave 0
+        pf = epoch;
+        if (lane < 8) {
+            const int q = knownA + lane;
+            if (wantA && q < nK) pf = flag_of(aflags, chunk_of(q));
+        } else if (lane < 16) {
+            const int q = knownB + lane - 8;
+            if (wantB && q < nK) pf = flag_of(bflags, chunk_of(q));
+        }
+    };
+    auto poll_absorb = [&]() {  // wave 0
+        const uint64_t ok = __ballot(pf == epoch);
+        knownA += __builtin_ctzll(~(ok & 0xFFull) | 0x100ull);
+        knownB += __builtin_ctzll(~((ok >> 8) & 0xFFull) | 0x100ull);
+    };
+    unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_wait = 0;
+    // wave 0; polled: poll_issue() was called for this step (absorb it exactly once)
+    auto decide = [&](int q, bool polled) -> int {
+        if (consume) return 3;
+        if (polled) poll_absorb();
+        if (follower) {
+            int polls = 0;
+            while (((wantA && q >= knownA) || (wantB && q >= knownB)) && polls < P.spin_limit) {
+                __builtin_amdgcn_s_sleep(1);
+                poll_issue();
+                poll_absorb();
+                ++polls;
+            }
+            n_wait += polls;
+        }
+        return (wantA && q < knownA ? 1 : 0) | (wantB && q < knownB ? 2 : 0);
+    };
+    auto need_poll = [&](int q) -> bool { return (wantA && q >= knownA) || (wantB && q >= knownB); };
+
     ChA ra;
     ChB rb;
     auto load_chunks = [&](int q, int src) {
         const bool apk = src & 1, bpk = src & 2;
-        if (apk) ra.load_packed(apanel + (int64_t)q * KT * MT, tid);
-        else ra.load_unpacked(P.A, P.a_smn, P.a_sk, P.M, P.K, x0a, (int64_t)q * KT, P.a_vec, tid);
-        if (bpk) rb.load_packed(bpanel + (int64_t)q * KT * NT, tid);
-        else rb.load_unpacked(P.B, P.b_smn, P.b_sk, P.N, P.K, x0b, (int64_t)q * KT, P.b_vec, tid);
+        const int c = chunk_of(q);
+        const int64_t p0 = (int64_t)c * KT;
+        const bool kin = p0 + KT <= P.K;
+        if (apk) ra.load_packed(apanel + (int64_t)c * KT * MT, tid);
+        else if (a_in && kin) ra.load_fast(a_org + c * a_step, a_off);
+        else ra.load_edge(P.A, lda, P.M, P.K, x0a, p0, P.a_vec, tid);
+        if (bpk) rb.load_packed(bpanel + (int64_t)c * KT * NT, tid);
+        else if (b_in && kin) rb.load_fast(b_org + c * b_step, b_off);
+        else rb.load_edge(P.B, ldb, P.N, P.K, x0b, p0, P.b_vec, tid);
         if (P.do_stats && tid == 0) {
             n_prod += (int)prodA + (int)prodB;
             n_pk += (int)apk + (int)bpk;
-            n_unpk += (int)(useA && !prodA && !apk) + (int)(useB && !prodB && !bpk);
+            n_unpk += (int)(wantA && !apk) + (int)(wantB && !bpk);
         }
     };
 
@@ -327,61 +428,79 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
 
-    // Prologue: chunk 0; thread 0 decides chunk 1.
+    // Prologue: decide chunk 0, stage it; decide chunk 1.
+    if (wave == 0) {
+        const bool polled = need_poll(0);
+        if (polled) poll_issue();
+        const int src = decide(0, polled);
+        if (lane == 0) s_src[0] = src;
+    }
+    __syncthreads();
     {
         const int src = s_src[0];
+        const bool polled1 = wave == 0 && nK > 1 && need_poll(1);
+        if (polled1) poll_issue();
         load_chunks(0, src);
-        if (tid == 0 && nK > 1) s_src[1] = decide(1);
-        ra.store_lds(sA[0], src & 1, tid);
-        rb.store_lds(sB[0], src & 2, tid);
-        if (prodA) ra.store_pack(apanel, tid);
-        if (prodB) rb.store_pack(bpanel, tid);
+        ra.store_lds(sA[0], tid);
+        rb.store_lds(sB[0], tid);
+        if (prodA) ra.store_pack(apanel + (int64_t)chunk_of(0) * KT * MT, tid);
+        if (prodB) rb.store_pack(bpanel + (int64_t)chunk_of(0) * KT * NT, tid);
+        if (wave == 0 && nK > 1) {
+            const int src1 = decide(1, polled1);
+            if (lane == 0) s_src[1] = src1;
+        }
     }
     __syncthreads();
 
     for (int q = 0; q < nK; ++q) {
         const int cur = q & 1;
         const bool more = q + 1 < nK;
+        // Wave 0 polls for step q+2 first; the answer is needed only after this
+        // step's MFMAs.
+        const bool decide_next = wave == 0 && q + 2 < nK;
+        const bool polled = decide_next && need_poll(q + 2);
+        if (polled) poll_issue();
         int src = 0;
         if (more) {
             src = s_src[(q + 1) & 1];  // decided before the previous barrier
             load_chunks(q + 1, src);
         }
-        // Thread 0 reads the flags of chunk q+2 now; the loads complete under the MFMAs.
-        int next_src = 0;
-        if (tid == 0 && q + 2 < nK) next_src = decide(q + 2);
-        // MFMAs on chunk q.
-        const T* la = sA[cur] + wm * WTM + (lane & 15);
-        const T* lb = sB[cur] + wn * WTN + (lane & 15);
+        // MFMAs on chunk c(q).  Fragment element (row x, k-row kr) of either
+        // orientation: lane l supplies x = base + l%16, kr = 4s + l/16.
+        const T* la = sA[cur] + ChA::lds_at(wm * WTM + (lane & 15), lane >> 4);
+        const T* lb = sB[cur] + ChB::lds_at(wn * WTN + (lane & 15), lane >> 4);
 #pragma unroll
         for (int s = 0; s < KT / 4; ++s) {
-            const int kr = 4 * s + (lane >> 4);
             T af[FM], bf[FN];
 #pragma unroll
-            for (int a = 0; a < FM; ++a) af[a] = la[kr * ChA::LDP + a * 16];
+            for (int a = 0; a < FM; ++a) af[a] = la[ChA::lds_at(a * 16, 4 * s)];
 #pragma unroll
-            for (int b = 0; b < FN; ++b) bf[b] = lb[kr * ChB::LDP + b * 16];
+            for (int b = 0; b < FN; ++b) bf[b] = lb[ChB::lds_at(b * 16, 4 * s)];
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
                 for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(af[a], bf[b], acc[a][b]);
         }
-        // Pack stores of chunk q (issued one step earlier) must be complete
-        // before chunk q is published below.
+        // Pack stores of chunk c(q) (issued one step earlier) must be complete
+        // before it is published below.
         if (producer) wait_all_memory();
         if (more) {
-            ra.store_lds(sA[cur ^ 1], src & 1, tid);
-            rb.store_lds(sB[cur ^ 1], src & 2, tid);
-            if (prodA) ra.store_pack(apanel + (int64_t)(q + 1) * KT * MT, tid);
-            if (prodB) rb.store_pack(bpanel + (int64_t)(q + 1) * KT * NT, tid);
+            ra.store_lds(sA[cur ^ 1], tid);
+            rb.store_lds(sB[cur ^ 1], tid);
+            if (prodA) ra.store_pack(apanel + (int64_t)chunk_of(q + 1) * KT * MT, tid);
+            if (prodB) rb.store_pack(bpanel + (int64_t)chunk_of(q + 1) * KT * NT, tid);
         }
         // s_src[q & 1] was last read at the top of iteration q-1, before the
-        // previous barrier, so it is free for chunk q+2.
-        if (tid == 0 && q + 2 < nK) s_src[q & 1] = next_src;
+        // previous barrier, so it is free for step q+2.
+        if (decide_next) {
+            const int src2 = decide(q + 2, polled);
+            if (lane == 0) s_src[q & 1] = src2;
+        }
         __syncthreads();
         if (tid == 0 && producer && !P.no_publish) {
-            if (prodA) __hip_atomic_store(aflags + q, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (prodB) __hip_atomic_store(bflags + q, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int c = chunk_of(q);
+            if (prodA) __hip_atomic_store(aflags + c, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prodB) __hip_atomic_store(bflags + c, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 
@@ -389,6 +508,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         atomicAdd(P.stats + 0, n_prod);
         atomicAdd(P.stats + 1, n_pk);
         atomicAdd(P.stats + 2, n_unpk);
+        atomicAdd(P.stats + 3, n_wait);
     }
 
     // Epilogue: C = alpha*acc + beta*C (C not read when beta == 0).
@@ -463,13 +583,13 @@ __global__ void __launch_bounds__(NTHR) pack_kernel(const Params<T> P)
     if (b < nA) {
         const int64_t t = b / nK, q = b % nK;
         Chunk<T, MT, KT, NTHR, AKC> r;
-        r.load_unpacked(P.A, P.a_smn, P.a_sk, P.M, P.K, t * MT, q * KT, P.a_vec, tid);
+        r.load_edge(P.A, AKC ? P.a_smn : P.a_sk, P.M, P.K, t * MT, q * KT, P.a_vec, tid);
         r.store_pack(P.apack + (t * nK + q) * KT * MT, tid);
     } else {
         const int64_t bb = b - nA;
         const int64_t t = bb / nK, q = bb % nK;
         Chunk<T, NT, KT, NTHR, BKC> r;
-        r.load_unpacked(P.B, P.b_smn, P.b_sk, P.N, P.K, t * NT, q * KT, P.b_vec, tid);
+        r.load_edge(P.B, BKC ? P.b_smn : P.b_sk, P.N, P.K, t * NT, q * KT, P.b_vec, tid);
         r.store_pack(P.bpack + (t * nK + q) * KT * NT, tid);
     }
 }
@@ -515,11 +635,20 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.group_m = 8;
     P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
     P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
-    const int64_t a_far = d.a_smn == 1 ? d.a_sk : d.a_smn;  // the non-unit stride
-    const int64_t b_far = d.b_smn == 1 ? d.b_sk : d.b_smn;
+    const int64_t a_far = d.a_kmajor ? d.a_smn : d.a_sk;  // the leading dimension
+    const int64_t b_far = d.b_kmajor ? d.b_smn : d.b_sk;
     P.a_vec = aligned16(d.A) && a_far % VEC == 0;
     P.b_vec = aligned16(d.B) && b_far % VEC == 0;
     P.c_vec = aligned16(d.C) && d.ldc % VEC == 0;
+    // byte offsets inside one chunk must fit in 32 bits: (MT + KT*ld) elements
+    // for an MN-contiguous operand, (MT*ld + KT) for a k-contiguous one
+    const int64_t a_span = (d.a_kmajor ? MT * a_far + KT : MT + KT * a_far) * (int64_t)sizeof(T);
+    const int64_t b_span = (d.b_kmajor ? NT * b_far + KT : NT + KT * b_far) * (int64_t)sizeof(T);
+    P.a_fast = P.a_vec && a_span < ((int64_t)1 << 31);
+    P.b_fast = P.b_vec && b_span < ((int64_t)1 << 31);
+    P.spin_limit = d.spin_limit;
+    P.order = d.order;
+    P.stagger = d.stagger;
     return P;
 }
 
@@ -528,7 +657,7 @@ hipError_t launch_tile(const LaunchDesc& d)
 {
     constexpr int KT = sizeof(T) == 8 ? 16 : 32;
     const Params<T> P = make_params<T>(d, MT, NT, KT);
-    const bool akc = d.a_smn != 1, bkc = d.b_smn != 1;
+    const bool akc = d.a_kmajor, bkc = d.b_kmajor;
     const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN)), block(WM * WN * 64);
     if (!akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, false><<<grid, block, 0, d.stream>>>(P);
     else if (!akc && bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, true><<<grid, block, 0, d.stream>>>(P);
@@ -543,7 +672,7 @@ hipError_t launch_pack_t(const LaunchDesc& d)
     constexpr int KT = sizeof(T) == 8 ? 16 : 32;
     constexpr int NTHR = WM * WN * 64;
     const Params<T> P = make_params<T>(d, MT, NT, KT);
-    const bool akc = d.a_smn != 1, bkc = d.b_smn != 1;
+    const bool akc = d.a_kmajor, bkc = d.b_kmajor;
     const int64_t blocks = ((int64_t)P.tilesM + P.tilesN) * P.nK;
     const dim3 grid((unsigned)blocks), block(NTHR);
     if (!akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, false, false><<<grid, block, 0, d.stream>>>(P);

@@ -25,6 +25,7 @@ FIP_COL_MAJOR, FIP_ROW_MAJOR = 0, 1
 FIP_F64, FIP_F32 = 0, 1
 FIP_ERR_HANDLE, FIP_ERR_WORKSPACE, FIP_ERR_LAUNCH, FIP_ERR_UNSUPPORTED, FIP_ERR_ALLOC = -1, -2, -3, -4, -5
 FIP_ATTR_PACK_POLICY, FIP_ATTR_TILE, FIP_ATTR_NO_PUBLISH, FIP_ATTR_STATS, FIP_ATTR_EPOCH = 1, 2, 3, 4, 5
+FIP_ATTR_SPIN_LIMIT, FIP_ATTR_ORDER, FIP_ATTR_STAGGER = 6, 7, 8
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
 
@@ -38,6 +39,7 @@ class fip_plan_t(ctypes.Structure):
         ("tile_class", ctypes.c_int32),
         ("pack_a", ctypes.c_int32), ("pack_b", ctypes.c_int32),
         ("copies", ctypes.c_int32), ("policy", ctypes.c_int32),
+        ("a_kmajor", ctypes.c_int32), ("b_kmajor", ctypes.c_int32),
         ("a_pack_offset", ctypes.c_int64), ("a_copy_bytes", ctypes.c_int64),
         ("b_pack_offset", ctypes.c_int64), ("b_copy_bytes", ctypes.c_int64),
         ("a_flag_offset", ctypes.c_int64), ("b_flag_offset", ctypes.c_int64),

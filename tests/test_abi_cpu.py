@@ -149,3 +149,13 @@ def test_missing_workspace_is_an_error_not_a_fallback(h):
     assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_ALL) == 0
     rc = F.fip_dgemm(h, 0, 300, 300, 300, 1.0, FAKE, 300, "N", FAKE, 300, "N", 0.0, FAKE, 300)
     assert rc == F.FIP_ERR_WORKSPACE
+
+
+def test_plan_orientation_matches_oracle_rule(h):
+    import oracle
+    for layout in (0, 1):
+        for tA in "NTC":
+            for tB in "NTC":
+                p = plan(h, 300, 200, 77, layout=layout, policy=F.FIP_PACK_ALL, tile=2, t=tA + tB)
+                assert p.a_kmajor == (not oracle.mn_contiguous(0, layout, tA))
+                assert p.b_kmajor == (not oracle.mn_contiguous(1, layout, tB))

@@ -156,10 +156,14 @@ def test_special_cases(F, dtype):
     assert np.array_equal(C.cpu().numpy(), c.C, equal_nan=True)
 
 
-def _run_policy(F, c, policy, no_publish=0, ws=None):
+def _run_policy(F, c, policy, no_publish=0, ws=None, stagger=0, order=0, spin=None):
     import torch
     h = handle(F, policy=policy)
     h.set_attr(F.FIP_ATTR_NO_PUBLISH, no_publish)
+    h.set_attr(F.FIP_ATTR_STAGGER, stagger)
+    h.set_attr(F.FIP_ATTR_ORDER, order)
+    if spin is not None:
+        h.set_attr(F.FIP_ATTR_SPIN_LIMIT, spin)
     if ws is not None:
         h.attach_workspace(ws)
     A, B = to_dev(c.A), to_dev(c.B)
@@ -175,20 +179,23 @@ def _run_policy(F, c, policy, no_publish=0, ws=None):
 @pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
 @pytest.mark.parametrize("layout,tA,tB", [(COL, "N", "N"), (COL, "T", "N"), (ROW, "N", "T"),
                                           (ROW, "T", "T")])
-def test_modes_bitwise_identical(F, dtype, layout, tA, tB):
-    """Fused (AUTO, ALL, ALL without publishing), unpacked (NONE) and pack-then-compute
-    (fip_pack + CONSUME_ONLY) run the same tile kernel with the same k order, so C must
-    agree bit for bit; and with the oracle within tolerance."""
-    say("modes", dtype.__name__, layout, tA, tB)
+@pytest.mark.parametrize("stagger", [0, 1])
+def test_modes_bitwise_identical(F, dtype, layout, tA, tB, stagger):
+    """Fused (AUTO, ALL, ALL without publishing, both tile orders, waiting or not), unpacked
+    (NONE) and pack-then-compute (fip_pack + CONSUME_ONLY) run the same tile kernel with the
+    same k order, so C must agree bit for bit; and with the oracle within tolerance."""
+    say("modes", dtype.__name__, layout, tA, tB, "stagger", stagger)
     c = synth.make_case(layout, 700, 600, 333, tA, tB, ld_pad=7 if tA == "T" else 0,
                         dtype=dtype, seed=99)
-    ref, _ = _run_policy(F, c, F.FIP_PACK_NONE)
+    ref, _ = _run_policy(F, c, F.FIP_PACK_NONE, stagger=stagger)
     check_full(c, ref)
-    for pol, nopub in [(F.FIP_PACK_AUTO, 0), (F.FIP_PACK_ALL, 0), (F.FIP_PACK_ALL, 1),
-                       (F.FIP_PACK_CONSUME_ONLY, 0), (F.FIP_PACK_AUTO, 0)]:
-        say("  policy", pol, "no_publish", nopub)
-        out, _ = _run_policy(F, c, pol, nopub)
-        assert np.array_equal(out.view(np.uint8), ref.view(np.uint8)), (pol, nopub)
+    for pol, nopub, order, spin in [(F.FIP_PACK_AUTO, 0, 0, None), (F.FIP_PACK_ALL, 0, 1, None),
+                                    (F.FIP_PACK_ALL, 1, 0, 4), (F.FIP_PACK_ALL, 0, 0, 0),
+                                    (F.FIP_PACK_CONSUME_ONLY, 0, 0, None),
+                                    (F.FIP_PACK_AUTO, 0, 1, 0)]:
+        say("  policy", pol, "no_publish", nopub, "order", order, "spin", spin)
+        out, _ = _run_policy(F, c, pol, nopub, stagger=stagger, order=order, spin=spin)
+        assert np.array_equal(out.view(np.uint8), ref.view(np.uint8)), (pol, nopub, order, spin)
 
 
 @pytest.mark.parametrize("dtype,shape,tile", [(F64, (700, 600, 333), -1), (F32, (700, 600, 333), -1),

@@ -265,11 +265,27 @@ def _encoded_case(layout, t, rows, cols, pad, dtype):
     return synth.fill_stored(layout, sr, sc, ld, stored, dtype), ld, vals
 
 
+def _storage_runs_along_mn(buf, layout, t, rows, cols, ld, is_b):
+    """Independent route to the orientation: NumPy's own strides of the op() view."""
+    v = synth.op_view(buf, layout, t, rows, cols, ld)
+    mn_axis = 1 if is_b else 0
+    return v.strides[mn_axis] == v.itemsize and v.strides[1 - mn_axis] != v.itemsize
+
+
+def test_orientation_rule_matches_numpy_strides():
+    for is_b, layout, t in itertools.product([0, 1], [COL, ROW], TRANS):
+        rows, cols = (7, 5) if is_b else (5, 7)
+        buf, ld, _ = _encoded_case(layout, t, rows, cols, 3, np.float64)
+        assert oracle.mn_contiguous(is_b, layout, t) == \
+            _storage_runs_along_mn(buf, layout, t, rows, cols, ld, is_b)
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_pack_block_structure_bruteforce(dtype):
     """Every (mn, k) <= 6, (MNT, KT) in {1..4}^2, both operands, all layouts/trans:
-    reshaping the packed buffer to (tiles, ksteps, KT, MNT) must expose op(X)
-    tile by tile, k-major, with zero fill outside op(X)."""
+    reshaping the packed buffer to (tiles, ksteps, KT, MNT) for operands stored along MN,
+    or (tiles, ksteps, MNT, KT) for operands stored along k, must expose op(X) tile by
+    tile with zero fill outside op(X)."""
     for mn, k, MNT, KT in itertools.product(range(0, 7), range(0, 7), range(1, 5), range(1, 5)):
         for layout, t, is_b in itertools.product([COL, ROW], ["N", "T"], [0, 1]):
             rows, cols = (k, mn) if is_b else (mn, k)
@@ -279,13 +295,17 @@ def test_pack_block_structure_bruteforce(dtype):
             assert out.size == nt * nk * MNT * KT
             if out.size == 0:
                 continue
-            blocks = out.reshape(nt, nk, KT, MNT)
             # op(X) oriented as (mn, k), zero padded to the tile grid
             opx = vals.T if is_b else vals
             padded = np.zeros((nt * MNT, nk * KT))
             padded[:mn, :k] = opx
-            expect = padded.reshape(nt, MNT, nk, KT).transpose(0, 2, 3, 1)
-            assert np.array_equal(blocks.astype(np.float64), expect)
+            tiles = padded.reshape(nt, MNT, nk, KT).transpose(0, 2, 1, 3)  # (nt, nk, MNT, KT)
+            mn_major = (layout == COL) != (t == "T") if not is_b else (layout == COL) == (t == "T")
+            if mn_major:
+                got = out.reshape(nt, nk, KT, MNT).transpose(0, 1, 3, 2)
+            else:
+                got = out.reshape(nt, nk, MNT, KT)
+            assert np.array_equal(got.astype(np.float64), tiles), (mn, k, MNT, KT, layout, t, is_b)
 
 
 def test_pack_is_a_bit_copy():
@@ -309,6 +329,10 @@ def test_unpack_of_pack_is_op():
         c = synth.make_case(layout, m, 1, k, t, "N", ld_pad=7, seed=int(g.integers(1 << 30)))
         out = oracle.pack(c.A, 0, layout, t, m, k, c.lda, MT, KT)
         nt, nk = -(-m // MT), -(-k // KT)
-        back = out.reshape(nt, nk, KT, MT).transpose(0, 3, 1, 2).reshape(nt * MT, nk * KT)
+        if _storage_runs_along_mn(c.A, layout, t, m, k, c.lda, 0):
+            blocks = out.reshape(nt, nk, KT, MT).transpose(0, 3, 1, 2)  # (nt, MT, nk, KT)
+        else:
+            blocks = out.reshape(nt, nk, MT, KT).transpose(0, 2, 1, 3)
+        back = blocks.reshape(nt * MT, nk * KT)
         assert np.array_equal(back[:m, :k], opv(c, "A"))
         assert not back[m:, :].any() and not back[:, k:].any()
