@@ -71,10 +71,6 @@ enum {
     /* 1: count per-chunk events (packed, read packed, read unpacked, polls)
        into the workspace's statistics block (a diagnostic; costs atomics). */
     FIP_ATTR_STATS = 4,
-    /* Polls a follower (a workgroup that packs nothing) may spend waiting for
-       a chunk its producer has not yet published before it reads the
-       unpacked operand instead.  0 = never wait.  Default 2000. */
-    FIP_ATTR_SPIN_LIMIT = 6,
     /* Tile order inside an XCD's run: 0 = GROUP_M tiles of a column
        consecutive, 1 = consecutive tiles in distinct columns.  Default 0. */
     FIP_ATTR_ORDER = 7,
@@ -91,7 +87,10 @@ enum {
 };
 
 enum {
-    FIP_PACK_AUTO = 0,         /* paper Sec. 3.3 reuse table */
+    FIP_PACK_AUTO = 0,         /* paper Sec. 3.3 reuse table, applied when the
+                                  launch has more tiles than fit on the device
+                                  at once (only then can a later pass reuse a
+                                  pack without waiting for it) */
     FIP_PACK_ALL = 1,          /* pack both operands whatever the shape */
     FIP_PACK_NONE = 2,         /* never pack (the unpacked "SUP" path, Sec. 2.3) */
     FIP_PACK_CONSUME_ONLY = 3, /* read only packed panels written beforehand by
@@ -127,10 +126,10 @@ typedef struct {
     int32_t a_kmajor, b_kmajor;/* packed block orientation: 1 = k-runs contiguous */
     int64_t a_pack_offset, a_copy_bytes;
     int64_t b_pack_offset, b_copy_bytes;
-    int64_t a_flag_offset, b_flag_offset;   /* uint64 [copies][tiles][ksteps] */
+    int64_t a_flag_offset, b_flag_offset;   /* uint64 [copies][tiles]: panel complete */
     int64_t a_claim_offset, b_claim_offset; /* uint64 [copies][tiles] */
-    int64_t stats_offset;      /* 4 x uint64: chunks packed, read packed, read
-                                  unpacked by followers, follower polls */
+    int64_t stats_offset;      /* 4 x uint64: chunks packed, chunks read packed,
+                                  chunks of packed panels read unpacked, re-polls */
     int64_t workspace_bytes;   /* bytes this call needs */
 } fip_plan_t;
 

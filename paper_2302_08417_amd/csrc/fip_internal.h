@@ -33,7 +33,6 @@ struct LaunchDesc {
     int mode;              // Mode
     int pack_a, pack_b;    // fused mode: operand packed on first touch
     int no_publish, stats;
-    int spin_limit;        // follower polls per chunk before reading unpacked
     int order;             // tile order inside an XCD's run (0 grouped, 1 rounds)
     int stagger;           // k-loop start offset by tile row
     int64_t M, N, K;
@@ -44,7 +43,7 @@ struct LaunchDesc {
     // workspace pieces (device pointers; null when unused)
     void* apack; int64_t apack_copy_elems;
     void* bpack; int64_t bpack_copy_elems;
-    uint64_t* aflag; uint64_t* bflag;   // [copies][tiles][ksteps]
+    uint64_t* aflag; uint64_t* bflag;   // panel complete: [copies][tiles]
     uint64_t* aclaim; uint64_t* bclaim; // [copies][tiles]
     unsigned long long* stats_ptr;      // 4 counters
     uint64_t epoch;                     // unique per fused call in this process

@@ -41,7 +41,6 @@ struct fip_handle_s {
     int tile_override;
     int no_publish;
     int stats;
-    int spin_limit;
     int order;
     int stagger;
     void* ws;
@@ -83,6 +82,14 @@ KernelShape kernel_shape(int layout, int64_t m, int64_t n)
 {
     if (layout == FIP_ROW_MAJOR) return {n, m, true};
     return {m, n, false};
+}
+
+// Workgroups of one tile class that fit on the device at once (256 CUs times
+// the per-CU residency the kernels' LDS and register use allow: about 2, 4 and
+// 6 for the 128, 64 and 32 tiles).
+int64_t resident_tiles(int cls)
+{
+    return 256 * (cls == 0 ? 2 : cls == 1 ? 4 : 6);
 }
 
 // Tile class: the largest C tile that still gives the 256 CUs about one tile
@@ -137,8 +144,13 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
         } else {
             // Paper Sec. 3.3: pack A's panel only if several tile columns of C
             // reuse it (n > n_R), B's panel only if several tile rows do (m > m_R).
-            pl->kpack_a = pl->tilesKN > 1;
-            pl->kpack_b = pl->tilesKM > 1;
+            // On the GPU the tiles of one launch run concurrently: a later pass
+            // can read a packed panel without waiting only if it starts after
+            // the first pass finished, i.e. when the launch has more tiles than
+            // fit on the device at once.  Otherwise nobody could reuse the pack.
+            const bool later_passes = pl->tilesKM * pl->tilesKN > resident_tiles(cls);
+            pl->kpack_a = pl->tilesKN > 1 && later_passes;
+            pl->kpack_b = pl->tilesKM > 1 && later_passes;
         }
         if (pl->kpack_a || pl->kpack_b) copies = fip::kCopies;
     }
@@ -146,8 +158,8 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
 
     int64_t off = 0;
     pl->off_stats = off; off = align256(off + 4 * 8);
-    pl->off_aflag = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * pl->nK * 8 : 0));
-    pl->off_bflag = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * pl->nK * 8 : 0));
+    pl->off_aflag = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * 8 : 0));
+    pl->off_bflag = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * 8 : 0));
     pl->off_aclaim = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * 8 : 0));
     pl->off_bclaim = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * 8 : 0));
     pl->apack_copy_elems = pl->kpack_a ? pl->tilesKM * pl->nK * KT * MT : 0;
@@ -305,7 +317,6 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.pack_a = pl.kpack_a; d.pack_b = pl.kpack_b;
         d.no_publish = h->no_publish;
         d.stats = h->stats;
-        d.spin_limit = h->spin_limit;
         d.order = h->order;
         d.stagger = h->stagger;
         d.M = ks.M; d.N = ks.N; d.K = k;
@@ -342,7 +353,6 @@ int fip_create(fip_handle_t* handle)
     h->stream = nullptr;
     h->policy = FIP_PACK_AUTO;
     h->tile_override = -1;
-    h->spin_limit = 2000;
     h->order = 0;
     *handle = h;
     return 0;
@@ -383,10 +393,6 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
         if (value != 0 && value != 1) return 3;
         handle->stats = (int)value;
         return 0;
-    case FIP_ATTR_SPIN_LIMIT:
-        if (value < 0 || value > (1 << 24)) return 3;
-        handle->spin_limit = (int)value;
-        return 0;
     case FIP_ATTR_ORDER:
         if (value != 0 && value != 1) return 3;
         handle->order = (int)value;
@@ -409,7 +415,6 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_TILE: *value = handle->tile_override; return 0;
     case FIP_ATTR_NO_PUBLISH: *value = handle->no_publish; return 0;
     case FIP_ATTR_STATS: *value = handle->stats; return 0;
-    case FIP_ATTR_SPIN_LIMIT: *value = handle->spin_limit; return 0;
     case FIP_ATTR_ORDER: *value = handle->order; return 0;
     case FIP_ATTR_STAGGER: *value = handle->stagger; return 0;
     case FIP_ATTR_EPOCH: *value = (int64_t)handle->epoch; return 0;

@@ -34,8 +34,14 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Types;
-template <> struct Types<double> { typedef d2 vec; typedef d4 acc; static constexpr int VEC = 2; };
-template <> struct Types<float> { typedef f4 vec; typedef f4 acc; static constexpr int VEC = 4; };
+// vec: 16-byte vector (16-byte aligned); uvec: the same vector with only
+// element alignment, for unpacked operands whose leading dimension or base is
+// not a multiple of 16 bytes (gfx950 global loads accept dword-aligned
+// multi-dword accesses, so this is still one 16-byte load).
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+template <> struct Types<double> { typedef d2 vec; typedef d2u uvec; typedef d4 acc; static constexpr int VEC = 2; };
+template <> struct Types<float> { typedef f4 vec; typedef f4u uvec; typedef f4 acc; static constexpr int VEC = 4; };
 
 // One 16x16x4 MFMA on fragments a (lane l: A[i = l%16][k = l/16]) and b (lane l:
 // B[k = l/16][j = l%16]) of a 16x16 C block.  Output layouts differ by type:
@@ -83,7 +89,6 @@ struct Params {
     int mode, pack_a, pack_b, no_publish, do_stats;
     int a_vec, b_vec, c_vec;
     int a_fast, b_fast;  // interior chunks may use the 32-bit-offset vector loader
-    int spin_limit;  // polls a follower spends waiting for a publish flag (0: never wait)
     int order;       // tile order inside an XCD's run: 0 grouped, 1 column-distinct rounds
     int stagger;     // 1: start the k-loop of tile row tm at chunk (tm % 8) * nK / 8
 };
@@ -141,18 +146,24 @@ struct Chunk {
     }
     __device__ __forceinline__ void load_fast(const T* __restrict__ origin, const uint32_t* off)
     {
+        typedef typename Types<T>::uvec U;
         const char* base = reinterpret_cast<const char*>(origin);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) r[i] = *reinterpret_cast<const V*>(base + off[i]);
+        for (int i = 0; i < NV; ++i) {
+            const U u = *reinterpret_cast<const U*>(base + off[i]);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) r[i][e] = u[e];
+        }
     }
 
     // Unpacked source, fringe chunk (Sec. 2.2 zero padding done in registers):
-    // elements outside the MN x K operand read as +0.0; vector loads only where
-    // a whole aligned vector exists.
+    // elements outside the MN x K operand read as +0.0; one vector load where
+    // the whole vector exists, element loads otherwise.
     __device__ __forceinline__ void load_edge(const T* __restrict__ X, int64_t ld, int64_t MN,
                                               int64_t K, int64_t x0, int64_t p0, bool vec_ok,
                                               int tid)
     {
+        typedef typename Types<T>::uvec U;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int o = elem_o(i, tid);
@@ -160,7 +171,9 @@ struct Chunk {
             if (!KC) {
                 const T* src = X + x + p * ld;
                 if (vec_ok && p < K && x + VEC <= MN) {
-                    r[i] = *reinterpret_cast<const V*>(src);
+                    const U u = *reinterpret_cast<const U*>(src);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) r[i][e] = u[e];
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) r[i][e] = (p < K && x + e < MN) ? src[e] : T(0);
@@ -168,7 +181,9 @@ struct Chunk {
             } else {
                 const T* src = X + x * ld + p;
                 if (vec_ok && x < MN && p + VEC <= K) {
-                    r[i] = *reinterpret_cast<const V*>(src);
+                    const U u = *reinterpret_cast<const U*>(src);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) r[i][e] = u[e];
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) r[i][e] = (x < MN && p + e < K) ? src[e] : T(0);
@@ -266,7 +281,6 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     __shared__ __attribute__((aligned(16))) T sA[2][ChA::LDS_ELEMS];
     __shared__ __attribute__((aligned(16))) T sB[2][ChB::LDS_ELEMS];
     __shared__ int s_role;
-    __shared__ int s_src[2];  // per chunk parity: bit 0 A packed, bit 1 B packed
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -303,22 +317,10 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     T* bpanel = nullptr;
     if (useA || consume) apanel = P.apack + (int64_t)copy * P.apack_copy + (int64_t)tm * nK * KT * MT;
     if (useB || consume) bpanel = P.bpack + (int64_t)copy * P.bpack_copy + (int64_t)tn * nK * KT * NT;
-    uint64_t* aflags = useA ? P.aflag + ((int64_t)copy * P.tilesM + tm) * nK : nullptr;
-    uint64_t* bflags = useB ? P.bflag + ((int64_t)copy * P.tilesN + tn) * nK : nullptr;
+    // One completion flag and one claim per (copy, panel).
+    uint64_t* adone = useA ? P.aflag + (int64_t)copy * P.tilesM + tm : nullptr;
+    uint64_t* bdone = useB ? P.bflag + (int64_t)copy * P.tilesN + tn : nullptr;
 
-    // Thread 0 decides, for the whole workgroup, where each chunk comes from
-    // (packed copy or unpacked operand) and broadcasts it through LDS behind
-    // the next barrier.  The decision must be workgroup-uniform: for an operand
-    // contiguous along k the two sources are staged by different
-    // thread-to-element assignments, so waves that chose differently would
-    // each fill a different part of the LDS tile.
-    //
-    // A producer never waits.  A workgroup that produces nothing ("follower")
-    // may wait a bounded number of polls for a chunk its producer has not yet
-    // published (the paper's "one synchronization", Sec. 3.5): the producer is
-    // resident (it claimed the panel at its start) and never waits itself, so
-    // the wait cannot form a cycle, and after spin_limit polls the follower
-    // reads the unpacked operand instead.  Either way the bits are the same.
     // Logical k-step q works on chunk c(q) = (q + rot) mod nK.  With
     // staggering, tiles of different tile rows start their k-loops at
     // different chunks (rot depends on the tile row only, so tiles sharing an
@@ -328,10 +330,13 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         const int c = q + rot;
         return c >= nK ? c - nK : c;
     };
-    auto flag_of = [&](const uint64_t* flags, int c) -> uint64_t {
-        return __hip_atomic_load(flags + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    auto load_flag = [&](const uint64_t* f) -> uint64_t {
+        return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
 
+    // First touch claims a panel (Sec. 3.2: the first pass packs it).  The role
+    // must be workgroup-uniform because every thread stores its share of each
+    // packed chunk, so thread 0 claims and broadcasts.
     if (tid == 0) {
         int role = 0;
         if (useA && __hip_atomic_exchange(P.aclaim + copy * P.tilesM + tm, epoch, __ATOMIC_RELAXED,
@@ -346,66 +351,24 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     const bool prodA = s_role & 1, prodB = s_role & 2;
     const bool producer = prodA || prodB;
     const bool wantA = useA && !prodA, wantB = useB && !prodB;  // would read a packed copy
-    const bool follower = !producer && (wantA || wantB);
 
-    // Wave 0 decides, for the whole workgroup, where each chunk comes from
-    // (packed copy or unpacked operand) and broadcasts it through LDS behind
-    // the next barrier.  The decision must be workgroup-uniform: for an operand
-    // contiguous along k the two sources are staged by different
-    // thread-to-element assignments, so waves that chose differently would
-    // each fill a different part of the LDS tile.
-    //
-    // Wave 0 keeps, per operand, the first logical step not yet known to be
-    // published (flags only ever go from unpublished to published within a
-    // call, so this knowledge never goes stale).  One poll reads the flags of
-    // the next 8 unknown steps at once (lanes 0-7 for A, 8-15 for B).
-    //
-    // A producer never waits.  A follower (it produces nothing) may wait a
-    // bounded number of polls for a chunk its producer has not yet published
-    // (the paper's "one synchronization", Sec. 3.5): the producer is resident
-    // (it claimed the panel at its start) and never waits itself, so the wait
-    // cannot form a cycle, and after spin_limit polls the follower reads the
-    // unpacked operand instead.  Either way the bits are the same.
-    int knownA = 0, knownB = 0;
-    uint64_t pf = 0;
-    auto poll_issue = [&]() {  // wave 0
-        pf = epoch;
-        if (lane < 8) {
-            const int q = knownA + lane;
-            if (wantA && q < nK) pf = flag_of(aflags, chunk_of(q));
-        } else if (lane < 16) {
-            const int q = knownB + lane - 8;
-            if (wantB && q < nK) pf = flag_of(bflags, chunk_of(q));
-        }
-    };
-    auto poll_absorb = [&]() {  // wave 0
-        const uint64_t ok = __ballot(pf == epoch);
-        knownA += __builtin_ctzll(~(ok & 0xFFull) | 0x100ull);
-        knownB += __builtin_ctzll(~((ok >> 8) & 0xFFull) | 0x100ull);
-    };
-    unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_wait = 0;
-    // wave 0; polled: poll_issue() was called for this step (absorb it exactly once)
-    auto decide = [&](int q, bool polled) -> int {
-        if (consume) return 3;
-        if (polled) poll_absorb();
-        if (follower) {
-            int polls = 0;
-            while (((wantA && q >= knownA) || (wantB && q >= knownB)) && polls < P.spin_limit) {
-                __builtin_amdgcn_s_sleep(1);
-                poll_issue();
-                poll_absorb();
-                ++polls;
-            }
-            n_wait += polls;
-        }
-        return (wantA && q < knownA ? 1 : 0) | (wantB && q < knownB ? 2 : 0);
-    };
-    auto need_poll = [&](int q) -> bool { return (wantA && q >= knownA) || (wantB && q >= knownB); };
+    // Later passes (Sec. 3.1) read the packed copy once its producer has
+    // published the whole panel.  Packed and unpacked sources stage the same
+    // elements into the same LDS places (same thread-to-element mapping), so
+    // each wave decides for itself, from its own flag reads: at the tile start,
+    // then again every REPOLL k-steps while still unpacked.  Nobody waits.
+    constexpr int REPOLL = 16;
+    bool apk = consume, bpk = consume;
+    uint64_t fa = 0, fb = 0;
+    if (wantA) fa = load_flag(adone);
+    if (wantB) fb = load_flag(bdone);
+    apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
+    bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
 
+    unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_polls = 0;
     ChA ra;
     ChB rb;
-    auto load_chunks = [&](int q, int src) {
-        const bool apk = src & 1, bpk = src & 2;
+    auto load_chunks = [&](int q) {
         const int c = chunk_of(q);
         const int64_t p0 = (int64_t)c * KT;
         const bool kin = p0 + KT <= P.K;
@@ -417,7 +380,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         else rb.load_edge(P.B, ldb, P.N, P.K, x0b, p0, P.b_vec, tid);
         if (P.do_stats && tid == 0) {
             n_prod += (int)prodA + (int)prodB;
-            n_pk += (int)apk + (int)bpk;
+            n_pk += (int)(wantA && apk) + (int)(wantB && bpk) + (consume ? 2 : 0);
             n_unpk += (int)(wantA && !apk) + (int)(wantB && !bpk);
         }
     };
@@ -428,43 +391,31 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
 
-    // Prologue: decide chunk 0, stage it; decide chunk 1.
-    if (wave == 0) {
-        const bool polled = need_poll(0);
-        if (polled) poll_issue();
-        const int src = decide(0, polled);
-        if (lane == 0) s_src[0] = src;
-    }
-    __syncthreads();
-    {
-        const int src = s_src[0];
-        const bool polled1 = wave == 0 && nK > 1 && need_poll(1);
-        if (polled1) poll_issue();
-        load_chunks(0, src);
-        ra.store_lds(sA[0], tid);
-        rb.store_lds(sB[0], tid);
-        if (prodA) ra.store_pack(apanel + (int64_t)chunk_of(0) * KT * MT, tid);
-        if (prodB) rb.store_pack(bpanel + (int64_t)chunk_of(0) * KT * NT, tid);
-        if (wave == 0 && nK > 1) {
-            const int src1 = decide(1, polled1);
-            if (lane == 0) s_src[1] = src1;
-        }
-    }
+    // Prologue: stage chunk c(0).
+    load_chunks(0);
+    ra.store_lds(sA[0], tid);
+    rb.store_lds(sB[0], tid);
+    if (prodA) ra.store_pack(apanel + (int64_t)chunk_of(0) * KT * MT, tid);
+    if (prodB) rb.store_pack(bpanel + (int64_t)chunk_of(0) * KT * NT, tid);
     __syncthreads();
 
+    bool polling = false;
     for (int q = 0; q < nK; ++q) {
         const int cur = q & 1;
         const bool more = q + 1 < nK;
-        // Wave 0 polls for step q+2 first; the answer is needed only after this
-        // step's MFMAs.
-        const bool decide_next = wave == 0 && q + 2 < nK;
-        const bool polled = decide_next && need_poll(q + 2);
-        if (polled) poll_issue();
-        int src = 0;
-        if (more) {
-            src = s_src[(q + 1) & 1];  // decided before the previous barrier
-            load_chunks(q + 1, src);
+        // Re-poll (asynchronously: the answer is used one step later).
+        if (polling) {
+            apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
+            bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+            polling = false;
         }
+        if (((wantA && !apk) || (wantB && !bpk)) && q % REPOLL == REPOLL - 1) {
+            if (wantA && !apk) fa = load_flag(adone);
+            if (wantB && !bpk) fb = load_flag(bdone);
+            polling = true;
+            if (P.do_stats && tid == 0) ++n_polls;
+        }
+        if (more) load_chunks(q + 1);
         // MFMAs on chunk c(q).  Fragment element (row x, k-row kr) of either
         // orientation: lane l supplies x = base + l%16, kr = 4s + l/16.
         const T* la = sA[cur] + ChA::lds_at(wm * WTM + (lane & 15), lane >> 4);
@@ -481,26 +432,24 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 #pragma unroll
                 for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(af[a], bf[b], acc[a][b]);
         }
-        // Pack stores of chunk c(q) (issued one step earlier) must be complete
-        // before it is published below.
-        if (producer) wait_all_memory();
         if (more) {
             ra.store_lds(sA[cur ^ 1], tid);
             rb.store_lds(sB[cur ^ 1], tid);
             if (prodA) ra.store_pack(apanel + (int64_t)chunk_of(q + 1) * KT * MT, tid);
             if (prodB) rb.store_pack(bpanel + (int64_t)chunk_of(q + 1) * KT * NT, tid);
         }
-        // s_src[q & 1] was last read at the top of iteration q-1, before the
-        // previous barrier, so it is free for step q+2.
-        if (decide_next) {
-            const int src2 = decide(q + 2, polled);
-            if (lane == 0) s_src[q & 1] = src2;
-        }
         __syncthreads();
-        if (tid == 0 && producer && !P.no_publish) {
-            const int c = chunk_of(q);
-            if (prodA) __hip_atomic_store(aflags + c, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (prodB) __hip_atomic_store(bflags + c, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    // The producer publishes its panel once every pack store of it has
+    // completed (the XCD's L2 has acknowledged them; consumers of this copy
+    // run on the same XCD and read through that L2).
+    if (producer) {
+        wait_all_memory();
+        __syncthreads();
+        if (tid == 0 && !P.no_publish) {
+            if (prodA) __hip_atomic_store(adone, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prodB) __hip_atomic_store(bdone, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 
@@ -508,7 +457,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         atomicAdd(P.stats + 0, n_prod);
         atomicAdd(P.stats + 1, n_pk);
         atomicAdd(P.stats + 2, n_unpk);
-        atomicAdd(P.stats + 3, n_wait);
+        atomicAdd(P.stats + 3, n_polls);
     }
 
     // Epilogue: C = alpha*acc + beta*C (C not read when beta == 0).
@@ -637,8 +586,10 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
     const int64_t a_far = d.a_kmajor ? d.a_smn : d.a_sk;  // the leading dimension
     const int64_t b_far = d.b_kmajor ? d.b_smn : d.b_sk;
-    P.a_vec = aligned16(d.A) && a_far % VEC == 0;
-    P.b_vec = aligned16(d.B) && b_far % VEC == 0;
+    // unpacked vector loads need only element alignment (see Types::uvec)
+    P.a_vec = ((uintptr_t)d.A % sizeof(T)) == 0;
+    P.b_vec = ((uintptr_t)d.B % sizeof(T)) == 0;
+    (void)a_far; (void)b_far;
     P.c_vec = aligned16(d.C) && d.ldc % VEC == 0;
     // byte offsets inside one chunk must fit in 32 bits: (MT + KT*ld) elements
     // for an MN-contiguous operand, (MT*ld + KT) for a k-contiguous one
@@ -646,7 +597,6 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     const int64_t b_span = (d.b_kmajor ? NT * b_far + KT : NT + KT * b_far) * (int64_t)sizeof(T);
     P.a_fast = P.a_vec && a_span < ((int64_t)1 << 31);
     P.b_fast = P.b_vec && b_span < ((int64_t)1 << 31);
-    P.spin_limit = d.spin_limit;
     P.order = d.order;
     P.stagger = d.stagger;
     return P;

@@ -102,15 +102,27 @@ def plan(h, m, n, k, layout=0, dtype=F.FIP_F64, policy=F.FIP_PACK_AUTO, tile=-1,
 
 
 def test_pack_table_of_the_paper(h):
-    """Sec. 3.3: n <= n_R -> do not pack A; m <= m_R -> do not pack B (tile = MT x NT)."""
-    for tile, T in [(0, 128), (1, 64), (2, 32)]:
-        for m, n, pa, pb in [(T, T, 0, 0), (T, T + 1, 1, 0), (T + 1, T, 0, 1), (5 * T, 3 * T, 1, 1)]:
+    """Sec. 3.3: n <= n_R -> do not pack A; m <= m_R -> do not pack B (tile = MT x NT),
+    applied to launches with more tiles than fit on the device at once."""
+    for tile, T, slots in [(0, 128, 512), (1, 64, 1024), (2, 32, 1536)]:
+        big = (slots + 1) * T  # one tile row or column that alone needs several rounds
+        for m, n, pa, pb in [(T, T, 0, 0), (T, big, 1, 0), (big, T, 0, 1),
+                             (40 * T, 40 * T, 1, 1)]:
             for layout in (0, 1):
                 p = plan(h, m, n, 64, layout=layout, tile=tile)
                 assert (p.pack_a, p.pack_b) == (pa, pb), (tile, m, n, layout)
                 assert p.MT == T and p.NT == T
                 if not pa and not pb:
                     assert p.workspace_bytes == 0 and p.copies == 0
+
+
+def test_single_round_launches_do_not_pack(h):
+    # every tile is resident at once: no later pass could reuse a pack
+    for tile, T in [(0, 128), (1, 64), (2, 32)]:
+        p = plan(h, 5 * T, 3 * T, 64, tile=tile)
+        assert (p.pack_a, p.pack_b) == (0, 0)
+        q = plan(h, 5 * T, 3 * T, 64, tile=tile, policy=F.FIP_PACK_ALL)
+        assert (q.pack_a, q.pack_b) == (1, 1)
 
 
 def test_plan_layout_and_sizes(h):
