@@ -160,6 +160,9 @@ def main():
                     help="comma-separated sizes for the sweep (default: 16..8192 powers of two)")
     ap.add_argument("--sweep-dtypes", default="f64,f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (3 times), to "
+                         "calibrate HBM byte counters against a kernel of known traffic")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -175,6 +178,17 @@ def main():
         sys.exit(1)
     from paper_2302_08417_amd import fipgemm as F
     from paper_2302_08417_amd import synth
+
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "reads": args.copy_probe,
+                          "writes": args.copy_probe}), flush=True)
+        return
 
     n, dt = args.size, args.dtype
     log(f"[bench] headline: fused-pack {dt} gemm m=n=k={n}")

@@ -74,12 +74,6 @@ enum {
     /* Tile order inside an XCD's run: 0 = GROUP_M tiles of a column
        consecutive, 1 = consecutive tiles in distinct columns.  Default 0. */
     FIP_ATTR_ORDER = 7,
-    /* 1: tile row t starts its k-loop at k-step (t % 8) * ceil(k/KT) / 8 and
-       wraps around, so tile rows read different k-ranges at any moment.  The
-       order depends only on the tile, and is used by every pack policy, so
-       results stay identical across policies; it does change the summation
-       order relative to 0.  Default 0. */
-    FIP_ATTR_STAGGER = 8,
     /* Read only: the 64-bit epoch stamp of the most recent fused call
        (claims and publish flags of that call hold this value; stamps are
        unique within the process). */

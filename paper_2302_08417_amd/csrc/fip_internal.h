@@ -34,7 +34,6 @@ struct LaunchDesc {
     int pack_a, pack_b;    // fused mode: operand packed on first touch
     int no_publish, stats;
     int order;             // tile order inside an XCD's run (0 grouped, 1 rounds)
-    int stagger;           // k-loop start offset by tile row
     int64_t M, N, K;
     const void* A; int64_t a_smn, a_sk; int a_kmajor;
     const void* B; int64_t b_smn, b_sk; int b_kmajor;

@@ -42,7 +42,6 @@ struct fip_handle_s {
     int no_publish;
     int stats;
     int order;
-    int stagger;
     void* ws;
     size_t ws_bytes;
     uint64_t epoch;   // stamp of the most recent fused call
@@ -318,7 +317,6 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.no_publish = h->no_publish;
         d.stats = h->stats;
         d.order = h->order;
-        d.stagger = h->stagger;
         d.M = ks.M; d.N = ks.N; d.K = k;
         fill_operands(pl, layout, A, lda, tA, B, ldb, tB, &d);
         d.C = C; d.ldc = ldc;
@@ -397,10 +395,6 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
         if (value != 0 && value != 1) return 3;
         handle->order = (int)value;
         return 0;
-    case FIP_ATTR_STAGGER:
-        if (value != 0 && value != 1) return 3;
-        handle->stagger = (int)value;
-        return 0;
     default:
         return 2;
     }
@@ -416,7 +410,6 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_NO_PUBLISH: *value = handle->no_publish; return 0;
     case FIP_ATTR_STATS: *value = handle->stats; return 0;
     case FIP_ATTR_ORDER: *value = handle->order; return 0;
-    case FIP_ATTR_STAGGER: *value = handle->stagger; return 0;
     case FIP_ATTR_EPOCH: *value = (int64_t)handle->epoch; return 0;
     default: return 2;
     }

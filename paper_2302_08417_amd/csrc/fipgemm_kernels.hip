@@ -59,6 +59,18 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// alpha*x + beta*y with one fixed rounding sequence (alpha*x rounded, then one
+// fused multiply-add), written out so that no tile shape's code generation can
+// contract it differently: every kernel variant then rounds C identically.
+__device__ __forceinline__ double axpby(double alpha, double x, double beta, double y)
+{
+    return __builtin_fma(beta, y, alpha * x);
+}
+__device__ __forceinline__ float axpby(float alpha, float x, float beta, float y)
+{
+    return __builtin_fmaf(beta, y, alpha * x);
+}
+
 // Hardware id of the XCD (XCC) running this wave: hwreg XCC_ID, bits [3:0].
 __device__ __forceinline__ unsigned xcc_id()
 {
@@ -90,7 +102,6 @@ struct Params {
     int a_vec, b_vec, c_vec;
     int a_fast, b_fast;  // interior chunks may use the 32-bit-offset vector loader
     int order;       // tile order inside an XCD's run: 0 grouped, 1 column-distinct rounds
-    int stagger;     // 1: start the k-loop of tile row tm at chunk (tm % 8) * nK / 8
 };
 
 // LDS pitch of an MN-major tile ([k][mn]): the tile extent plus padding so
@@ -143,6 +154,16 @@ struct Chunk {
         const int o = elem_o(i, tid);
         const int64_t x = x_of(o), p = p_of(o);
         return (uint32_t)((KC ? x * ld + p : x + p * ld) * (int64_t)sizeof(T));
+    }
+    __device__ __forceinline__ void load_at(const char* __restrict__ base, const uint32_t* off)
+    {
+        typedef typename Types<T>::uvec U;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const U u = *reinterpret_cast<const U*>(base + off[i]);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) r[i][e] = u[e];
+        }
     }
     __device__ __forceinline__ void load_fast(const T* __restrict__ origin, const uint32_t* off)
     {
@@ -247,24 +268,6 @@ __device__ __forceinline__ void tile_coords(int w, int tilesM, int tilesN, int g
     }
 }
 
-template <typename T, int NTHR>
-__device__ __forceinline__ void load4(const T* p, bool vec, T out[4])
-{
-    typedef typename Types<T>::vec V;
-    constexpr int VEC = Types<T>::VEC;
-    if (vec) {
-#pragma unroll
-        for (int h = 0; h < 4 / VEC; ++h) {
-            const V v = *reinterpret_cast<const V*>(p + h * VEC);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) out[h * VEC + e] = v[e];
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) out[e] = p[e];
-    }
-}
-
 template <typename T, int MT, int NT, int KT, int WM, int WN, bool AKC, bool BKC>
 __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P)
 {
@@ -288,20 +291,23 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     tile_coords(blockIdx.x, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
     const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * NT;
     const int nK = P.nK;
+    const int nKfull = (int)(P.K / KT);  // chunks with all KT k-values present
     const uint64_t epoch = P.epoch;
-    // Unpacked operands: the non-unit stride, and whether this tile lies fully
-    // inside (only the last k-step can then still be a fringe chunk).
+
+    // Unpacked operands: leading dimension, chunk origin and per-lane byte
+    // offsets of interior chunks (loop-invariant; the host guarantees they fit
+    // in 32 bits).  A tile is interior along MN when it lies fully inside.
     const int64_t lda = AKC ? P.a_smn : P.a_sk, ldb = BKC ? P.b_smn : P.b_sk;
     const bool a_in = P.a_fast && x0a + MT <= P.M, b_in = P.b_fast && x0b + NT <= P.N;
+    const char* a_org = reinterpret_cast<const char*>(P.A + (AKC ? x0a * lda : x0a));
+    const char* b_org = reinterpret_cast<const char*>(P.B + (BKC ? x0b * ldb : x0b));
+    const int64_t a_step = (AKC ? KT : KT * lda) * (int64_t)sizeof(T);  // bytes per chunk
+    const int64_t b_step = (BKC ? KT : KT * ldb) * (int64_t)sizeof(T);
     uint32_t a_off[ChA::NV], b_off[ChB::NV];
 #pragma unroll
     for (int i = 0; i < ChA::NV; ++i) a_off[i] = ChA::fast_offset(i, tid, lda);
 #pragma unroll
     for (int i = 0; i < ChB::NV; ++i) b_off[i] = ChB::fast_offset(i, tid, ldb);
-    // origin of the unpacked chunk (x0, p0): X + x0*s_mn + p0*s_k
-    const int64_t a_step = AKC ? KT : KT * lda, b_step = BKC ? KT : KT * ldb;
-    const T* a_org = P.A + (AKC ? x0a * lda : x0a);
-    const T* b_org = P.B + (BKC ? x0b * ldb : x0b);
 
     const bool consume = P.mode == kModeConsumePacked;
     bool fused = P.mode == kModeFused;
@@ -320,16 +326,6 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     // One completion flag and one claim per (copy, panel).
     uint64_t* adone = useA ? P.aflag + (int64_t)copy * P.tilesM + tm : nullptr;
     uint64_t* bdone = useB ? P.bflag + (int64_t)copy * P.tilesN + tn : nullptr;
-
-    // Logical k-step q works on chunk c(q) = (q + rot) mod nK.  With
-    // staggering, tiles of different tile rows start their k-loops at
-    // different chunks (rot depends on the tile row only, so tiles sharing an
-    // A panel stay in step, and the same order is used in every mode).
-    const int rot = P.stagger ? (int)(((int64_t)(tm & 7) * nK) >> 3) : 0;
-    auto chunk_of = [&](int q) -> int {
-        const int c = q + rot;
-        return c >= nK ? c - nK : c;
-    };
     auto load_flag = [&](const uint64_t* f) -> uint64_t {
         return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
@@ -355,29 +351,46 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     // Later passes (Sec. 3.1) read the packed copy once its producer has
     // published the whole panel.  Packed and unpacked sources stage the same
     // elements into the same LDS places (same thread-to-element mapping), so
-    // each wave decides for itself, from its own flag reads: at the tile start,
+    // each wave decides for itself from its own flag reads: at the tile start,
     // then again every REPOLL k-steps while still unpacked.  Nobody waits.
     constexpr int REPOLL = 16;
     bool apk = consume, bpk = consume;
-    uint64_t fa = 0, fb = 0;
-    if (wantA) fa = load_flag(adone);
-    if (wantB) fb = load_flag(bdone);
-    apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
-    bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+    {
+        const uint64_t fa = wantA ? load_flag(adone) : 0, fb = wantB ? load_flag(bdone) : 0;
+        apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
+        bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+    }
 
     unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_polls = 0;
     ChA ra;
     ChB rb;
-    auto load_chunks = [&](int q) {
-        const int c = chunk_of(q);
-        const int64_t p0 = (int64_t)c * KT;
-        const bool kin = p0 + KT <= P.K;
-        if (apk) ra.load_packed(apanel + (int64_t)c * KT * MT, tid);
-        else if (a_in && kin) ra.load_fast(a_org + c * a_step, a_off);
-        else ra.load_edge(P.A, lda, P.M, P.K, x0a, p0, P.a_vec, tid);
-        if (bpk) rb.load_packed(bpanel + (int64_t)c * KT * NT, tid);
-        else if (b_in && kin) rb.load_fast(b_org + c * b_step, b_off);
-        else rb.load_edge(P.B, ldb, P.N, P.K, x0b, p0, P.b_vec, tid);
+    // Packed chunks and interior unpacked chunks are read by one and the same
+    // vector-load sequence: only the base pointer and the per-lane offsets
+    // differ (packed element o sits o*sizeof(T) bytes into its chunk).
+    auto load_chunks = [&](int c) {
+        const bool kin = c < nKfull;
+        if (apk || (a_in && kin)) {
+            const char* base = apk ? reinterpret_cast<const char*>(apanel + (int64_t)c * KT * MT)
+                                   : a_org + (int64_t)c * a_step;
+            uint32_t off[ChA::NV];
+#pragma unroll
+            for (int i = 0; i < ChA::NV; ++i)
+                off[i] = apk ? (uint32_t)(ChA::elem_o(i, tid) * sizeof(T)) : a_off[i];
+            ra.load_at(base, off);
+        } else {
+            ra.load_edge(P.A, lda, P.M, P.K, x0a, (int64_t)c * KT, P.a_vec, tid);
+        }
+        if (bpk || (b_in && kin)) {
+            const char* base = bpk ? reinterpret_cast<const char*>(bpanel + (int64_t)c * KT * NT)
+                                   : b_org + (int64_t)c * b_step;
+            uint32_t off[ChB::NV];
+#pragma unroll
+            for (int i = 0; i < ChB::NV; ++i)
+                off[i] = bpk ? (uint32_t)(ChB::elem_o(i, tid) * sizeof(T)) : b_off[i];
+            rb.load_at(base, off);
+        } else {
+            rb.load_edge(P.B, ldb, P.N, P.K, x0b, (int64_t)c * KT, P.b_vec, tid);
+        }
         if (P.do_stats && tid == 0) {
             n_prod += (int)prodA + (int)prodB;
             n_pk += (int)(wantA && apk) + (int)(wantB && bpk) + (consume ? 2 : 0);
@@ -391,32 +404,28 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
 
-    // Prologue: stage chunk c(0).
+    // Prologue: stage chunk 0.
     load_chunks(0);
     ra.store_lds(sA[0], tid);
     rb.store_lds(sB[0], tid);
-    if (prodA) ra.store_pack(apanel + (int64_t)chunk_of(0) * KT * MT, tid);
-    if (prodB) rb.store_pack(bpanel + (int64_t)chunk_of(0) * KT * NT, tid);
+    if (prodA) ra.store_pack(apanel, tid);
+    if (prodB) rb.store_pack(bpanel, tid);
     __syncthreads();
 
-    bool polling = false;
     for (int q = 0; q < nK; ++q) {
         const int cur = q & 1;
         const bool more = q + 1 < nK;
-        // Re-poll (asynchronously: the answer is used one step later).
-        if (polling) {
-            apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
-            bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
-            polling = false;
-        }
-        if (((wantA && !apk) || (wantB && !bpk)) && q % REPOLL == REPOLL - 1) {
+        // Re-poll while an operand is still read unpacked.  The flag load is
+        // issued before this step's chunk loads and read after them, when the
+        // loads have been waited for anyway.
+        const bool poll = ((wantA && !apk) || (wantB && !bpk)) && q % REPOLL == REPOLL - 1;
+        uint64_t fa = 0, fb = 0;
+        if (poll) {
             if (wantA && !apk) fa = load_flag(adone);
             if (wantB && !bpk) fb = load_flag(bdone);
-            polling = true;
-            if (P.do_stats && tid == 0) ++n_polls;
         }
         if (more) load_chunks(q + 1);
-        // MFMAs on chunk c(q).  Fragment element (row x, k-row kr) of either
+        // MFMAs on chunk q.  Fragment element (row x, k-row kr) of either
         // orientation: lane l supplies x = base + l%16, kr = 4s + l/16.
         const T* la = sA[cur] + ChA::lds_at(wm * WTM + (lane & 15), lane >> 4);
         const T* lb = sB[cur] + ChB::lds_at(wn * WTN + (lane & 15), lane >> 4);
@@ -435,8 +444,13 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         if (more) {
             ra.store_lds(sA[cur ^ 1], tid);
             rb.store_lds(sB[cur ^ 1], tid);
-            if (prodA) ra.store_pack(apanel + (int64_t)chunk_of(q + 1) * KT * MT, tid);
-            if (prodB) rb.store_pack(bpanel + (int64_t)chunk_of(q + 1) * KT * NT, tid);
+            if (prodA) ra.store_pack(apanel + (int64_t)(q + 1) * KT * MT, tid);
+            if (prodB) rb.store_pack(bpanel + (int64_t)(q + 1) * KT * NT, tid);
+        }
+        if (poll) {  // takes effect from chunk q+2 on
+            apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
+            bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+            if (P.do_stats && tid == 0) ++n_polls;
         }
         __syncthreads();
     }
@@ -460,62 +474,71 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         atomicAdd(P.stats + 3, n_polls);
     }
 
-    // Epilogue: C = alpha*acc + beta*C (C not read when beta == 0).
+    // Epilogue: C = alpha*acc + beta*C (C not read when beta == 0).  Lane l of
+    // block (a, b) holds C elements (row r0 + di(l, r), column c0 + dj(l, r)),
+    // r = 0..3 (see mfma16).  Interior tiles read all of their C first, then
+    // write it back, with no masks.
     const T alpha = P.alpha, beta = P.beta;
+    const bool c_in = x0a + MT <= P.M && x0b + NT <= P.N;
+    auto di = [&](int r) -> int { return sizeof(T) == 8 ? (lane & 15) : 4 * (lane >> 4) + r; };
+    auto dj = [&](int r) -> int { return sizeof(T) == 8 ? 4 * r + (lane >> 4) : (lane & 15); };
+    const int64_t r0w = x0a + wm * WTM, c0w = x0b + wn * WTN;
+    if (c_in) {
+        // one block row at a time: all of its C loads are issued before any
+        // use, without holding a second full accumulator's worth of registers
 #pragma unroll
-    for (int a = 0; a < FM; ++a) {
+        for (int a = 0; a < FM; ++a) {
+            T cv[FN][4];
+            if (beta != T(0)) {
 #pragma unroll
-        for (int b = 0; b < FN; ++b) {
-            const int64_t r0 = x0a + wm * WTM + a * 16, c0 = x0b + wn * WTN + b * 16;
-            if constexpr (sizeof(T) == 8) {
-                // lane holds row r0 + l%16, columns c0 + 4*r + l/16
-                const int64_t i = r0 + (lane & 15);
-                if (i >= P.M) continue;
+                for (int b = 0; b < FN; ++b) {
+                    const T* cb = P.C + (r0w + a * 16) + (c0w + b * 16) * P.ldc;
+                    if constexpr (sizeof(T) == 8) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t j = c0 + 4 * r + (lane >> 4);
-                    if (j >= P.N) continue;
-                    T* cp = P.C + i + j * P.ldc;
-                    T v = alpha * acc[a][b][r];
-                    if (beta != T(0)) v = v + beta * *cp;
-                    *cp = v;
+                        for (int r = 0; r < 4; ++r) cv[b][r] = cb[di(r) + (int64_t)dj(r) * P.ldc];
+                    } else {
+                        typedef typename Types<T>::uvec U;
+                        const U u = *reinterpret_cast<const U*>(cb + di(0) + (int64_t)dj(0) * P.ldc);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) cv[b][r] = u[r];
+                    }
                 }
-            } else {
-                // lane holds column c0 + l%16, rows r0 + 4*(l/16) .. +3
-                const int64_t i0 = r0 + 4 * (lane >> 4);
-                const int64_t j = c0 + (lane & 15);
-                if (j >= P.N || i0 >= P.M) continue;
-                T* cp = P.C + i0 + j * P.ldc;
-                const bool full = i0 + 4 <= P.M;
-                const bool vec = full && P.c_vec;
+            }
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+                T* cb = P.C + (r0w + a * 16) + (c0w + b * 16) * P.ldc;
                 T out[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) out[r] = alpha * acc[a][b][r];
-                if (beta != T(0)) {
-                    T cv[4];
-                    if (full) load4<T, NTHR>(cp, vec, cv);
-                    else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) cv[r] = (i0 + r < P.M) ? cp[r] : T(0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) out[r] = out[r] + beta * cv[r];
+                for (int r = 0; r < 4; ++r) {
+                    out[r] = beta != T(0) ? axpby(alpha, acc[a][b][r], beta, cv[b][r])
+                                          : alpha * acc[a][b][r];
                 }
-                if (vec) {
+                if constexpr (sizeof(T) == 8) {
 #pragma unroll
-                    for (int h = 0; h < 4 / VEC; ++h) {
-                        V v;
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) v[e] = out[h * VEC + e];
-                        *reinterpret_cast<V*>(cp + h * VEC) = v;
-                    }
+                    for (int r = 0; r < 4; ++r) cb[di(r) + (int64_t)dj(r) * P.ldc] = out[r];
                 } else {
+                    typedef typename Types<T>::uvec U;
+                    U u;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (i0 + r < P.M) cp[r] = out[r];
+                    for (int r = 0; r < 4; ++r) u[r] = out[r];
+                    *reinterpret_cast<U*>(cb + di(0) + (int64_t)dj(0) * P.ldc) = u;
                 }
             }
         }
+    } else {
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = r0w + a * 16 + di(r), j = c0w + b * 16 + dj(r);
+                    if (i < P.M && j < P.N) {
+                        T* cp = P.C + i + j * P.ldc;
+                        *cp = beta != T(0) ? axpby(alpha, acc[a][b][r], beta, *cp)
+                                           : alpha * acc[a][b][r];
+                    }
+                }
     }
 }
 
@@ -598,7 +621,6 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.a_fast = P.a_vec && a_span < ((int64_t)1 << 31);
     P.b_fast = P.b_vec && b_span < ((int64_t)1 << 31);
     P.order = d.order;
-    P.stagger = d.stagger;
     return P;
 }
 

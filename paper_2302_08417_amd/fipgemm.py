@@ -25,7 +25,7 @@ FIP_COL_MAJOR, FIP_ROW_MAJOR = 0, 1
 FIP_F64, FIP_F32 = 0, 1
 FIP_ERR_HANDLE, FIP_ERR_WORKSPACE, FIP_ERR_LAUNCH, FIP_ERR_UNSUPPORTED, FIP_ERR_ALLOC = -1, -2, -3, -4, -5
 FIP_ATTR_PACK_POLICY, FIP_ATTR_TILE, FIP_ATTR_NO_PUBLISH, FIP_ATTR_STATS, FIP_ATTR_EPOCH = 1, 2, 3, 4, 5
-FIP_ATTR_ORDER, FIP_ATTR_STAGGER = 7, 8
+FIP_ATTR_ORDER = 7
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
 
