@@ -8,7 +8,8 @@ value = GFLOP/s (2mnk flops per step) of the fused-pack path.  The JSON line als
 carries the roofline position of the GEMM kernel, the oracle timed on the host
 cores over a bounded sample of the same workload, and a size sweep comparing
 fused-pack, pack-then-compute (fip_pack + CONSUME_ONLY) and unpacked (NONE)
-paths in FP64 and FP32.
+paths in FP64 and FP32 (median over interleaved rounds; pack-then-compute time includes
+its pack launch).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu-baseline]
 """
@@ -121,6 +122,21 @@ class Gemm:
         self.handles.clear()
 
 
+def time_interleaved(g, policies, rounds=11, warmup=3):
+    """Median per-call time (ms) of each policy.  Every round times one batch of each policy,
+    alternating the order between rounds, so that clock ramps and drift hit all of them alike."""
+    import statistics
+    est = g.flops() / (40e12 if g.case.A.dtype.itemsize == 8 else 80e12) + 5e-6
+    reps = max(1, min(200, int(0.01 / est)))
+    for pol in policies:
+        g.time(pol, 1, warmup)
+    times = {pol: [] for pol in policies}
+    for r in range(rounds):
+        for pol in (policies if r % 2 == 0 else policies[::-1]):
+            times[pol].append(g.time(pol, reps, 0))
+    return {pol: statistics.median(v) for pol, v in times.items()}, rounds * reps
+
+
 def cpu_baseline(n, target_s=12.0):
     """The oracle, as it stands, on a column sample of the headline workload."""
     import numpy as np
@@ -139,8 +155,9 @@ def cpu_baseline(n, target_s=12.0):
 
     cols = 4
     t = run(cols)
-    cols = int(max(4, min(n, cols * target_s / max(t, 1e-3))))
-    t = run(cols)
+    while t < 0.5 * target_s and cols < n:  # grow the sample until it takes about target_s
+        cols = int(max(cols + 1, min(n, cols * target_s / max(t, 1e-3))))
+        t = run(cols)
     gf = 2.0 * n * cols * n / t / 1e9
     return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
             "kind": "oracle",
@@ -167,9 +184,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures a single GPU: this build runs on one MI355X only "
-              "(multi-GPU sharding is a design note, not an implementation); use --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs a GEMM on a single MI355X, "
+              "and sharding across GPUs is described as a design, not implemented; "
+              "use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -239,11 +256,13 @@ def main():
         for sdt in args.sweep_dtypes.split(","):
             for s in sizes:
                 gs = Gemm(F, torch, s, sdt, seed=synth.BASE_SEED + 17 * s)
-                reps = max(5, min(200, int(2e11 / gs.flops()) if sdt == "f64" else int(4e11 / gs.flops())))
                 row = {"dtype": sdt, "m": s, "n": s, "k": s}
-                for name, pol in (("fused", F.FIP_PACK_AUTO), ("pack_then_compute", F.FIP_PACK_CONSUME_ONLY),
-                                  ("no_pack", F.FIP_PACK_NONE)):
-                    t = gs.time(pol, reps, 3)
+                names = {F.FIP_PACK_AUTO: "fused", F.FIP_PACK_CONSUME_ONLY: "pack_then_compute",
+                         F.FIP_PACK_NONE: "no_pack"}
+                med, calls = time_interleaved(gs, list(names))
+                row["calls_per_variant"] = calls
+                for pol, name in names.items():
+                    t = med[pol]
                     row[name + "_us"] = round(t * 1e3, 2)
                     row[name + "_gflops"] = round(gs.flops() / (t * 1e-3) / 1e9, 2)
                 row["fused_pct_peak"] = round(100 * row["fused_gflops"] / (PEAK_TFLOPS[sdt] * 1e3), 2)
