@@ -49,7 +49,18 @@ extern "C" {
 typedef struct fip_handle_s* fip_handle_t;
 
 enum { FIP_COL_MAJOR = 0, FIP_ROW_MAJOR = 1 };
-enum { FIP_F64 = 0, FIP_F32 = 1 };
+/* Element types / compute forms ("dtype" arguments).  FIP_F64 and FIP_F32 are
+   the plain GEMMs; the others are the mixed-precision forms of fip_gemm_mx
+   (binary32 accumulation); FIP_F32 and FIP_BF16 also name the C storage type
+   of fip_gemm_mx. */
+enum {
+    FIP_F64 = 0,          /* binary64 operands and C */
+    FIP_F32 = 1,          /* binary32 operands and C */
+    FIP_BF16 = 2,         /* bfloat16 operands */
+    FIP_E4M3 = 3,         /* OCP FP8 E4M3 operands (codes), optional power-of-two scales */
+    FIP_BF16X3 = 4,       /* binary32 operands split into 3 bfloat16 terms, 6 products */
+    FIP_BF16X3_FAST = 5,  /* binary32 operands split into 2 bfloat16 terms, 3 products */
+};
 
 /* Error codes (negative). */
 #define FIP_ERR_HANDLE (-1)      /* null or destroyed handle */
@@ -107,6 +118,12 @@ enum {
  * hardware XCC id of the workgroup that packs it; copy c of op(A)'s pack
  * starts at workspace + a_pack_offset + c * a_copy_bytes.  The standalone
  * pack (fip_pack) and CONSUME_ONLY use copy 0.
+ * Mixed-precision forms (dtype FIP_BF16 .. FIP_BF16X3_FAST): MT = NT = 128,
+ * KT = 64 (bfloat16), 128 (E4M3) or 32 (split forms); every block is K-major
+ * whatever the storage (a_kmajor = b_kmajor = 1), and holds PLANES planes of
+ * MT*KT packed elements one after the other (PLANES = 3 for FIP_BF16X3, 2 for
+ * FIP_BF16X3_FAST, else 1): plane t holds term t of the split (bfloat16 bits),
+ * or the operand's own bfloat16 / E4M3 bits.  a_copy_bytes counts all planes.
  */
 typedef struct {
     int32_t dtype, layout;
@@ -149,7 +166,7 @@ int fip_set_workspace(fip_handle_t handle, void* dptr, size_t bytes);
 /*
  * Plan a call without running it: tile class, pack decision and workspace
  * layout for the given shape under the handle's current attributes.
- * dtype: FIP_F64 or FIP_F32.  Writes *plan.  No HIP call is made.
+ * dtype: any FIP_F64 .. FIP_BF16X3_FAST.  Writes *plan.  No HIP call is made.
  */
 int fip_plan(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,
              char transA, char transB, fip_plan_t* plan);
@@ -180,11 +197,60 @@ int fip_sgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, 
 /*
  * Standalone pack (Sec. 2.1: conventional pack-then-compute): write copy 0 of
  * the packed op(A) and op(B) that a CONSUME_ONLY call of the same shape,
- * dtype (FIP_F64 / FIP_F32) and tile class reads.  Both operands are packed
- * whatever the shape.  Arguments as in fip_dgemm.
+ * dtype (any FIP_F64 .. FIP_BF16X3_FAST) and tile class reads.  Both operands
+ * are packed whatever the shape.  Arguments as in fip_dgemm.
  */
 int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,
              const void* A, int64_t lda, char transA, const void* B, int64_t ldb, char transB);
+
+/*
+ * Mixed-precision GEMM (paper Sec. 5: the fused packing carried over to other
+ * precisions; the pack is where operands are converted):
+ *
+ *     C := alpha * op(A) * op(B) + beta * C
+ *
+ * with binary32 accumulation (MFMA) and the operand forms
+ *   FIP_BF16         A, B bfloat16 (uint16 bit patterns).
+ *   FIP_E4M3         A, B OCP FP8 E4M3 codes (uint8), the values being q / s:
+ *                    a_scale[i] (length m, per row of op(A)) and b_scale[j]
+ *                    (length n, per column of op(B)) are the power-of-two
+ *                    scales the codes were made with (see fip_quantize_fp8);
+ *                    NULL means 1.  The product is divided by
+ *                    a_scale[i]*b_scale[j] in the epilogue.
+ *   FIP_BF16X3       A, B binary32; while packing, each element x becomes
+ *                    x0 + x1 + x2 with x0 = bf16(x), x1 = bf16(x - x0),
+ *                    x2 = bf16(x - x0 - x1) (round to nearest even), and the
+ *                    product keeps the six terms x_i*y_j with i + j <= 2.
+ *   FIP_BF16X3_FAST  the same with x0 + x1 and the three terms i + j <= 1.
+ * c_type: FIP_F32 (C binary32) or FIP_BF16 (C bfloat16; read, when beta != 0,
+ * as binary32, and the result rounded to nearest even).  alpha, beta binary32.
+ * a_scale / b_scale must be NULL for the forms other than FIP_E4M3.
+ * Packing policy, workspace, quick returns, leading-dimension rules and
+ * argument-position errors as in fip_dgemm (positions: dtype 2, layout 3,
+ * m 4, n 5, k 6, alpha 7, A 8, lda 9, transA 10, B 11, ldb 12, transB 13,
+ * beta 14, C 15, ldc 16, c_type 17, a_scale 18, b_scale 19).  Device pointers.
+ */
+int fip_gemm_mx(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+                float alpha, const void* A, int64_t lda, char transA, const void* B, int64_t ldb,
+                char transB, float beta, void* C, int64_t ldc, int c_type, const float* a_scale,
+                const float* b_scale);
+
+/*
+ * Quantize a binary32 matrix X (rows x cols, stored in layout with leading
+ * dimension ldx) to OCP FP8 E4M3 with one power-of-two scale per row
+ * (axis = 0) or per column (axis = 1):
+ *   s_line = 2^e, e the largest integer with amax_line * 2^e <= 448
+ *            (e = 0 when the line is all zero), clamped to [-126, 126];
+ *   Q[r, c] = e4m3(X[r, c] * s_line), round to nearest even, saturating at
+ *            +-448 (NaN -> 0x7F); NaNs do not count towards amax.
+ * Q (uint8, same layout, leading dimension ldq) and scales (binary32, rows or
+ * cols entries) are device buffers owned by the caller; scales is also used
+ * as scratch while the call runs.  For fip_gemm_mx, quantize op(A) per row
+ * and op(B) per column.  Four kernel launches on the handle's stream.
+ * Positions: layout 2, rows 3, cols 4, X 5, ldx 6, axis 7, Q 8, ldq 9, scales 10.
+ */
+int fip_quantize_fp8(fip_handle_t handle, int layout, int64_t rows, int64_t cols, const float* X,
+                     int64_t ldx, int axis, uint8_t* Q, int64_t ldq, float* scales);
 
 /*
  * Diagnostic: launch nblocks one-wave workgroups; workgroup b writes the

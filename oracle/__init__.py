@@ -41,10 +41,29 @@ def lib():
         L.oracle_pack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ch, i64, i64, vp, i64,
                                   i64, i64, vp]
         L.oracle_pack.restype = None
+        L.oracle_pack_oriented.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ch, i64, i64,
+                                           vp, i64, i64, i64, ctypes.c_int, vp]
+        L.oracle_pack_oriented.restype = None
         L.oracle_materialize_op.argtypes = [ctypes.c_int, ch, i64, i64, vp, i64, vp]
         L.oracle_materialize_op.restype = None
         L.oracle_mn_contiguous.argtypes = [ctypes.c_int, ctypes.c_int, ch]
         L.oracle_mn_contiguous.restype = ctypes.c_int
+        u8p = vp
+        L.oracle_bf16_round.argtypes = [vp, i64, vp]
+        L.oracle_bf16_round.restype = None
+        L.oracle_bf16_decode.argtypes = [vp, i64, vp]
+        L.oracle_bf16_decode.restype = None
+        L.oracle_split3.argtypes = [vp, i64, vp]
+        L.oracle_split3.restype = None
+        L.oracle_e4m3_decode.argtypes = [u8p, i64, vp]
+        L.oracle_e4m3_decode.restype = None
+        L.oracle_e4m3_encode.argtypes = [vp, i64, u8p]
+        L.oracle_e4m3_encode.restype = None
+        L.oracle_fp8_scale_exponent.argtypes = [dbl]
+        L.oracle_fp8_scale_exponent.restype = ctypes.c_int
+        L.oracle_quantize_fp8.argtypes = [ctypes.c_int, i64, i64, vp, i64, ctypes.c_int, u8p, i64,
+                                          vp]
+        L.oracle_quantize_fp8.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -136,3 +155,102 @@ def pack(X, is_b, layout, trans, mn, k, ld, MNT, KT):
     lib().oracle_pack(Xc.dtype.itemsize, int(bool(is_b)), layout, _t(trans), mn, k, _ptr(Xc), ld,
                       MNT, KT, _ptr(out))
     return out[: nt * nk * MNT * KT]
+
+
+# ---------------------------------------------------------------------------
+# Number formats of the mixed-precision forms (fip_oracle_mx.c)
+
+
+def bf16_round(x):
+    """bfloat16 bits (uint16) of binary32 values, round to nearest even."""
+    x32 = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1))
+    out = np.empty(max(x32.size, 1), dtype=np.uint16)
+    lib().oracle_bf16_round(_ptr(x32), x32.size, _ptr(out))
+    return out[: x32.size]
+
+
+def bf16_decode(h):
+    """binary64 values of bfloat16 bit patterns."""
+    h16 = np.ascontiguousarray(np.asarray(h, dtype=np.uint16).reshape(-1))
+    out = np.empty(max(h16.size, 1), dtype=np.float64)
+    lib().oracle_bf16_decode(_ptr(h16), h16.size, _ptr(out))
+    return out[: h16.size]
+
+
+def split3(x):
+    """Three bfloat16 planes (3, n) with x = x0 + x1 + x2 (see fip_oracle_mx.c)."""
+    x32 = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1))
+    out = np.empty(max(3 * x32.size, 1), dtype=np.uint16)
+    lib().oracle_split3(_ptr(x32), x32.size, _ptr(out))
+    return out[: 3 * x32.size].reshape(3, x32.size)
+
+
+def e4m3_decode(q):
+    """binary64 values of OCP FP8 E4M3 codes (NaN codes -> NaN)."""
+    q8 = np.ascontiguousarray(np.asarray(q, dtype=np.uint8).reshape(-1))
+    out = np.empty(max(q8.size, 1), dtype=np.float64)
+    lib().oracle_e4m3_decode(_ptr(q8), q8.size, _ptr(out))
+    return out[: q8.size]
+
+
+def e4m3_encode(x):
+    """E4M3 codes of binary64 values: nearest even, saturating at +-448."""
+    x64 = _f64(x)
+    out = np.empty(max(x64.size, 1), dtype=np.uint8)
+    lib().oracle_e4m3_encode(_ptr(x64), x64.size, _ptr(out))
+    return out[: x64.size]
+
+
+def fp8_scale_exponent(amax):
+    """e of the line scale 2^e: the largest with amax * 2^e <= 448 (0 for amax == 0)."""
+    return int(lib().oracle_fp8_scale_exponent(float(amax)))
+
+
+def quantize_fp8(layout, rows, cols, X, ld, axis, ldq=None):
+    """(Q, scales): X (binary32, stored rows x cols) quantized to E4M3 with a power-of-two
+    scale per row (axis 0) or per column (axis 1); Q is stored like X with leading dimension
+    ldq (default ld)."""
+    ldq = ld if ldq is None else ldq
+    X32 = np.ascontiguousarray(np.asarray(X, dtype=np.float32).reshape(-1))
+    outer = cols if layout == COL else rows
+    Q = np.zeros(max(ldq * outer, 1), dtype=np.uint8)
+    sc = np.empty(max(rows if axis == 0 else cols, 1), dtype=np.float32)
+    lib().oracle_quantize_fp8(layout, rows, cols, _ptr(X32), ld, axis, _ptr(Q), ldq, _ptr(sc))
+    return Q[: ldq * outer], sc[: rows if axis == 0 else cols]
+
+
+def pack_oriented(X, is_b, layout, trans, mn, k, ld, MNT, KT, kmajor):
+    """oracle.pack with the block orientation forced (kmajor 1 / 0) or from storage (-1)."""
+    Xc = np.ascontiguousarray(np.asarray(X).reshape(-1))
+    nt, nk = -(-mn // MNT), -(-k // KT)
+    out = np.empty(max(nt * nk * MNT * KT, 1), dtype=Xc.dtype)
+    lib().oracle_pack_oriented(Xc.dtype.itemsize, int(bool(is_b)), layout, _t(trans), mn, k,
+                               _ptr(Xc), ld, MNT, KT, int(kmajor), _ptr(out))
+    return out[: nt * nk * MNT * KT]
+
+
+MX_KT = {2: 64, 3: 128, 4: 32, 5: 32}     # k-step of each mixed-precision form
+MX_PLANES = {2: 1, 3: 1, 4: 3, 5: 2}
+
+
+def pack_mx(form, X, is_b, layout, trans, mn, k, ld, MNT=128):
+    """Reference pack of a mixed-precision operand as bytes: blocks (tile, k-step), each
+    holding PLANES K-major planes of MNT*KT elements.  bfloat16 / E4M3 operands: their bits;
+    the split forms: the bfloat16 terms of split3, plane t = term t."""
+    KT, PL = MX_KT[form], MX_PLANES[form]
+    if PL == 1:
+        return pack_oriented(X, is_b, layout, trans, mn, k, ld, MNT, KT, 1).view(np.uint8)
+    planes = split3(np.asarray(X, dtype=np.float32))
+    packs = [pack_oriented(planes[t], is_b, layout, trans, mn, k, ld, MNT, KT, 1)
+             .reshape(-1, MNT * KT) for t in range(PL)]
+    return np.stack(packs, axis=1).reshape(-1).view(np.uint8)
+
+
+def mx_values(form, X, scale=None, scale_axis_len=None):
+    """binary64 values of a stored mixed-precision operand buffer (decoded bits; E4M3 codes
+    are not divided by their scales here)."""
+    if form == 2:
+        return bf16_decode(X)
+    if form == 3:
+        return e4m3_decode(X)
+    return np.asarray(X, dtype=np.float64)

@@ -268,15 +268,19 @@ int oracle_mn_contiguous(int is_b, int layout, char trans)
  * op(X) are all-zero bytes.  Element bits are copied untouched (NaN payloads,
  * -0.0, subnormals).
  */
-void oracle_pack(int elem_size, int is_b, int layout, char trans,
-                 int64_t mn, int64_t k, const void* X, int64_t ld,
-                 int64_t MNT, int64_t KT, void* out)
+/* The pack with an explicit block orientation: kmajor = 1 stores each block
+   K-major ((i % MNT)*KT + p % KT), 0 MN-major ((p % KT)*MNT + i % MNT), -1
+   follows the operand's storage (the FP64/FP32 contract).  The mixed-precision
+   forms always pack K-major. */
+void oracle_pack_oriented(int elem_size, int is_b, int layout, char trans, int64_t mn, int64_t k,
+                          const void* X, int64_t ld, int64_t MNT, int64_t KT, int kmajor,
+                          void* out)
 {
     const unsigned char* src = (const unsigned char*)X;
     unsigned char* dst = (unsigned char*)out;
     const int64_t nt = (mn + MNT - 1) / MNT, nk = (k + KT - 1) / KT;
     const int tr = is_trans(trans);
-    const int mn_major = oracle_mn_contiguous(is_b, layout, trans);
+    const int mn_major = kmajor < 0 ? oracle_mn_contiguous(is_b, layout, trans) : !kmajor;
     for (int64_t t = 0; t < nt; ++t)
         for (int64_t q = 0; q < nk; ++q)
             for (int64_t pp = 0; pp < KT; ++pp)
@@ -291,4 +295,10 @@ void oracle_pack(int elem_size, int is_b, int layout, char trans,
                     const int64_t off = layout == OR_COL ? sr + sc * ld : sr * ld + sc;
                     memcpy(d, src + off * elem_size, (size_t)elem_size);
                 }
+}
+
+void oracle_pack(int elem_size, int is_b, int layout, char trans, int64_t mn, int64_t k,
+                 const void* X, int64_t ld, int64_t MNT, int64_t KT, void* out)
+{
+    oracle_pack_oriented(elem_size, is_b, layout, trans, mn, k, X, ld, MNT, KT, -1, out);
 }

@@ -23,7 +23,8 @@
  *     magnitude amax: the largest power of two s with amax * s <= 448
  *     (s = 1 when amax == 0); its exponent is clamped to [-126, 126].
  *   Three-term split of a binary32 x: x0 = bf16(x), x1 = bf16(x - x0),
- *     x2 = bf16(x - x0 - x1), each difference exact in binary32.
+ *     x2 = bf16(x - x0 - x1), each difference exact in binary32, so that
+ *     x0 + x1 + x2 == x for every finite x whose bfloat16 rounding is finite.
  */
 #include <math.h>
 #include <stdint.h>

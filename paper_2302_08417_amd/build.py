@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfipgemm.so")
-SOURCES = ["fipgemm_kernels.hip", "fipgemm_api.cpp"]
+SOURCES = ["fipgemm_kernels.hip", "fipgemm_mx.hip", "fipgemm_api.cpp"]
 ARCH = os.environ.get("FIPGEMM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -25,21 +25,27 @@ def build(verbose: bool = False) -> str:
     objs = []
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:  # compile the sources concurrently
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"]
         cmd = [HIPCC, *COMMON, *lang, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        out = "\n".join(line for line in (r.stdout + r.stderr).splitlines()
-                        if "packed-fp32-ops" not in line)
-        if r.returncode != 0:
+        procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                 stderr=subprocess.STDOUT, text=True)))
+    failed = []
+    for src, obj, p in procs:
+        text, _ = p.communicate()
+        out = "\n".join(line for line in text.splitlines() if "packed-fp32-ops" not in line)
+        if p.returncode != 0:
             sys.stderr.write(out + "\n")
-            raise RuntimeError(f"hipcc failed on {src}")
-        if verbose and out.strip():
+            failed.append(src)
+        elif verbose and out.strip():
             print(out)
         objs.append(obj)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -57,6 +57,54 @@ hipError_t launch_pack(const LaunchDesc& d);
 hipError_t launch_scale(int elem, int64_t M, int64_t N, void* C, int64_t ldc, double beta,
                         hipStream_t stream);
 
+// ---- Mixed-precision forms (fipgemm_mx.hip) --------------------------------
+// Operands stored as bfloat16 or FP8 E4M3, or binary32 split into bfloat16
+// terms while packing; binary32 accumulation; C binary32 or bfloat16.
+enum MxForm : int32_t {
+    kMxBF16 = 0,     // A, B bfloat16
+    kMxFP8 = 1,      // A, B E4M3 with optional per-row / per-column scales
+    kMxX3 = 2,       // A, B binary32, three bfloat16 terms, six products
+    kMxX3Fast = 3,   // A, B binary32, two bfloat16 terms, three products
+};
+constexpr int kMxTile = 128;                     // C tile 128 x 128, 2 x 2 waves
+inline int mx_kt(int form) { return form == kMxBF16 ? 64 : form == kMxFP8 ? 128 : 32; }
+inline int mx_planes(int form) { return form == kMxX3 ? 3 : form == kMxX3Fast ? 2 : 1; }
+inline int mx_src_bytes(int form) { return form == kMxBF16 ? 2 : form == kMxFP8 ? 1 : 4; }
+inline int mx_pack_bytes(int form) { return form == kMxFP8 ? 1 : 2; }  // per plane element
+// Workgroups of one mixed-precision tile kernel that fit on a CU (LDS-bound).
+inline int mx_per_cu(int form) { return form == kMxBF16 || form == kMxFP8 ? 2 : 1; }
+
+struct MxLaunchDesc {
+    int form;              // MxForm
+    int mode;              // Mode
+    int pack_a, pack_b, no_publish, stats, order;
+    int c_bf16;            // C stored as bfloat16 (else binary32)
+    int64_t M, N, K;       // kernel terms (C column-major M x N)
+    const void* A; int64_t a_ld; int a_kmajor;   // element (x, p): K-major X[x*ld + p],
+    const void* B; int64_t b_ld; int b_kmajor;   //   MN-major X[x + p*ld]
+    void* C; int64_t ldc;
+    float alpha, beta;
+    const float* a_scale;  // per kernel row (null = 1); FP8 only
+    const float* b_scale;  // per kernel column (null = 1); FP8 only
+    void* apack; int64_t apack_copy_bytes;
+    void* bpack; int64_t bpack_copy_bytes;
+    uint64_t* aflag; uint64_t* bflag; uint64_t* aclaim; uint64_t* bclaim;
+    unsigned long long* stats_ptr;
+    uint64_t epoch;
+    hipStream_t stream;
+};
+
+hipError_t launch_gemm_mx(const MxLaunchDesc& d);
+// Standalone pack of both operands (copy 0) in the form's packed layout.
+hipError_t launch_pack_mx(const MxLaunchDesc& d);
+// FP8 quantization of a binary32 matrix with power-of-two line scales.
+hipError_t launch_quantize_fp8(int layout_col, int64_t rows, int64_t cols, const float* X,
+                               int64_t ldx, int axis, uint8_t* Q, int64_t ldq, float* scales,
+                               hipStream_t stream);
+// C := beta*C for a binary32 or bfloat16 C (kernel terms).
+hipError_t launch_scale_mx(int c_bf16, int64_t M, int64_t N, void* C, int64_t ldc, float beta,
+                           hipStream_t stream);
+
 // Enqueue the XCC-id diagnostic (one 64-thread workgroup per entry).
 hipError_t launch_xcc_map(uint32_t* out, int64_t nblocks, hipStream_t stream);
 

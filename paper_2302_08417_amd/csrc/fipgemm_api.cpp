@@ -61,15 +61,6 @@ int64_t max1(int64_t v) { return v > 1 ? v : 1; }
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// op(X)[r, c] = X[r*rs + c*cs] for the BLAS (layout, trans, ld) triple.
-void op_strides(int layout, char trans, int64_t ld, int64_t* rs, int64_t* cs)
-{
-    const bool col = layout == FIP_COL_MAJOR;
-    const bool t = is_trans(trans);
-    if (col != t) { *rs = 1; *cs = ld; }  // col-major N, row-major T
-    else { *rs = ld; *cs = 1; }           // col-major T, row-major N
-}
-
 // Kernel view of one call: C is always column-major; for row-major storage
 // the kernel computes C^T = op(B)^T op(A)^T, i.e. the operands swap sides.
 struct KernelShape {
@@ -116,14 +107,43 @@ struct Plan {
 
 bool mn_major(bool is_b, int layout, char trans);
 
+// Mixed-precision form of a dtype code, or -1 for FIP_F64 / FIP_F32.
+int mx_form_of(int dtype)
+{
+    switch (dtype) {
+    case FIP_BF16: return fip::kMxBF16;
+    case FIP_E4M3: return fip::kMxFP8;
+    case FIP_BF16X3: return fip::kMxX3;
+    case FIP_BF16X3_FAST: return fip::kMxX3Fast;
+    default: return -1;
+    }
+}
+
+bool valid_dtype(int dtype) { return dtype == FIP_F64 || dtype == FIP_F32 || mx_form_of(dtype) >= 0; }
+
 void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
                char tA, char tB, bool standalone_pack, Plan* pl)
 {
     memset(pl, 0, sizeof(*pl));
-    pl->elem = dtype == FIP_F64 ? 8 : 4;
+    const int form = mx_form_of(dtype);
     pl->ks = kernel_shape(layout, m, n);
-    const int cls = h->tile_override >= 0 ? h->tile_override : choose_tile_class(pl->ks.M, pl->ks.N);
-    const int MT = fip::tile_mt(cls), NT = MT, KT = fip::tile_kt(cls, pl->elem);
+    int cls, MT, KT;
+    int64_t resident;
+    if (form >= 0) {
+        // one tile shape; a packed element is PLANES values of the packed type
+        cls = 0;
+        MT = fip::kMxTile;
+        KT = fip::mx_kt(form);
+        pl->elem = fip::mx_planes(form) * fip::mx_pack_bytes(form);
+        resident = 256 * fip::mx_per_cu(form);
+    } else {
+        pl->elem = dtype == FIP_F64 ? 8 : 4;
+        cls = h->tile_override >= 0 ? h->tile_override : choose_tile_class(pl->ks.M, pl->ks.N);
+        MT = fip::tile_mt(cls);
+        KT = fip::tile_kt(cls, pl->elem);
+        resident = resident_tiles(cls);
+    }
+    const int NT = MT;
     pl->tilesKM = cdiv(pl->ks.M, MT);
     pl->tilesKN = cdiv(pl->ks.N, NT);
     pl->nK = cdiv(k, KT);
@@ -147,7 +167,7 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
             // can read a packed panel without waiting only if it starts after
             // the first pass finished, i.e. when the launch has more tiles than
             // fit on the device at once.  Otherwise nobody could reuse the pack.
-            const bool later_passes = pl->tilesKM * pl->tilesKN > resident_tiles(cls);
+            const bool later_passes = pl->tilesKM * pl->tilesKN > resident;
             pl->kpack_a = pl->tilesKN > 1 && later_passes;
             pl->kpack_b = pl->tilesKM > 1 && later_passes;
         }
@@ -174,8 +194,10 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     p.copies = copies;
     p.policy = policy;
     p.stats_offset = pl->off_stats;
-    p.a_kmajor = !mn_major(false, layout, tA);
-    p.b_kmajor = !mn_major(true, layout, tB);
+    // packed block orientation: the operand's own for FP64/FP32, always
+    // K-major (the MFMA operand form) for the mixed-precision forms
+    p.a_kmajor = form >= 0 ? 1 : !mn_major(false, layout, tA);
+    p.b_kmajor = form >= 0 ? 1 : !mn_major(true, layout, tB);
     const bool fl = pl->mode == fip::kModeFused;
     p.workspace_bytes = (pl->kpack_a || pl->kpack_b) ? off : 0;
     // Report in the caller's terms: op(A) is the kernel's B-side when swapped.
@@ -337,6 +359,93 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
     }
 }
 
+// Kernel descriptor of a mixed-precision call (operands, workspace, stream);
+// the caller fills C, alpha, beta, scales and the epoch.
+void fill_mx_desc(const fip_handle_s* h, const Plan& pl, int form, int layout, int64_t k,
+                  const void* A, int64_t lda, char tA, const void* B, int64_t ldb, char tB,
+                  fip::MxLaunchDesc* d)
+{
+    memset(d, 0, sizeof(*d));
+    d->form = form;
+    d->mode = pl.mode;
+    d->pack_a = pl.kpack_a; d->pack_b = pl.kpack_b;
+    d->no_publish = h->no_publish;
+    d->stats = h->stats;
+    d->order = h->order;
+    d->M = pl.ks.M; d->N = pl.ks.N; d->K = k;
+    const bool a_mn = mn_major(false, layout, tA), b_mn = mn_major(true, layout, tB);
+    if (!pl.ks.swapped) {
+        d->A = A; d->a_ld = lda; d->a_kmajor = !a_mn;
+        d->B = B; d->b_ld = ldb; d->b_kmajor = !b_mn;
+    } else {
+        d->A = B; d->a_ld = ldb; d->a_kmajor = !b_mn;
+        d->B = A; d->b_ld = lda; d->b_kmajor = !a_mn;
+    }
+    if (pl.pub.workspace_bytes > 0) {
+        char* ws = static_cast<char*>(h->ws);
+        d->stats_ptr = reinterpret_cast<unsigned long long*>(ws + pl.off_stats);
+        d->aflag = reinterpret_cast<uint64_t*>(ws + pl.off_aflag);
+        d->bflag = reinterpret_cast<uint64_t*>(ws + pl.off_bflag);
+        d->aclaim = reinterpret_cast<uint64_t*>(ws + pl.off_aclaim);
+        d->bclaim = reinterpret_cast<uint64_t*>(ws + pl.off_bclaim);
+        d->apack = ws + pl.off_apack;
+        d->bpack = ws + pl.off_bpack;
+        d->apack_copy_bytes = pl.apack_copy_elems * pl.elem;
+        d->bpack_copy_bytes = pl.bpack_copy_elems * pl.elem;
+    } else {
+        d->stats = 0;
+    }
+    d->stream = h->stream;
+}
+
+int gemm_mx_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+                 float alpha, const void* A, int64_t lda, char tA, const void* B, int64_t ldb,
+                 char tB, float beta, void* C, int64_t ldc, int c_type, const float* a_scale,
+                 const float* b_scale)
+{
+    try {
+        if (!valid_handle(h)) return FIP_ERR_HANDLE;
+        const int form = mx_form_of(dtype);
+        if (form < 0) return 2;
+        // positions: layout 3, m 4, n 5, k 6, alpha 7, A 8, lda 9, transA 10, B 11, ldb 12,
+        // transB 13, beta 14, C 15, ldc 16, c_type 17, a_scale 18, b_scale 19
+        const int bad = check_args(3, layout, m, n, k, alpha != 0.f, A, lda, tA, B, ldb, tB, true,
+                                   beta == 1.f, C, ldc);
+        if (bad) return bad;
+        if (c_type != FIP_F32 && c_type != FIP_BF16) return 17;
+        if (form != fip::kMxFP8 && a_scale != nullptr) return 18;
+        if (form != fip::kMxFP8 && b_scale != nullptr) return 19;
+        if (m == 0 || n == 0) return 0;
+        if ((alpha == 0.f || k == 0) && beta == 1.f) return 0;
+        const KernelShape ks = kernel_shape(layout, m, n);
+        const int c_bf16 = c_type == FIP_BF16;
+        if (alpha == 0.f || k == 0) {
+            if (fip::launch_scale_mx(c_bf16, ks.M, ks.N, C, ldc, beta, h->stream) != hipSuccess)
+                return FIP_ERR_LAUNCH;
+            return 0;
+        }
+        Plan pl;
+        make_plan(h, dtype, layout, m, n, k, tA, tB, false, &pl);
+        const int ws = prepare_workspace(h, pl);
+        if (ws) return ws;
+        fip::MxLaunchDesc d;
+        fill_mx_desc(h, pl, form, layout, k, A, lda, tA, B, ldb, tB, &d);
+        d.C = C; d.ldc = ldc; d.c_bf16 = c_bf16;
+        d.alpha = alpha; d.beta = beta;
+        // per row of op(A) / column of op(B); the kernel's A-side is op(B)^T
+        // when the operands are swapped for row-major storage
+        d.a_scale = ks.swapped ? b_scale : a_scale;
+        d.b_scale = ks.swapped ? a_scale : b_scale;
+        if (pl.pub.workspace_bytes > 0 && pl.mode == fip::kModeFused) d.epoch = h->epoch = next_epoch();
+        if (fip::launch_gemm_mx(d) != hipSuccess) return FIP_ERR_LAUNCH;
+        h->last = pl.pub;
+        h->has_last = 1;
+        return 0;
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -430,7 +539,7 @@ int fip_plan(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
              char transA, char transB, fip_plan_t* plan)
 {
     if (!valid_handle(handle)) return FIP_ERR_HANDLE;
-    if (dtype != FIP_F64 && dtype != FIP_F32) return 2;
+    if (!valid_dtype(dtype)) return 2;
     if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 3;
     if (m < 0) return 4;
     if (n < 0) return 5;
@@ -474,7 +583,7 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
 {
     try {
         if (!valid_handle(handle)) return FIP_ERR_HANDLE;
-        if (dtype != FIP_F64 && dtype != FIP_F32) return 2;
+        if (!valid_dtype(dtype)) return 2;
         // positions: layout 3, m 4, n 5, k 6, A 7, lda 8, transA 9, B 10, ldb 11, transB 12
         const int bad = check_args(3, layout, m, n, k, true, A, lda, transA, B, ldb, transB, false,
                                    false, nullptr, 1);
@@ -488,6 +597,15 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
         if (pl.pub.workspace_bytes == 0) { handle->last = pl.pub; handle->has_last = 1; return 0; }
         const int ws = prepare_workspace(handle, pl);
         if (ws) return ws;
+        if (mx_form_of(dtype) >= 0) {
+            fip::MxLaunchDesc d;
+            fill_mx_desc(handle, pl, mx_form_of(dtype), layout, k, A, lda, transA, B, ldb, transB,
+                         &d);
+            if (fip::launch_pack_mx(d) != hipSuccess) return FIP_ERR_LAUNCH;
+            handle->last = pl.pub;
+            handle->has_last = 1;
+            return 0;
+        }
         fip::LaunchDesc d;
         memset(&d, 0, sizeof(d));
         d.elem = pl.elem;
@@ -501,6 +619,39 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
         handle->last = pl.pub;
         handle->has_last = 1;
         return 0;
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+int fip_gemm_mx(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+                float alpha, const void* A, int64_t lda, char transA, const void* B, int64_t ldb,
+                char transB, float beta, void* C, int64_t ldc, int c_type, const float* a_scale,
+                const float* b_scale)
+{
+    return gemm_mx_impl(handle, dtype, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB,
+                        beta, C, ldc, c_type, a_scale, b_scale);
+}
+
+int fip_quantize_fp8(fip_handle_t handle, int layout, int64_t rows, int64_t cols, const float* X,
+                     int64_t ldx, int axis, uint8_t* Q, int64_t ldq, float* scales)
+{
+    try {
+        if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+        if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 2;
+        if (rows < 0) return 3;
+        if (cols < 0) return 4;
+        const bool col = layout == FIP_COL_MAJOR;
+        const bool any = rows > 0 && cols > 0;
+        if (any && X == nullptr) return 5;
+        if (ldx < max1(col ? rows : cols)) return 6;
+        if (axis != 0 && axis != 1) return 7;
+        if (any && Q == nullptr) return 8;
+        if (ldq < max1(col ? rows : cols)) return 9;
+        if (any && scales == nullptr) return 10;
+        if (!any) return 0;
+        return fip::launch_quantize_fp8(col, rows, cols, X, ldx, axis, Q, ldq, scales,
+                                        handle->stream) == hipSuccess ? 0 : FIP_ERR_LAUNCH;
     } catch (...) {
         return FIP_ERR_LAUNCH;
     }

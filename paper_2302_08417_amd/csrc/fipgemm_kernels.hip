@@ -12,19 +12,21 @@
 // the unpacked chunk from HBM (coalesced along whichever stride is 1, masked
 // with zero fill at the fringes, Sec. 2.2), and stores the same registers both
 // to LDS for its own MFMAs and to the HBM pack buffer at the chunk's canonical
-// position.  Once a chunk's pack stores are complete the producer publishes a
-// per-(panel, k-step) flag stamped with the call's epoch.  Every other
-// workgroup on that XCD needing the panel checks the flag per k-step: if set,
-// it reads the packed, contiguous, aligned chunk (16-byte vector loads, no
-// masks); otherwise it reads the unpacked operand itself.  Nobody ever waits,
-// so the schedule cannot deadlock, and both sources hold identical bits, so
-// the result does not depend on timing.
+// position.  Once every pack store of the panel has completed, the producer
+// publishes the panel's completion flag, stamped with the call's epoch.
+// Every other workgroup on that XCD needing the panel checks the flag at its
+// tile start and then every few k-steps: once set, it reads the packed,
+// contiguous chunks (16-byte vector loads, no masks); until then it reads the
+// unpacked operand itself.  Nobody ever waits, so the schedule cannot
+// deadlock, and both sources hold identical bits, so the result does not
+// depend on timing.
 //
 // Which panels are packed follows the paper's reuse table (Sec. 3.3), decided
 // on the host.  The paper's shared-A, private-B multithreading scheme
 // (Sec. 3.5) maps to per-XCD pack copies: each XCD has its own L2, so a copy
 // written and read by one XCD needs no cross-L2 cache maintenance.
 #include "fip_internal.h"
+#include "fip_device.h"
 
 namespace fip {
 namespace {
@@ -57,33 +59,6 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
 __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// alpha*x + beta*y with one fixed rounding sequence (alpha*x rounded, then one
-// fused multiply-add), written out so that no tile shape's code generation can
-// contract it differently: every kernel variant then rounds C identically.
-__device__ __forceinline__ double axpby(double alpha, double x, double beta, double y)
-{
-    return __builtin_fma(beta, y, alpha * x);
-}
-__device__ __forceinline__ float axpby(float alpha, float x, float beta, float y)
-{
-    return __builtin_fmaf(beta, y, alpha * x);
-}
-
-// Hardware id of the XCD (XCC) running this wave: hwreg XCC_ID, bits [3:0].
-__device__ __forceinline__ unsigned xcc_id()
-{
-    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11));
-}
-
-// Wait until every memory operation this wave issued has completed; for
-// global stores that means the XCD's L2 has acknowledged them.
-__device__ __forceinline__ void wait_all_memory()
-{
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 template <typename T>
@@ -236,38 +211,6 @@ struct Chunk {
     }
 };
 
-// Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs,
-// so w % 8 is (normally) the XCD.  Each XCD gets one contiguous run of a
-// grouped tile order: bands of GROUP_M tile rows, swept column by column.
-// That keeps the tiles running together on an XCD compact for its L2 and most
-// of the panels an XCD packs private to it.
-//   order 0: inside a band, the GROUP_M tiles of one column are consecutive;
-//   order 1: inside a band, consecutive tiles take distinct columns (round r,
-//            slot s -> column s, row (s + r) mod GROUP_M), so the first round of
-//            workgroups touches every column panel of the band once and later
-//            rounds find them all packed.
-__device__ __forceinline__ void tile_coords(int w, int tilesM, int tilesN, int group_m, int order,
-                                            int& tm, int& tn)
-{
-    const int T = tilesM * tilesN;
-    const int xcd = w & 7, local = w >> 3;
-    const int q = T >> 3, rr = T & 7;
-    const int t = xcd * q + min(xcd, rr) + local;
-    const int per_group = group_m * tilesN;
-    const int g = t / per_group;
-    const int first_m = g * group_m;
-    const int gsize = min(tilesM - first_m, group_m);
-    const int rem = t - g * per_group;
-    if (order == 0) {
-        tm = first_m + rem % gsize;
-        tn = rem / gsize;
-    } else {
-        const int round = rem / tilesN, slot = rem - round * tilesN;
-        tn = slot;
-        tm = first_m + (slot + round) % gsize;
-    }
-}
-
 template <typename T, int MT, int NT, int KT, int WM, int WN, bool AKC, bool BKC>
 __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P)
 {
@@ -275,8 +218,6 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     typedef Chunk<T, MT, KT, NTHR, AKC> ChA;
     typedef Chunk<T, NT, KT, NTHR, BKC> ChB;
     typedef typename Types<T>::acc Acc;
-    typedef typename Types<T>::vec V;
-    constexpr int VEC = Types<T>::VEC;
     constexpr int WTM = MT / WM, WTN = NT / WN;  // per-wave C sub-tile
     constexpr int FM = WTM / 16, FN = WTN / 16;  // MFMA blocks per wave
     static_assert(FM >= 1 && FN >= 1 && KT % 4 == 0, "tile shape");

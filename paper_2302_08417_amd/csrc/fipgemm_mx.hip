@@ -1,0 +1,820 @@
+// HIP kernels of the mixed-precision fused-pack GEMM for gfx950 (CDNA4).
+//
+// The paper expects its fused packing to carry over to other precisions, and
+// notes that the packing stage can encode a transformation of the data on its
+// way into the packed buffer (Sec. 5, the 1m method).  Here the pack is where
+// the conversion happens, once per panel:
+//   BF16      A, B stored as bfloat16; the pack copies the bits.
+//   FP8       A, B stored as OCP E4M3 codes (with optional power-of-two scales
+//             per row of op(A) / column of op(B), applied in the epilogue);
+//             the pack copies the bytes.
+//   BF16X3    A, B stored as binary32; the first pass splits every element
+//             into x0 + x1 + x2 (three bfloat16 terms, x0 = bf16(x),
+//             x1 = bf16(x - x0), x2 = bf16(x - x0 - x1)) and packs the three
+//             planes; later passes read the split planes instead of splitting
+//             again.  Six bfloat16 MFMA products per block (terms i + j <= 2),
+//             the small ones in their own accumulator, added to x0*y0 last.
+//   BF16X3F   the same with two terms and three products.
+// Accumulation is binary32 in every form (MFMA 16x16x32 bf16, 16x16x128 fp8).
+//
+// Structure (shared with the FP64/FP32 kernel): one workgroup per 128 x 128 C
+// tile, 2 x 2 waves of 64 x 64, k-steps of KT, two LDS buffers.  Fused
+// packing per operand panel: first toucher per XCD claims and packs, publishes
+// a completion flag once its stores are acknowledged; other workgroups read
+// the packed copy from the moment they see the flag, the unpacked operand
+// before that.  Packed and unpacked sources fill the same thread's registers
+// with the same elements, so each wave may choose its source independently.
+//
+// Packed layout (every form): chunk (tile t, k-step q) is block t*nK + q of
+// PLANES * 128 * KT elements; plane t of a block holds the chunk K-major,
+// element (x, p) at x*KT + p.  K-major is the MFMA operand form (each lane
+// reads a contiguous k-run), so a packed chunk goes to LDS with plain vector
+// copies whatever the caller's storage order was: the first pass does the
+// transposition of MN-major operands once, later passes never.
+#include "fip_internal.h"
+#include "fip_device.h"
+
+namespace fip {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+// Element-aligned (4-byte) forms for unpacked operands: one 8- or 16-byte
+// global load on gfx950 as long as the address is dword aligned.
+typedef unsigned u4a __attribute__((ext_vector_type(4), aligned(4)));
+typedef unsigned u2a __attribute__((ext_vector_type(2), aligned(4)));
+
+constexpr int MT = kMxTile;   // 128: C tile is MT x MT
+constexpr int NTHR = 256;     // 2 x 2 waves
+constexpr int NR = 4;         // operand rows per thread's micro-block
+constexpr int WT = 64;        // per-wave C sub-tile
+constexpr int FB = WT / 16;   // 16 x 16 MFMA blocks per wave side
+
+// Per-form constants.  KT: k-step; SB: bytes per source element; PL: packed
+// planes; EB: bytes per packed element; VK: k extent of a thread's micro-block
+// (a micro-block is NR rows x VK k-values of the operand chunk; 256 threads
+// cover the 128 x KT chunk); WPR: 32-bit words per micro-block row and plane.
+template <int FORM> struct Form;
+template <> struct Form<kMxBF16> {
+    typedef uint16_t S;
+    static constexpr int KT = 64, SB = 2, PL = 1, EB = 2, VK = 8;
+};
+template <> struct Form<kMxFP8> {
+    typedef uint8_t S;
+    static constexpr int KT = 128, SB = 1, PL = 1, EB = 1, VK = 16;
+};
+template <> struct Form<kMxX3> {
+    typedef float S;
+    static constexpr int KT = 32, SB = 4, PL = 3, EB = 2, VK = 4;
+};
+template <> struct Form<kMxX3Fast> {
+    typedef float S;
+    static constexpr int KT = 32, SB = 4, PL = 2, EB = 2, VK = 4;
+};
+
+template <int FORM> struct Geo {
+    typedef Form<FORM> Fm;
+    static constexpr int KT = Fm::KT, PL = Fm::PL, EB = Fm::EB, VK = Fm::VK, SB = Fm::SB;
+    static constexpr int WPR = VK * EB / 4;
+    static constexpr int KGROUPS = KT / VK;               // micro-blocks along k (8)
+    static constexpr int PITCH = KT * EB + 16;            // LDS row pitch in bytes
+    static constexpr int LDS_PLANE = MT * PITCH;
+    static constexpr int LDS_OPERAND = PL * LDS_PLANE;    // one buffer of one operand
+    static constexpr int PACK_PLANE = MT * KT * EB;       // bytes of one plane of a chunk
+    static constexpr int PACK_CHUNK = PL * PACK_PLANE;
+    static_assert(KGROUPS * (MT / NR) == NTHR, "micro-blocks must cover the chunk");
+    static_assert(WPR == 2 || WPR == 4, "8- or 16-byte rows");
+};
+
+// bfloat16 of a binary32, round to nearest even (the hardware conversion).
+__device__ __forceinline__ uint32_t bf16_bits(float v)
+{
+    const __bf16 h = (__bf16)v;
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Registers of one operand chunk on their way from HBM to LDS (and, for a
+// producer, to the pack buffer): thread b holds rows x0 .. x0+3 (x0 = 4*(b/8))
+// and k-values p0 .. p0+VK-1 (p0 = VK*(b%8)) of the chunk, already in packed
+// form: for each plane and row, WPR words of consecutive k.
+template <int FORM, bool KC>
+struct Stage {
+    typedef Geo<FORM> G;
+    typedef typename Form<FORM>::S S;
+    static constexpr int PL = G::PL, WPR = G::WPR, VK = G::VK, EB = G::EB, SB = G::SB;
+    uint32_t w[PL][NR][WPR];
+
+    __device__ __forceinline__ static int x0_of(int tid) { return NR * (tid / G::KGROUPS); }
+    __device__ __forceinline__ static int p0_of(int tid) { return VK * (tid % G::KGROUPS); }
+
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int t = 0; t < PL; ++t)
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+#pragma unroll
+                for (int u = 0; u < WPR; ++u) w[t][j][u] = 0;
+    }
+
+    // Place source element (row j, k i) of the micro-block; w must start cleared.
+    __device__ __forceinline__ void put(int j, int i, S v)
+    {
+        if constexpr (FORM == kMxBF16) {
+            w[0][j][i >> 1] |= (uint32_t)v << (16 * (i & 1));
+        } else if constexpr (FORM == kMxFP8) {
+            w[0][j][i >> 2] |= (uint32_t)v << (8 * (i & 3));
+        } else {
+            const uint32_t h0 = bf16_bits(v);
+            const float r1 = v - bf16_float(h0);
+            const uint32_t h1 = bf16_bits(r1);
+            w[0][j][i >> 1] |= h0 << (16 * (i & 1));
+            w[1][j][i >> 1] |= h1 << (16 * (i & 1));
+            if constexpr (PL == 3) {
+                const float r2 = r1 - bf16_float(h1);
+                w[2][j][i >> 1] |= bf16_bits(r2) << (16 * (i & 1));
+            }
+        }
+    }
+
+    // Unpacked source, every element of the micro-block present and vector
+    // loads dword aligned.  src: this thread's element (x0, p0) of the chunk;
+    // ldb: leading dimension in bytes.
+    __device__ __forceinline__ void load_full(const char* __restrict__ src, int64_t ldb)
+    {
+        if constexpr (KC) {
+            // rows are contiguous along k: one 16-byte load per row
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const u4 v = *reinterpret_cast<const u4a*>(src + j * ldb);
+                if constexpr (FORM == kMxBF16 || FORM == kMxFP8) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) w[0][j][u] = v[u];
+                } else {
+#pragma unroll
+                    for (int t = 0; t < PL; ++t)
+#pragma unroll
+                        for (int u = 0; u < WPR; ++u) w[t][j][u] = 0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) put(j, i, __uint_as_float(v[i]));
+                }
+            }
+        } else {
+            // columns are contiguous along mn: VK loads of NR elements each,
+            // transposed into rows in registers
+            clear();
+#pragma unroll
+            for (int i = 0; i < VK; ++i) {
+                const char* p = src + i * ldb;
+                if constexpr (FORM == kMxBF16) {
+                    const u2 v = *reinterpret_cast<const u2a*>(p);
+                    put(0, i, (S)(v[0] & 0xFFFFu));
+                    put(1, i, (S)(v[0] >> 16));
+                    put(2, i, (S)(v[1] & 0xFFFFu));
+                    put(3, i, (S)(v[1] >> 16));
+                } else if constexpr (FORM == kMxFP8) {
+                    const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+                    for (int j = 0; j < NR; ++j) put(j, i, (S)((v >> (8 * j)) & 0xFFu));
+                } else {
+                    const u4 v = *reinterpret_cast<const u4a*>(p);
+#pragma unroll
+                    for (int j = 0; j < NR; ++j) put(j, i, __uint_as_float(v[j]));
+                }
+            }
+        }
+    }
+
+    // Unpacked source, fringe chunk (or unaligned operand): element loads with
+    // predicates; elements outside the MN x K operand are +0 (Sec. 2.2
+    // padding done in registers).  X: operand base; (xc, pc): chunk origin.
+    __device__ __forceinline__ void load_edge(const S* __restrict__ X, int64_t ld, int64_t MN,
+                                              int64_t K, int64_t xc, int64_t pc, int tid)
+    {
+        clear();
+        const int64_t x0 = xc + x0_of(tid), p0 = pc + p0_of(tid);
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+#pragma unroll
+            for (int i = 0; i < VK; ++i) {
+                const int64_t x = x0 + j, p = p0 + i;
+                S v = S(0);
+                if (x < MN && p < K) v = KC ? X[x * ld + p] : X[x + p * ld];
+                put(j, i, v);
+            }
+    }
+
+    // Packed source: the chunk's planes, K-major; this thread's rows are
+    // WPR-word runs at ((x0 + j)*KT + p0)*EB.
+    __device__ __forceinline__ void load_packed(const char* __restrict__ chunk, int tid)
+    {
+        const int off = (x0_of(tid) * G::KT + p0_of(tid)) * EB;
+#pragma unroll
+        for (int t = 0; t < PL; ++t)
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const char* p = chunk + t * G::PACK_PLANE + off + j * G::KT * EB;
+                if constexpr (WPR == 4) {
+                    const u4 v = *reinterpret_cast<const u4*>(p);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) w[t][j][u] = v[u];
+                } else {
+                    const u2 v = *reinterpret_cast<const u2*>(p);
+                    w[t][j][0] = v[0];
+                    w[t][j][1] = v[1];
+                }
+            }
+    }
+
+    __device__ __forceinline__ void store_pack(char* __restrict__ chunk, int tid) const
+    {
+        const int off = (x0_of(tid) * G::KT + p0_of(tid)) * EB;
+#pragma unroll
+        for (int t = 0; t < PL; ++t)
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                char* p = chunk + t * G::PACK_PLANE + off + j * G::KT * EB;
+                if constexpr (WPR == 4) {
+                    *reinterpret_cast<u4*>(p) = u4{w[t][j][0], w[t][j][1], w[t][j][2], w[t][j][3]};
+                } else {
+                    *reinterpret_cast<u2*>(p) = u2{w[t][j][0], w[t][j][1]};
+                }
+            }
+    }
+
+    __device__ __forceinline__ void store_lds(char* lds, int tid) const
+    {
+        const int off = x0_of(tid) * G::PITCH + p0_of(tid) * EB;
+#pragma unroll
+        for (int t = 0; t < PL; ++t)
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                char* p = lds + t * G::LDS_PLANE + off + j * G::PITCH;
+                if constexpr (WPR == 4) {
+                    *reinterpret_cast<u4*>(p) = u4{w[t][j][0], w[t][j][1], w[t][j][2], w[t][j][3]};
+                } else {
+                    *reinterpret_cast<u2*>(p) = u2{w[t][j][0], w[t][j][1]};
+                }
+            }
+    }
+};
+
+struct MxParams {
+    const char* A; const char* B; char* C;
+    int64_t a_ld, b_ld, ldc;        // in elements
+    int64_t M, N, K;
+    float alpha, beta;
+    const float* a_scale; const float* b_scale;
+    char* apack; char* bpack;
+    int64_t apack_copy, bpack_copy;  // bytes per copy
+    uint64_t* aflag; uint64_t* bflag; uint64_t* aclaim; uint64_t* bclaim;
+    unsigned long long* stats;
+    uint64_t epoch;
+    int tilesM, tilesN, nK, group_m;
+    int mode, pack_a, pack_b, no_publish, do_stats, order;
+    int a_vec, b_vec;                // unpacked vector loads allowed (dword alignment)
+    int c_bf16;
+};
+
+// One MFMA k-substep on LDS buffers la (A-side rows) and lb (B-side rows).
+// Fragment of a 16 x 16 block: lane l supplies row l%16 and a contiguous run
+// of k (8 bf16 = 16 bytes, or 32 fp8 bytes) starting at run (l/16); A and B
+// use the same k assignment, which is all the product needs.  Output item r
+// of lane l is C[4*(l/16) + r][l%16].
+template <int FORM>
+struct Mma {
+    typedef Geo<FORM> G;
+    static constexpr int NACC = (FORM == kMxX3 || FORM == kMxX3Fast) ? 2 : 1;
+
+    __device__ __forceinline__ static void step(const char* la, const char* lb, int lane,
+                                                f4 (&acc)[NACC][FB][FB])
+    {
+        const int row = lane & 15, run = lane >> 4;
+        if constexpr (FORM == kMxFP8) {
+            i8v fa[FB], fb[FB];
+#pragma unroll
+            for (int a = 0; a < FB; ++a)
+                fa[a] = *reinterpret_cast<const i8v*>(la + (a * 16 + row) * G::PITCH + run * 32);
+#pragma unroll
+            for (int b = 0; b < FB; ++b)
+                fb[b] = *reinterpret_cast<const i8v*>(lb + (b * 16 + row) * G::PITCH + run * 32);
+#pragma unroll
+            for (int a = 0; a < FB; ++a)
+#pragma unroll
+                for (int b = 0; b < FB; ++b)
+                    acc[0][a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                        fa[a], fb[b], acc[0][a][b], 0, 0, 0, 0, 0, 0);
+        } else if constexpr (FORM == kMxBF16) {
+#pragma unroll
+            for (int s = 0; s < G::KT / 32; ++s) {
+                bf8v fa[FB], fb[FB];
+#pragma unroll
+                for (int a = 0; a < FB; ++a)
+                    fa[a] = *reinterpret_cast<const bf8v*>(la + (a * 16 + row) * G::PITCH +
+                                                           (s * 32 + run * 8) * 2);
+#pragma unroll
+                for (int b = 0; b < FB; ++b)
+                    fb[b] = *reinterpret_cast<const bf8v*>(lb + (b * 16 + row) * G::PITCH +
+                                                           (s * 32 + run * 8) * 2);
+#pragma unroll
+                for (int a = 0; a < FB; ++a)
+#pragma unroll
+                    for (int b = 0; b < FB; ++b)
+                        acc[0][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b],
+                                                                               acc[0][a][b], 0, 0, 0);
+            }
+        } else {
+            // split forms: KT = 32, one substep; planes PL of each operand
+            constexpr int PL = G::PL;
+            bf8v fb[PL][FB];
+#pragma unroll
+            for (int t = 0; t < PL; ++t)
+#pragma unroll
+                for (int b = 0; b < FB; ++b)
+                    fb[t][b] = *reinterpret_cast<const bf8v*>(lb + t * G::LDS_PLANE +
+                                                              (b * 16 + row) * G::PITCH + run * 16);
+#pragma unroll
+            for (int a = 0; a < FB; ++a) {
+                bf8v fa[PL];
+#pragma unroll
+                for (int t = 0; t < PL; ++t)
+                    fa[t] = *reinterpret_cast<const bf8v*>(la + t * G::LDS_PLANE +
+                                                           (a * 16 + row) * G::PITCH + run * 16);
+#pragma unroll
+                for (int b = 0; b < FB; ++b) {
+                    f4 big = acc[0][a][b], small = acc[1][a][b];
+                    big = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0], fb[0][b], big, 0, 0, 0);
+                    small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0], fb[1][b], small, 0, 0, 0);
+                    small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1], fb[0][b], small, 0, 0, 0);
+                    if constexpr (PL == 3) {
+                        small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0], fb[2][b], small, 0, 0, 0);
+                        small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1], fb[1][b], small, 0, 0, 0);
+                        small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2], fb[0][b], small, 0, 0, 0);
+                    }
+                    acc[0][a][b] = big;
+                    acc[1][a][b] = small;
+                }
+            }
+        }
+    }
+};
+
+template <int FORM, bool AKC, bool BKC>
+__global__ void __launch_bounds__(NTHR, (FORM == kMxBF16 || FORM == kMxFP8) ? 2 : 1)
+gemm_mx_kernel(const MxParams P)
+{
+    typedef Geo<FORM> G;
+    typedef Stage<FORM, AKC> StA;
+    typedef Stage<FORM, BKC> StB;
+    typedef typename Form<FORM>::S S;
+    constexpr int KT = G::KT, SB = G::SB;
+    constexpr int NACC = Mma<FORM>::NACC;
+
+    __shared__ __attribute__((aligned(16))) char sA[2][G::LDS_OPERAND];
+    __shared__ __attribute__((aligned(16))) char sB[2][G::LDS_OPERAND];
+    __shared__ int s_role;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    int tm, tn;
+    tile_coords(blockIdx.x, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
+    const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * MT;
+    const int nK = P.nK;
+    const int nKfull = (int)(P.K / KT);
+    const uint64_t epoch = P.epoch;
+
+    // Unpacked sources: this thread's element (x0, p0) of chunk 0, and the
+    // byte step from one chunk to the next.
+    const bool a_in = P.a_vec && x0a + MT <= P.M, b_in = P.b_vec && x0b + MT <= P.N;
+    const int64_t a_ldb = P.a_ld * SB, b_ldb = P.b_ld * SB;
+    const char* a_src = P.A + (AKC ? (x0a + StA::x0_of(tid)) * a_ldb + StA::p0_of(tid) * SB
+                                   : (x0a + StA::x0_of(tid)) * SB + StA::p0_of(tid) * a_ldb);
+    const char* b_src = P.B + (BKC ? (x0b + StB::x0_of(tid)) * b_ldb + StB::p0_of(tid) * SB
+                                   : (x0b + StB::x0_of(tid)) * SB + StB::p0_of(tid) * b_ldb);
+    const int64_t a_step = AKC ? (int64_t)KT * SB : (int64_t)KT * a_ldb;
+    const int64_t b_step = BKC ? (int64_t)KT * SB : (int64_t)KT * b_ldb;
+
+    const bool consume = P.mode == kModeConsumePacked;
+    bool fused = P.mode == kModeFused;
+    int copy = 0;
+    if (fused) {
+        const unsigned x = xcc_id();
+        if (x < (unsigned)kCopies) copy = (int)x;
+        else fused = false;
+    }
+    const bool useA = fused && P.pack_a, useB = fused && P.pack_b;
+    char* apanel = nullptr;
+    char* bpanel = nullptr;
+    if (useA || consume) apanel = P.apack + copy * P.apack_copy + (int64_t)tm * nK * G::PACK_CHUNK;
+    if (useB || consume) bpanel = P.bpack + copy * P.bpack_copy + (int64_t)tn * nK * G::PACK_CHUNK;
+    uint64_t* adone = useA ? P.aflag + (int64_t)copy * P.tilesM + tm : nullptr;
+    uint64_t* bdone = useB ? P.bflag + (int64_t)copy * P.tilesN + tn : nullptr;
+    auto load_flag = [&](const uint64_t* f) -> uint64_t {
+        return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+
+    // First touch claims the panel (Sec. 3.2); thread 0 claims, the role is
+    // broadcast because every thread stores its share of each packed chunk.
+    if (tid == 0) {
+        int role = 0;
+        if (useA && __hip_atomic_exchange(P.aclaim + copy * P.tilesM + tm, epoch, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) != epoch)
+            role |= 1;
+        if (useB && __hip_atomic_exchange(P.bclaim + copy * P.tilesN + tn, epoch, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) != epoch)
+            role |= 2;
+        s_role = role;
+    }
+    __syncthreads();
+    const bool prodA = s_role & 1, prodB = s_role & 2;
+    const bool producer = prodA || prodB;
+    const bool wantA = useA && !prodA, wantB = useB && !prodB;
+
+    constexpr int REPOLL = 8;
+    bool apk = consume, bpk = consume;
+    {
+        const uint64_t fa = wantA ? load_flag(adone) : 0, fb = wantB ? load_flag(bdone) : 0;
+        apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
+        bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+    }
+
+    unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_polls = 0;
+    StA ra;
+    StB rb;
+    auto load_chunks = [&](int c) {
+        const bool kin = c < nKfull;
+        if (apk) ra.load_packed(apanel + (int64_t)c * G::PACK_CHUNK, tid);
+        else if (a_in && kin) ra.load_full(a_src + (int64_t)c * a_step, a_ldb);
+        else ra.load_edge(reinterpret_cast<const S*>(P.A), P.a_ld, P.M, P.K, x0a, (int64_t)c * KT, tid);
+        if (bpk) rb.load_packed(bpanel + (int64_t)c * G::PACK_CHUNK, tid);
+        else if (b_in && kin) rb.load_full(b_src + (int64_t)c * b_step, b_ldb);
+        else rb.load_edge(reinterpret_cast<const S*>(P.B), P.b_ld, P.N, P.K, x0b, (int64_t)c * KT, tid);
+        if (P.do_stats && tid == 0) {
+            n_prod += (int)prodA + (int)prodB;
+            n_pk += (int)(wantA && apk) + (int)(wantB && bpk) + (consume ? 2 : 0);
+            n_unpk += (int)(wantA && !apk) + (int)(wantB && !bpk);
+        }
+    };
+
+    f4 acc[NACC][FB][FB];
+#pragma unroll
+    for (int t = 0; t < NACC; ++t)
+#pragma unroll
+        for (int a = 0; a < FB; ++a)
+#pragma unroll
+            for (int b = 0; b < FB; ++b) acc[t][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+    load_chunks(0);
+    ra.store_lds(sA[0], tid);
+    rb.store_lds(sB[0], tid);
+    if (prodA) ra.store_pack(apanel, tid);
+    if (prodB) rb.store_pack(bpanel, tid);
+    __syncthreads();
+
+    for (int q = 0; q < nK; ++q) {
+        const int cur = q & 1;
+        const bool more = q + 1 < nK;
+        const bool poll = ((wantA && !apk) || (wantB && !bpk)) && q % REPOLL == REPOLL - 1;
+        uint64_t fa = 0, fb = 0;
+        if (poll) {
+            if (wantA && !apk) fa = load_flag(adone);
+            if (wantB && !bpk) fb = load_flag(bdone);
+        }
+        if (more) load_chunks(q + 1);
+        Mma<FORM>::step(sA[cur] + wm * WT * G::PITCH, sB[cur] + wn * WT * G::PITCH, lane, acc);
+        if (more) {
+            ra.store_lds(sA[cur ^ 1], tid);
+            rb.store_lds(sB[cur ^ 1], tid);
+            if (prodA) ra.store_pack(apanel + (int64_t)(q + 1) * G::PACK_CHUNK, tid);
+            if (prodB) rb.store_pack(bpanel + (int64_t)(q + 1) * G::PACK_CHUNK, tid);
+        }
+        if (poll) {
+            apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
+            bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+            if (P.do_stats && tid == 0) ++n_polls;
+        }
+        __syncthreads();
+    }
+
+    if (producer) {
+        wait_all_memory();
+        __syncthreads();
+        if (tid == 0 && !P.no_publish) {
+            if (prodA) __hip_atomic_store(adone, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prodB) __hip_atomic_store(bdone, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (P.do_stats && tid == 0) {
+        atomicAdd(P.stats + 0, n_prod);
+        atomicAdd(P.stats + 1, n_pk);
+        atomicAdd(P.stats + 2, n_unpk);
+        atomicAdd(P.stats + 3, n_polls);
+    }
+
+    // Epilogue: item r of lane l of block (a, b) is C[r0 + 4*(l/16) + r][c0 + l%16]:
+    // four consecutive rows of one column of the column-major C.  FP8 scales:
+    // the stored codes are x*s, so the product is divided by s_row * s_col
+    // (powers of two, applied one factor at a time: exact).
+    const float alpha = P.alpha, beta = P.beta;
+    const int64_t r0w = x0a + wm * WT, c0w = x0b + wn * WT;
+    const bool c_in = x0a + MT <= P.M && x0b + MT <= P.N;
+#pragma unroll
+    for (int a = 0; a < FB; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b) {
+            const int64_t i0 = r0w + a * 16 + 4 * (lane >> 4), j = c0w + b * 16 + (lane & 15);
+            f4 v = acc[0][a][b];
+            if constexpr (NACC == 2) v = acc[1][a][b] + v;  // small terms first, then x0*y0
+            float ib = 1.f;
+            if (FORM == kMxFP8 && P.b_scale != nullptr && j < P.N) ib = 1.f / P.b_scale[j];
+            if (P.c_bf16) {
+                uint16_t* cp = reinterpret_cast<uint16_t*>(P.C) + j * P.ldc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = i0 + r;
+                    if (c_in || (i < P.M && j < P.N)) {
+                        float t = v[r];
+                        if (FORM == kMxFP8 && P.a_scale != nullptr) t = t * (1.f / P.a_scale[i]);
+                        t = t * ib;
+                        const float c = beta != 0.f ? bf16_float(cp[i]) : 0.f;
+                        const float o = beta != 0.f ? axpby(alpha, t, beta, c) : alpha * t;
+                        cp[i] = (uint16_t)bf16_bits(o);
+                    }
+                }
+            } else {
+                float* cp = reinterpret_cast<float*>(P.C) + j * P.ldc;
+                if (c_in) {
+                    f4 c = f4{0.f, 0.f, 0.f, 0.f};
+                    if (beta != 0.f) {
+                        const u4 cu = *reinterpret_cast<const u4a*>(cp + i0);
+                        c = f4{__uint_as_float(cu[0]), __uint_as_float(cu[1]),
+                               __uint_as_float(cu[2]), __uint_as_float(cu[3])};
+                    }
+                    u4 o;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float t = v[r];
+                        if (FORM == kMxFP8 && P.a_scale != nullptr) t = t * (1.f / P.a_scale[i0 + r]);
+                        t = t * ib;
+                        o[r] = __float_as_uint(beta != 0.f ? axpby(alpha, t, beta, c[r]) : alpha * t);
+                    }
+                    *reinterpret_cast<u4a*>(cp + i0) = o;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t i = i0 + r;
+                        if (i < P.M && j < P.N) {
+                            float t = v[r];
+                            if (FORM == kMxFP8 && P.a_scale != nullptr) t = t * (1.f / P.a_scale[i]);
+                            t = t * ib;
+                            cp[i] = beta != 0.f ? axpby(alpha, t, beta, cp[i]) : alpha * t;
+                        }
+                    }
+                }
+            }
+        }
+}
+
+// Standalone pack of both operands into copy 0 (pack-then-compute baseline):
+// one chunk per workgroup, same registers and stores as a producer.
+template <int FORM, bool AKC, bool BKC>
+__global__ void __launch_bounds__(NTHR) pack_mx_kernel(const MxParams P)
+{
+    typedef Geo<FORM> G;
+    typedef typename Form<FORM>::S S;
+    const int tid = threadIdx.x;
+    const int nK = P.nK;
+    const int64_t nA = (int64_t)P.tilesM * nK;
+    const int64_t b = blockIdx.x;
+    if (b < nA) {
+        const int64_t t = b / nK, q = b % nK;
+        Stage<FORM, AKC> r;
+        r.load_edge(reinterpret_cast<const S*>(P.A), P.a_ld, P.M, P.K, t * MT, q * G::KT, tid);
+        r.store_pack(P.apack + (t * nK + q) * G::PACK_CHUNK, tid);
+    } else {
+        const int64_t bb = b - nA;
+        const int64_t t = bb / nK, q = bb % nK;
+        Stage<FORM, BKC> r;
+        r.load_edge(reinterpret_cast<const S*>(P.B), P.b_ld, P.N, P.K, t * MT, q * G::KT, tid);
+        r.store_pack(P.bpack + (t * nK + q) * G::PACK_CHUNK, tid);
+    }
+}
+
+// C := beta*C for the alpha = 0 / k = 0 quick path.
+__global__ void __launch_bounds__(256) scale_mx_kernel(char* C, int c_bf16, int64_t M, int64_t N,
+                                                       int64_t ldc, float beta)
+{
+    const int64_t total = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t i = idx % M, j = idx / M;
+        if (c_bf16) {
+            uint16_t* p = reinterpret_cast<uint16_t*>(C) + i + j * ldc;
+            *p = beta == 0.f ? (uint16_t)0 : (uint16_t)bf16_bits(beta * bf16_float(*p));
+        } else {
+            float* p = reinterpret_cast<float*>(C) + i + j * ldc;
+            *p = beta == 0.f ? 0.f : beta * *p;
+        }
+    }
+}
+
+// ---- FP8 E4M3 quantization ---------------------------------------------------
+// E4M3 code of a binary32 (OCP "FN": bias 7, no infinities, 0x7F NaN, largest
+// finite 448): round to nearest even on the bit pattern, saturating at 448.
+__device__ __forceinline__ uint32_t e4m3_code(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    const uint32_t a = u & 0x7FFFFFFFu;
+    if (a > 0x7F800000u) return 0x7Fu;                    // NaN
+    if (a > 0x43E00000u) return sign | 0x7Eu;             // |v| > 448: saturate
+    const int e = (int)(a >> 23) - 127;
+    if (e >= -6) {
+        // normal range: keep 3 fraction bits, ties to even; a carry moves into
+        // the exponent field by itself
+        const uint32_t r = (a + 0x7FFFFu + ((a >> 20) & 1u)) >> 20;
+        uint32_t code = r - ((127u - 7u) << 3);
+        if (code > 0x7Eu) code = 0x7Eu;
+        return sign | code;
+    }
+    // below 2^-6: multiples of 2^-9 (code m = value / 2^-9, m = 8 is 2^-6)
+    if (a < 0x00800000u) return sign;                     // binary32 subnormal: rounds to 0
+    const uint32_t mant = (a & 0x7FFFFFu) | 0x800000u;    // value = mant * 2^(e - 23)
+    const int sh = 14 - e;                                // value / 2^-9 = mant >> sh
+    if (sh > 24) return sign;                             // below 2^-10 ... actually < half unit
+    uint32_t m = mant >> sh;
+    const uint32_t rem = mant & ((1u << sh) - 1u), half = 1u << (sh - 1);
+    if (rem > half || (rem == half && (m & 1u))) ++m;
+    return sign | m;
+}
+
+// Exponent e of the line scale 2^e: the largest e with amax * 2^e <= 448
+// (448 = 0.875 * 2^9); 0 when amax is 0, not finite; clamped to [-126, 126].
+__device__ __forceinline__ int fp8_scale_exp(float amax)
+{
+    if (!(amax > 0.f) || !(amax < __builtin_huge_valf())) return 0;
+    int E;
+    const float f = frexpf(amax, &E);   // amax = f * 2^E, f in [0.5, 1)
+    int e = (f <= 0.875f ? 9 : 8) - E;
+    return e < -126 ? -126 : e > 126 ? 126 : e;
+}
+
+// Pass 1: zero the per-line maxima (bit patterns of |x|, stored in scales).
+__global__ void __launch_bounds__(256) fp8_zero_kernel(uint32_t* amax, int64_t lines)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < lines; i += (int64_t)gridDim.x * 256)
+        amax[i] = 0u;
+}
+
+// Pass 2: per-line max of |x| by atomic max on the bit pattern (monotone for
+// non-negative binary32); NaNs are skipped.  Threads walk the stored matrix in
+// storage order (coalesced).
+__global__ void __launch_bounds__(256) fp8_amax_kernel(int col, int64_t rows, int64_t cols,
+                                                       const float* X, int64_t ld, int axis,
+                                                       uint32_t* amax)
+{
+    const int64_t inner = col ? rows : cols, outer = col ? cols : rows;
+    const int64_t total = inner * outer;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t in = idx % inner, out = idx / inner;
+        const int64_t r = col ? in : out, c = col ? out : in;
+        const uint32_t a = __float_as_uint(X[in + out * ld]) & 0x7FFFFFFFu;
+        if (a > 0x7F800000u || a == 0u) continue;
+        atomicMax(amax + (axis == 0 ? r : c), a);
+    }
+}
+
+// Pass 3: quantize every element with its line's scale.
+__global__ void __launch_bounds__(256) fp8_quant_kernel(int col, int64_t rows, int64_t cols,
+                                                        const float* X, int64_t ld, int axis,
+                                                        const uint32_t* amax, uint8_t* Q,
+                                                        int64_t ldq)
+{
+    const int64_t inner = col ? rows : cols, outer = col ? cols : rows;
+    const int64_t total = inner * outer;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t in = idx % inner, out = idx / inner;
+        const int64_t r = col ? in : out, c = col ? out : in;
+        const int e = fp8_scale_exp(__uint_as_float(amax[axis == 0 ? r : c]));
+        Q[in + out * ldq] = (uint8_t)e4m3_code(ldexpf(X[in + out * ld], e));
+    }
+}
+
+// Pass 4: turn each line's maximum into its scale 2^e, in place.
+__global__ void __launch_bounds__(256) fp8_scale_kernel(uint32_t* amax_scale, int64_t lines)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < lines; i += (int64_t)gridDim.x * 256) {
+        const int e = fp8_scale_exp(__uint_as_float(amax_scale[i]));
+        amax_scale[i] = __float_as_uint(ldexpf(1.f, e));
+    }
+}
+
+unsigned grid_for(int64_t total)
+{
+    int64_t b = (total + 255) / 256;
+    if (b > 16384) b = 16384;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+MxParams make_mx_params(const MxLaunchDesc& d)
+{
+    const int KT = mx_kt(d.form), SB = mx_src_bytes(d.form);
+    MxParams P{};
+    P.A = static_cast<const char*>(d.A);
+    P.B = static_cast<const char*>(d.B);
+    P.C = static_cast<char*>(d.C);
+    P.a_ld = d.a_ld; P.b_ld = d.b_ld; P.ldc = d.ldc;
+    P.M = d.M; P.N = d.N; P.K = d.K;
+    P.alpha = d.alpha; P.beta = d.beta;
+    P.a_scale = d.a_scale; P.b_scale = d.b_scale;
+    P.apack = static_cast<char*>(d.apack); P.bpack = static_cast<char*>(d.bpack);
+    P.apack_copy = d.apack_copy_bytes; P.bpack_copy = d.bpack_copy_bytes;
+    P.aflag = d.aflag; P.bflag = d.bflag; P.aclaim = d.aclaim; P.bclaim = d.bclaim;
+    P.stats = d.stats_ptr;
+    P.epoch = d.epoch;
+    P.tilesM = (int)((d.M + MT - 1) / MT);
+    P.tilesN = (int)((d.N + MT - 1) / MT);
+    P.nK = (int)((d.K + KT - 1) / KT);
+    P.group_m = 8;
+    P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
+    P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
+    P.order = d.order;
+    // vector loads of the unpacked operand need every 4-byte group of a
+    // micro-block row (K-major) or column (MN-major) dword aligned: the base
+    // and the leading dimension in bytes must be multiples of 4
+    P.a_vec = ((uintptr_t)d.A % 4 == 0) && ((d.a_ld * SB) % 4 == 0);
+    P.b_vec = ((uintptr_t)d.B % 4 == 0) && ((d.b_ld * SB) % 4 == 0);
+    P.c_bf16 = d.c_bf16;
+    return P;
+}
+
+template <int FORM>
+hipError_t launch_form(const MxLaunchDesc& d, bool pack)
+{
+    const MxParams P = make_mx_params(d);
+    const bool akc = d.a_kmajor, bkc = d.b_kmajor;
+    const dim3 block(NTHR);
+    if (!pack) {
+        const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN));
+        if (!akc && !bkc) gemm_mx_kernel<FORM, false, false><<<grid, block, 0, d.stream>>>(P);
+        else if (!akc && bkc) gemm_mx_kernel<FORM, false, true><<<grid, block, 0, d.stream>>>(P);
+        else if (akc && !bkc) gemm_mx_kernel<FORM, true, false><<<grid, block, 0, d.stream>>>(P);
+        else gemm_mx_kernel<FORM, true, true><<<grid, block, 0, d.stream>>>(P);
+    } else {
+        const dim3 grid((unsigned)(((int64_t)P.tilesM + P.tilesN) * P.nK));
+        if (!akc && !bkc) pack_mx_kernel<FORM, false, false><<<grid, block, 0, d.stream>>>(P);
+        else if (!akc && bkc) pack_mx_kernel<FORM, false, true><<<grid, block, 0, d.stream>>>(P);
+        else if (akc && !bkc) pack_mx_kernel<FORM, true, false><<<grid, block, 0, d.stream>>>(P);
+        else pack_mx_kernel<FORM, true, true><<<grid, block, 0, d.stream>>>(P);
+    }
+    return hipGetLastError();
+}
+
+hipError_t dispatch_mx(const MxLaunchDesc& d, bool pack)
+{
+    switch (d.form) {
+    case kMxBF16: return launch_form<kMxBF16>(d, pack);
+    case kMxFP8: return launch_form<kMxFP8>(d, pack);
+    case kMxX3: return launch_form<kMxX3>(d, pack);
+    case kMxX3Fast: return launch_form<kMxX3Fast>(d, pack);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gemm_mx(const MxLaunchDesc& d) { return dispatch_mx(d, false); }
+
+hipError_t launch_pack_mx(const MxLaunchDesc& d) { return dispatch_mx(d, true); }
+
+hipError_t launch_scale_mx(int c_bf16, int64_t M, int64_t N, void* C, int64_t ldc, float beta,
+                           hipStream_t stream)
+{
+    scale_mx_kernel<<<dim3(grid_for(M * N)), dim3(256), 0, stream>>>(static_cast<char*>(C), c_bf16,
+                                                                      M, N, ldc, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize_fp8(int layout_col, int64_t rows, int64_t cols, const float* X,
+                               int64_t ldx, int axis, uint8_t* Q, int64_t ldq, float* scales,
+                               hipStream_t stream)
+{
+    const int64_t lines = axis == 0 ? rows : cols;
+    uint32_t* amax = reinterpret_cast<uint32_t*>(scales);
+    fp8_zero_kernel<<<dim3(grid_for(lines)), dim3(256), 0, stream>>>(amax, lines);
+    fp8_amax_kernel<<<dim3(grid_for(rows * cols)), dim3(256), 0, stream>>>(layout_col, rows, cols,
+                                                                           X, ldx, axis, amax);
+    fp8_quant_kernel<<<dim3(grid_for(rows * cols)), dim3(256), 0, stream>>>(
+        layout_col, rows, cols, X, ldx, axis, amax, Q, ldq);
+    fp8_scale_kernel<<<dim3(grid_for(lines)), dim3(256), 0, stream>>>(amax, lines);
+    return hipGetLastError();
+}
+
+}  // namespace fip

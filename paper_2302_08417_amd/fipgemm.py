@@ -22,7 +22,8 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 FIP_COL_MAJOR, FIP_ROW_MAJOR = 0, 1
-FIP_F64, FIP_F32 = 0, 1
+FIP_F64, FIP_F32, FIP_BF16, FIP_E4M3, FIP_BF16X3, FIP_BF16X3_FAST = 0, 1, 2, 3, 4, 5
+MX_FORMS = (FIP_BF16, FIP_E4M3, FIP_BF16X3, FIP_BF16X3_FAST)
 FIP_ERR_HANDLE, FIP_ERR_WORKSPACE, FIP_ERR_LAUNCH, FIP_ERR_UNSUPPORTED, FIP_ERR_ALLOC = -1, -2, -3, -4, -5
 FIP_ATTR_PACK_POLICY, FIP_ATTR_TILE, FIP_ATTR_NO_PUBLISH, FIP_ATTR_STATS, FIP_ATTR_EPOCH = 1, 2, 3, 4, 5
 FIP_ATTR_ORDER = 7
@@ -68,6 +69,9 @@ _SIGS = {
                   ctypes.c_float, _vp, _i64],
     "fip_pack": [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _ch, _vp, _i64, _ch],
     "fip_xcc_map": [_vp, _vp, _i64],
+    "fip_gemm_mx": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64,
+                    _ch, ctypes.c_float, _vp, _i64, _i32, _vp, _vp],
+    "fip_quantize_fp8": [_vp, _i32, _i64, _i64, _vp, _i64, _i32, _vp, _i64, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -160,6 +164,18 @@ def fip_xcc_map(h, out, nblocks):
     return _lib.fip_xcc_map(h, _addr(out), nblocks)
 
 
+def fip_gemm_mx(h, dtype, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc,
+                c_type, a_scale=None, b_scale=None):
+    return _lib.fip_gemm_mx(h, dtype, layout, m, n, k, alpha, _addr(A), lda, _trans(transA),
+                            _addr(B), ldb, _trans(transB), beta, _addr(C), ldc, c_type,
+                            _addr(a_scale), _addr(b_scale))
+
+
+def fip_quantize_fp8(h, layout, rows, cols, X, ldx, axis, Q, ldq, scales):
+    return _lib.fip_quantize_fp8(h, layout, rows, cols, _addr(X), ldx, axis, _addr(Q), ldq,
+                                 _addr(scales))
+
+
 # ---- convenience handle (torch owns the workspace and the stream) ----------------------
 
 class Handle:
@@ -235,9 +251,26 @@ class Handle:
         rc = fn(self.h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc)
         self._check(fn.__name__, rc)
 
-    def pack(self, layout, m, n, k, A, lda, transA, B, ldb, transB):
+    def gemm_mx(self, dtype, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C,
+                ldc, a_scale=None, b_scale=None):
+        """Mixed-precision form dtype (FIP_BF16 .. FIP_BF16X3_FAST); C binary32 or bfloat16."""
         import torch
-        dt = FIP_F64 if A.dtype == torch.float64 else FIP_F32
+        c_type = FIP_BF16 if C.dtype == torch.bfloat16 else FIP_F32
+        p = self.plan(dtype, layout, m, n, k, transA, transB)
+        self.ensure_workspace(p.workspace_bytes)
+        self.bind_stream()
+        self._check("fip_gemm_mx", fip_gemm_mx(self.h, dtype, layout, m, n, k, alpha, A, lda,
+                                               transA, B, ldb, transB, beta, C, ldc, c_type,
+                                               a_scale, b_scale))
+
+    def quantize_fp8(self, layout, rows, cols, X, ldx, axis, Q, ldq, scales):
+        self.bind_stream()
+        self._check("fip_quantize_fp8", fip_quantize_fp8(self.h, layout, rows, cols, X, ldx, axis,
+                                                         Q, ldq, scales))
+
+    def pack(self, layout, m, n, k, A, lda, transA, B, ldb, transB, dtype=None):
+        import torch
+        dt = dtype if dtype is not None else (FIP_F64 if A.dtype == torch.float64 else FIP_F32)
         old = self.get_attr(FIP_ATTR_PACK_POLICY)
         self.set_attr(FIP_ATTR_PACK_POLICY, FIP_PACK_CONSUME_ONLY)
         p = self.plan(dt, layout, m, n, k, transA, transB)

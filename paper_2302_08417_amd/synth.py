@@ -131,3 +131,98 @@ def sample_entries(m: int, n: int, count: int, seed: int):
         pts.add((int(g.integers(0, m)), int(g.integers(0, n))))
     arr = np.array(sorted(pts), dtype=np.int64)
     return arr[:, 0].copy(), arr[:, 1].copy()
+
+
+# ---------------------------------------------------------------------------
+# Mixed-precision operands.  Entries are U[-1, 1] with every row of op(A) and
+# every column of op(B) scaled by 2^u, u ~ U[-8, 8] (rows and columns of very
+# different magnitude).  Operand storage: bfloat16 bit patterns (uint16),
+# E4M3 codes (uint8) or binary32, with NaN patterns in the ld padding.
+# Conversions to the stored formats use torch's CPU casts (input preparation
+# only; the library and the oracle each implement their own).
+
+FORM_BF16, FORM_E4M3, FORM_BF16X3, FORM_BF16X3_FAST = 2, 3, 4, 5
+BF16_NAN, E4M3_NAN = 0x7FC0, 0x7F
+
+
+@dataclass
+class MxCase:
+    form: int
+    layout: int
+    m: int
+    n: int
+    k: int
+    transA: str
+    transB: str
+    lda: int
+    ldb: int
+    ldc: int
+    alpha: float
+    beta: float
+    A: np.ndarray          # stored operand (uint16 bits, uint8 codes or float32)
+    B: np.ndarray
+    C: np.ndarray          # float32, or uint16 bfloat16 bits when c_bf16
+    c_bf16: bool
+    a_scale: np.ndarray    # E4M3: power-of-two scale per row of op(A) (float32), else None
+    b_scale: np.ndarray    # E4M3: per column of op(B), else None
+    A32: np.ndarray        # binary32 values the operand was made from (same storage)
+    B32: np.ndarray
+
+
+def _to_bf16_bits(x: np.ndarray) -> np.ndarray:
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().view(np.uint16)
+
+
+def _to_e4m3_codes(x: np.ndarray) -> np.ndarray:
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.float8_e4m3fn)
+    return t.view(torch.uint8).numpy()
+
+
+def make_mx_case(form, layout=COL, m=64, n=64, k=64, transA="N", transB="N", ld_pad=0,
+                 alpha=1.0, beta=0.0, seed=BASE_SEED, c_bf16=False, spread=8.0) -> MxCase:
+    g = rng(seed)
+    row_exp = g.uniform(-spread, spread, size=m)   # per row of op(A)
+    col_exp = g.uniform(-spread, spread, size=n)   # per column of op(B)
+    opA = g.uniform(-1.0, 1.0, size=(m, k)) * np.exp2(row_exp)[:, None]
+    opB = g.uniform(-1.0, 1.0, size=(k, n)) * np.exp2(col_exp)[None, :]
+    a_scale = b_scale = None
+    if form == FORM_E4M3:
+        # codes of x * s with s = 2^(8 - round(u)) per line (|x * s| <= 2^8.5 < 448)
+        a_scale = np.exp2(8.0 - np.round(row_exp)).astype(np.float32)
+        b_scale = np.exp2(8.0 - np.round(col_exp)).astype(np.float32)
+        opAq = opA * a_scale[:, None]
+        opBq = opB * b_scale[None, :]
+    sa = stored_shape(transA, m, k)
+    sb = stored_shape(transB, k, n)
+    stA = opA.T if is_trans(transA) else opA
+    stB = opB.T if is_trans(transB) else opB
+    lda = min_ld(layout, *sa) + ld_pad
+    ldb = min_ld(layout, *sb) + ld_pad
+    ldc = min_ld(layout, m, n) + ld_pad
+    A32 = fill_stored(layout, sa[0], sa[1], lda, stA, np.float32)
+    B32 = fill_stored(layout, sb[0], sb[1], ldb, stB, np.float32)
+    if form == FORM_BF16:
+        A = fill_stored(layout, sa[0], sa[1], lda, _to_bf16_bits(stA).astype(np.float64),
+                        np.uint16, BF16_NAN)
+        B = fill_stored(layout, sb[0], sb[1], ldb, _to_bf16_bits(stB).astype(np.float64),
+                        np.uint16, BF16_NAN)
+    elif form == FORM_E4M3:
+        qA = opAq.T if is_trans(transA) else opAq
+        qB = opBq.T if is_trans(transB) else opBq
+        A = fill_stored(layout, sa[0], sa[1], lda, _to_e4m3_codes(qA).astype(np.float64),
+                        np.uint8, E4M3_NAN)
+        B = fill_stored(layout, sb[0], sb[1], ldb, _to_e4m3_codes(qB).astype(np.float64),
+                        np.uint8, E4M3_NAN)
+    else:
+        A, B = A32, B32
+    Cv = g.uniform(-1.0, 1.0, size=(m, n))
+    if c_bf16:
+        C = fill_stored(layout, m, n, ldc, _to_bf16_bits(Cv).astype(np.float64), np.uint16,
+                        BF16_NAN)
+    else:
+        C = fill_stored(layout, m, n, ldc, Cv, np.float32)
+    return MxCase(form, layout, m, n, k, transA, transB, lda, ldb, ldc, alpha, beta, A, B, C,
+                  c_bf16, a_scale, b_scale, A32, B32)

@@ -94,3 +94,83 @@ def check_sampled(c, Cgpu, count=4096, seed=7, tol_factor=4.0):
     slack = 2.0 * (c.n + c.k + 4) * 2.0 ** -53
     assert np.all(np.abs(cx - y) <= (tol_factor * kk * u + slack) * bnd + 1e-300), "Freivalds"
     return err / (kk * u * dmax)
+
+
+# ---------------------------------------------------------------------------
+# Mixed-precision forms
+
+MX_KT = {2: 64, 3: 128, 4: 32, 5: 32}
+U32 = 2.0 ** -24          # binary32 accumulation
+U_BF16 = 2.0 ** -8        # rounding of a bfloat16 C
+
+
+def mx_effective(form, buf, layout, trans, rows, cols, ld, scale=None, along_rows=True):
+    """binary64 buffer of the values a stored mixed-precision operand stands for: decoded
+    bits, E4M3 codes divided by their line scale (rows of op(A) / columns of op(B))."""
+    vals = oracle.mx_values(form, buf).copy()
+    if form == 3 and scale is not None:
+        v = synth.op_view(vals, layout, trans, rows, cols, ld)
+        if along_rows:
+            v /= scale.astype(np.float64)[:, None]
+        else:
+            v /= scale.astype(np.float64)[None, :]
+    return vals
+
+
+def mx_c0(c):
+    return oracle.bf16_decode(c.C) if c.c_bf16 else c.C.astype(np.float64)
+
+
+def mx_reference(c):
+    """(Cref, D) in C's storage: the product of the values the stored operands stand for
+    (for the split forms, the sum of the kept term products), in binary64."""
+    C0 = mx_c0(c)
+    if c.form in (2, 3):
+        A = mx_effective(c.form, c.A, c.layout, c.transA, c.m, c.k, c.lda, c.a_scale, True)
+        B = mx_effective(c.form, c.B, c.layout, c.transB, c.k, c.n, c.ldb, c.b_scale, False)
+        return oracle.gemm(c.layout, c.m, c.n, c.k, c.alpha, A, c.lda, c.transA, B, c.ldb,
+                           c.transB, c.beta, C0, c.ldc)
+    pa = oracle.split3(c.A)
+    pb = oracle.split3(c.B)
+    ta = [oracle.bf16_decode(pa[t]) for t in range(3)]
+    tb = [oracle.bf16_decode(pb[t]) for t in range(3)]
+    if c.form == 4:   # sum_{i+j<=2} A_i B_j = A0 (B0+B1+B2) + A1 (B0+B1) + A2 B0
+        pairs = [(ta[0], tb[0] + tb[1] + tb[2]), (ta[1], tb[0] + tb[1]), (ta[2], tb[0])]
+    else:             # sum_{i+j<=1} = A0 (B0+B1) + A1 B0
+        pairs = [(ta[0], tb[0] + tb[1]), (ta[1], tb[0])]
+    Cref = None
+    for idx, (a, b) in enumerate(pairs):
+        r, _ = oracle.gemm(c.layout, c.m, c.n, c.k, c.alpha, a, c.lda, c.transA, b, c.ldb,
+                           c.transB, c.beta if idx == 0 else 0.0, C0, c.ldc)
+        Cref = r if Cref is None else Cref + np.where(c_mask(c), r, 0.0)
+    _, D = oracle.gemm(c.layout, c.m, c.n, c.k, c.alpha, c.A32, c.lda, c.transA, c.B32, c.ldb,
+                       c.transB, c.beta, C0, c.ldc)
+    return Cref, D
+
+
+def mx_fp64_truth(c):
+    """binary64 product of the binary32 values the operands were made from."""
+    return oracle.gemm(c.layout, c.m, c.n, c.k, c.alpha, c.A32, c.lda, c.transA, c.B32, c.ldb,
+                       c.transB, c.beta, mx_c0(c), c.ldc)[0]
+
+
+def check_mx(c, Cgpu, tol_factor=4.0):
+    """Compare a mixed-precision result with the oracle: max|C - Cref| <= 4 k u32 max D
+    (+ u_bf16 max|Cref| when C is stored in bfloat16).  Returns (normalised error, error
+    against the binary64 product of the unquantized binary32 values, relative to max D)."""
+    Cref, D = mx_reference(c)
+    mask = c_mask(c)
+    outside = ~mask
+    assert Cgpu[outside].tobytes() == c.C[outside].tobytes(), "C padding was modified"
+    if not mask.any():
+        return 0.0, 0.0
+    got = (oracle.bf16_decode(Cgpu) if c.c_bf16 else Cgpu.astype(np.float64))[mask]
+    ref = Cref[mask]
+    assert np.all(np.isfinite(got)), "non-finite result"
+    dmax = float(D[mask].max())
+    err = float(np.abs(got - ref).max())
+    kk = max(c.k, 1)
+    bound = tol_factor * kk * U32 * dmax + (U_BF16 * float(np.abs(ref).max()) if c.c_bf16 else 0)
+    assert err <= bound, f"max err {err:.3e} > bound {bound:.3e} (dmax {dmax:.3e})"
+    truth = mx_fp64_truth(c)[mask]
+    return err / (kk * U32 * dmax), float(np.abs(got - truth).max()) / dmax
