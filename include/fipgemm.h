@@ -85,6 +85,10 @@ enum {
     /* Tile order inside an XCD's run: 0 = GROUP_M tiles of a column
        consecutive, 1 = consecutive tiles in distinct columns.  Default 0. */
     FIP_ATTR_ORDER = 7,
+    /* Batched calls: problems with max(m, n) <= value use 32 x 32 C tiles,
+       the others 64 x 64.  -1 (default): the value fip_vbatched_tune chose for
+       the batch's shapes, else 64. */
+    FIP_ATTR_VB_SPLIT = 8,
     /* Read only: the 64-bit epoch stamp of the most recent fused call
        (claims and publish flags of that call hold this value; stamps are
        unique within the process). */
@@ -251,6 +255,57 @@ int fip_gemm_mx(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n
  */
 int fip_quantize_fp8(fip_handle_t handle, int layout, int64_t rows, int64_t cols, const float* X,
                      int64_t ldx, int axis, uint8_t* Q, int64_t ldq, float* scales);
+
+/*
+ * Batched binary32 GEMM: count independent problems
+ *
+ *     C_i := alpha * op(A_i) * op(B_i) + beta * C_i,   i = 0 .. count-1,
+ *
+ * op(A_i) m[i] x k[i], op(B_i) k[i] x n[i], all in one persistent launch (the
+ * paper's single code path applied to a whole batch of small and uneven
+ * problems: every problem runs the unpacked tile path, Sec. 2.3 and 3.3).
+ *   m, n, k, transA, transB: HOST arrays of count entries (the planner needs
+ *     them; a batch with the same shapes reuses the plan uploaded by the
+ *     previous call).
+ *   A, B, C: DEVICE arrays of count device pointers; lda, ldb, ldc: DEVICE
+ *     arrays of count leading dimensions (not validated: they never reach the
+ *     host).  All matrices in `layout`, C distinct from A and B.
+ *   flags: 0, or FIP_VB_GRAPH: run the batch as a HIP graph, instantiated on
+ *     the first call and replayed while the call repeats with the same shapes,
+ *     pointer arrays, alpha, beta, workspace and stream.
+ * Workspace: fip_vbatched_workspace bytes (problem table, tile list, two
+ * counters that each launch leaves at zero); it must hold the plan between
+ * calls of the same batch.  A call with a new batch waits for the stream and
+ * copies the new plan in (synchronous host-to-device copies).
+ * Quick returns: count = 0, or alpha = 0 and beta = 1.  alpha = 0 reads no
+ * A, B; beta = 0 reads no C.  k[i] = 0 gives C_i := beta*C_i.
+ * Positions: layout 2, count 3, m 4, n 5, k 6, transA 7, transB 8, alpha 9,
+ * A 10, lda 11, B 12, ldb 13, beta 14, C 15, ldc 16, flags 17.
+ */
+#define FIP_VB_GRAPH 1
+int fip_vbatched_workspace(fip_handle_t handle, int layout, int64_t count, const int32_t* m,
+                           const int32_t* n, const int32_t* k, const char* transA,
+                           const char* transB, size_t* bytes);
+int fip_sgemm_vbatched(fip_handle_t handle, int layout, int64_t count, const int32_t* m,
+                       const int32_t* n, const int32_t* k, const char* transA, const char* transB,
+                       float alpha, const float* const* A, const int64_t* lda,
+                       const float* const* B, const int64_t* ldb, float beta, float* const* C,
+                       const int64_t* ldc, int flags);
+
+/*
+ * Autotuner of the batched call: times the batch (median of 3 launches after
+ * a warm-up) for each candidate FIP_ATTR_VB_SPLIT threshold (0, 16, 32, 48,
+ * 64, 96, 128, 192, 256, all), keeps the fastest for this batch's shapes in
+ * the handle (later fip_sgemm_vbatched calls with the same shapes use it) and
+ * writes it to *split_out.  It runs the batch 40 times: C is overwritten with
+ * unspecified values, so pass scratch C matrices of the same shapes.
+ * Arguments as in fip_sgemm_vbatched; position 17 is split_out.  Synchronous.
+ */
+int fip_vbatched_tune(fip_handle_t handle, int layout, int64_t count, const int32_t* m,
+                      const int32_t* n, const int32_t* k, const char* transA, const char* transB,
+                      float alpha, const float* const* A, const int64_t* lda,
+                      const float* const* B, const int64_t* ldb, float beta, float* const* C,
+                      const int64_t* ldc, int* split_out);
 
 /*
  * Diagnostic: launch nblocks one-wave workgroups; workgroup b writes the

@@ -94,6 +94,9 @@ def gemm(layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C0, ldc):
     Entries of the buffer outside the m x n matrix are copied from C0.
     """
     A64, B64, C64 = _f64(A), _f64(B), _f64(C0)
+    need = (ldc * n if layout == COL else ldc * m) if m and n else 0
+    if C64.size < need:
+        raise ValueError(f"C0 holds {C64.size} entries; the m x n result needs {need}")
     Cref = C64.copy()
     D = np.zeros_like(C64)
     rc = lib().oracle_gemm(layout, m, n, k, float(alpha), _ptr(A64), lda, _t(transA), _ptr(B64),

@@ -105,6 +105,35 @@ hipError_t launch_quantize_fp8(int layout_col, int64_t rows, int64_t cols, const
 hipError_t launch_scale_mx(int c_bf16, int64_t M, int64_t N, void* C, int64_t ldc, float beta,
                            hipStream_t stream);
 
+// ---- Batched binary32 GEMM (fipgemm_batched.hip) ----------------------------
+// One problem in kernel terms (C column-major M x N) and one tile of it.
+enum VbFlags : int32_t { kVbAKmajor = 1, kVbBKmajor = 2, kVbSwapped = 4 };
+struct VbProblem {
+    int32_t M, N, K;
+    int32_t flags;   // VbFlags: kernel A-/B-side K-major; swapped = row-major storage
+    int32_t cls;     // tile class: 1 = 64 x 64, 2 = 32 x 32
+    int32_t pad[3];
+};
+struct VbItem {
+    int32_t prob;
+    uint16_t tm, tn;
+};
+struct VbLaunchDesc {
+    const VbProblem* probs;        // device
+    const VbItem* items;           // device, in execution order
+    int64_t total;                 // number of items
+    const float* const* A; const int64_t* lda;   // caller's device arrays
+    const float* const* B; const int64_t* ldb;
+    float* const* C; const int64_t* ldc;
+    float alpha, beta;
+    uint32_t* ticket;              // device, 2 words, zero between launches
+    hipStream_t stream;
+};
+hipError_t launch_vbatched(const VbLaunchDesc& d);
+hipError_t launch_vb_zero(uint32_t* ticket, hipStream_t stream);
+hipError_t build_vbatched_graph(const VbLaunchDesc& d, hipGraphExec_t* exec);
+int vbatched_grid();   // resident workgroups of the batched kernel on the device
+
 // Enqueue the XCC-id diagnostic (one 64-thread workgroup per entry).
 hipError_t launch_xcc_map(uint32_t* out, int64_t nblocks, hipStream_t stream);
 

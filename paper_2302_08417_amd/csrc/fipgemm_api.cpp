@@ -3,11 +3,14 @@
 // layout) and kernel launches.  See include/fipgemm.h for the contract.
 #include "fipgemm.h"
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <new>
 #include <random>
 #include <string.h>
+#include <unordered_map>
+#include <vector>
 
 #include "fip_internal.h"
 
@@ -34,6 +37,26 @@ uint64_t next_epoch()
 
 }  // namespace
 
+// Batched calls: the plan uploaded to the workspace, the tile-size threshold
+// the autotuner chose per batch signature, and the graph of the last
+// repeated call.
+struct VbState {
+    uint64_t sig = 0;
+    int split = -1;
+    void* ws = nullptr;
+    int64_t total = 0;
+    int64_t off_probs = 0, off_items = 0;
+    std::vector<fip::VbProblem> probs;
+    std::vector<fip::VbItem> items;
+    std::unordered_map<uint64_t, int> tuned;
+    hipGraphExec_t exec = nullptr;
+    uint64_t gkey[12] = {};
+    ~VbState()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
 struct fip_handle_s {
     uint32_t magic;
     hipStream_t stream;
@@ -47,6 +70,8 @@ struct fip_handle_s {
     uint64_t epoch;   // stamp of the most recent fused call
     fip_plan_t last;
     int has_last;
+    int vb_split;     // FIP_ATTR_VB_SPLIT (-1: tuned or default)
+    VbState* vb;
 };
 
 namespace {
@@ -446,6 +471,176 @@ int gemm_mx_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, in
     }
 }
 
+// ---- batched binary32 GEMM ----------------------------------------------------
+
+constexpr int kVbDefaultSplit = 64;   // untuned: max(m, n) <= 64 -> 32 x 32 tiles
+constexpr int kVbMaxTiles = 65535;    // tile indices are 16-bit
+
+uint64_t fnv(uint64_t h, const void* p, size_t n)
+{
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+uint64_t vb_signature(int layout, int64_t count, const int32_t* m, const int32_t* n,
+                      const int32_t* k, const char* tA, const char* tB)
+{
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &layout, sizeof layout);
+    h = fnv(h, &count, sizeof count);
+    h = fnv(h, m, count * sizeof(int32_t));
+    h = fnv(h, n, count * sizeof(int32_t));
+    h = fnv(h, k, count * sizeof(int32_t));
+    for (int64_t i = 0; i < count; ++i) {
+        const char t[2] = {(char)is_trans(tA[i]), (char)is_trans(tB[i])};
+        h = fnv(h, t, 2);
+    }
+    return h;
+}
+
+int64_t vb_tiles(int64_t M, int64_t N, int mt) { return cdiv(M, mt) * cdiv(N, mt); }
+
+// Workspace bytes: counters, problem table, and the item list of the
+// smallest tile class for every problem (the most items any split yields).
+int64_t vb_workspace_bytes(int layout, int64_t count, const int32_t* m, const int32_t* n,
+                           int64_t* off_probs, int64_t* off_items)
+{
+    int64_t items = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const KernelShape ks = kernel_shape(layout, m[i], n[i]);
+        items += vb_tiles(ks.M, ks.N, 32);
+    }
+    int64_t off = 256;
+    *off_probs = off; off = align256(off + count * (int64_t)sizeof(fip::VbProblem));
+    *off_items = off; off = align256(off + items * (int64_t)sizeof(fip::VbItem));
+    return off;
+}
+
+int vb_check(int layout, int64_t count, const int32_t* m, const int32_t* n, const int32_t* k,
+             const char* tA, const char* tB)
+{
+    if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 2;
+    if (count < 0 || count > ((int64_t)1 << 31)) return 3;
+    if (count == 0) return 0;
+    if (m == nullptr) return 4;
+    if (n == nullptr) return 5;
+    if (k == nullptr) return 6;
+    if (tA == nullptr) return 7;
+    if (tB == nullptr) return 8;
+    for (int64_t i = 0; i < count; ++i) {
+        if (m[i] < 0 || m[i] > 32 * kVbMaxTiles) return 4;
+        if (n[i] < 0 || n[i] > 32 * kVbMaxTiles) return 5;
+        if (k[i] < 0) return 6;
+        if (!valid_trans(tA[i])) return 7;
+        if (!valid_trans(tB[i])) return 8;
+    }
+    return 0;
+}
+
+// Build the problem table and the LPT-ordered item list for a split, and copy
+// them into the workspace (after the stream has drained: an earlier batch may
+// still be reading the previous plan).
+int vb_upload(fip_handle_s* h, int layout, int64_t count, const int32_t* m, const int32_t* n,
+              const int32_t* k, const char* tA, const char* tB, uint64_t sig, int split)
+{
+    VbState& v = *h->vb;
+    int64_t off_probs, off_items;
+    vb_workspace_bytes(layout, count, m, n, &off_probs, &off_items);
+    v.probs.assign(count, fip::VbProblem{});
+    std::vector<int64_t> order(count);
+    std::vector<int64_t> cost(count);
+    for (int64_t i = 0; i < count; ++i) {
+        const KernelShape ks = kernel_shape(layout, m[i], n[i]);
+        fip::VbProblem& p = v.probs[i];
+        p.M = (int32_t)ks.M; p.N = (int32_t)ks.N; p.K = k[i];
+        const bool a_mn = mn_major(false, layout, tA[i]), b_mn = mn_major(true, layout, tB[i]);
+        const bool akm = ks.swapped ? !b_mn : !a_mn, bkm = ks.swapped ? !a_mn : !b_mn;
+        p.flags = (akm ? fip::kVbAKmajor : 0) | (bkm ? fip::kVbBKmajor : 0) |
+                  (ks.swapped ? fip::kVbSwapped : 0);
+        p.cls = std::max(ks.M, ks.N) <= split ? 2 : 1;
+        const int mt = p.cls == 1 ? 64 : 32;
+        cost[i] = (cdiv(k[i], 32) + 1) * mt * mt;   // one tile's k-steps plus its epilogue
+        order[i] = i;
+    }
+    // longest tiles first; a problem's tiles stay together
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    v.items.clear();
+    for (int64_t oi = 0; oi < count; ++oi) {
+        const int64_t i = order[oi];
+        const fip::VbProblem& p = v.probs[i];
+        const int mt = p.cls == 1 ? 64 : 32;
+        const int64_t tm_n = cdiv(p.M, mt), tn_n = cdiv(p.N, mt);
+        for (int64_t tn = 0; tn < tn_n; ++tn)
+            for (int64_t tm = 0; tm < tm_n; ++tm)
+                v.items.push_back(fip::VbItem{(int32_t)i, (uint16_t)tm, (uint16_t)tn});
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return FIP_ERR_LAUNCH;
+    char* ws = static_cast<char*>(h->ws);
+    if (count > 0 &&
+        hipMemcpy(ws + off_probs, v.probs.data(), count * sizeof(fip::VbProblem),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return FIP_ERR_LAUNCH;
+    if (!v.items.empty() &&
+        hipMemcpy(ws + off_items, v.items.data(), v.items.size() * sizeof(fip::VbItem),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return FIP_ERR_LAUNCH;
+    if (fip::launch_vb_zero(reinterpret_cast<uint32_t*>(ws), h->stream) != hipSuccess)
+        return FIP_ERR_LAUNCH;
+    v.sig = sig;
+    v.split = split;
+    v.ws = h->ws;
+    v.total = (int64_t)v.items.size();
+    v.off_probs = off_probs;
+    v.off_items = off_items;
+    if (v.exec) { (void)hipGraphExecDestroy(v.exec); v.exec = nullptr; }
+    return 0;
+}
+
+fip::VbLaunchDesc vb_desc(const fip_handle_s* h, float alpha, const float* const* A,
+                          const int64_t* lda, const float* const* B, const int64_t* ldb,
+                          float beta, float* const* C, const int64_t* ldc)
+{
+    const VbState& v = *h->vb;
+    char* ws = static_cast<char*>(h->ws);
+    fip::VbLaunchDesc d{};
+    d.probs = reinterpret_cast<const fip::VbProblem*>(ws + v.off_probs);
+    d.items = reinterpret_cast<const fip::VbItem*>(ws + v.off_items);
+    d.total = v.total;
+    d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = C; d.ldc = ldc;
+    d.alpha = alpha; d.beta = beta;
+    d.ticket = reinterpret_cast<uint32_t*>(ws);
+    d.stream = h->stream;
+    return d;
+}
+
+// Validate, make sure the plan for (signature, split) is in the workspace.
+int vb_prepare(fip_handle_s* h, int layout, int64_t count, const int32_t* m, const int32_t* n,
+               const int32_t* k, const char* tA, const char* tB, int forced_split,
+               uint64_t* sig_out)
+{
+    if (h->vb == nullptr) {
+        h->vb = new (std::nothrow) VbState;
+        if (h->vb == nullptr) return FIP_ERR_ALLOC;
+    }
+    const uint64_t sig = vb_signature(layout, count, m, n, k, tA, tB);
+    *sig_out = sig;
+    int split = forced_split;
+    if (split < 0) split = h->vb_split;
+    if (split < 0) {
+        auto it = h->vb->tuned.find(sig);
+        split = it != h->vb->tuned.end() ? it->second : kVbDefaultSplit;
+    }
+    int64_t op, oi;
+    const int64_t need = vb_workspace_bytes(layout, count, m, n, &op, &oi);
+    if (h->ws == nullptr || (int64_t)h->ws_bytes < need) return FIP_ERR_WORKSPACE;
+    VbState& v = *h->vb;
+    if (v.sig != sig || v.split != split || v.ws != h->ws || v.total == 0)
+        return vb_upload(h, layout, count, m, n, k, tA, tB, sig, split);
+    return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -461,6 +656,8 @@ int fip_create(fip_handle_t* handle)
     h->policy = FIP_PACK_AUTO;
     h->tile_override = -1;
     h->order = 0;
+    h->vb_split = -1;
+    h->vb = nullptr;
     *handle = h;
     return 0;
 }
@@ -469,6 +666,7 @@ int fip_destroy(fip_handle_t handle)
 {
     if (!valid_handle(handle)) return FIP_ERR_HANDLE;
     handle->magic = 0;
+    delete handle->vb;
     delete handle;
     return 0;
 }
@@ -504,6 +702,10 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
         if (value != 0 && value != 1) return 3;
         handle->order = (int)value;
         return 0;
+    case FIP_ATTR_VB_SPLIT:
+        if (value < -1 || value > (int64_t)1 << 30) return 3;
+        handle->vb_split = (int)value;
+        return 0;
     default:
         return 2;
     }
@@ -520,6 +722,7 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_STATS: *value = handle->stats; return 0;
     case FIP_ATTR_ORDER: *value = handle->order; return 0;
     case FIP_ATTR_EPOCH: *value = (int64_t)handle->epoch; return 0;
+    case FIP_ATTR_VB_SPLIT: *value = handle->vb_split; return 0;
     default: return 2;
     }
 }
@@ -652,6 +855,122 @@ int fip_quantize_fp8(fip_handle_t handle, int layout, int64_t rows, int64_t cols
         if (!any) return 0;
         return fip::launch_quantize_fp8(col, rows, cols, X, ldx, axis, Q, ldq, scales,
                                         handle->stream) == hipSuccess ? 0 : FIP_ERR_LAUNCH;
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+int fip_vbatched_workspace(fip_handle_t handle, int layout, int64_t count, const int32_t* m,
+                           const int32_t* n, const int32_t* k, const char* transA,
+                           const char* transB, size_t* bytes)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    const int bad = vb_check(layout, count, m, n, k, transA, transB);
+    if (bad) return bad;
+    if (bytes == nullptr) return 9;
+    int64_t op, oi;
+    *bytes = (size_t)vb_workspace_bytes(layout, count, m, n, &op, &oi);
+    return 0;
+}
+
+int fip_sgemm_vbatched(fip_handle_t handle, int layout, int64_t count, const int32_t* m,
+                       const int32_t* n, const int32_t* k, const char* transA, const char* transB,
+                       float alpha, const float* const* A, const int64_t* lda,
+                       const float* const* B, const int64_t* ldb, float beta, float* const* C,
+                       const int64_t* ldc, int flags)
+{
+    try {
+        if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+        const int bad = vb_check(layout, count, m, n, k, transA, transB);
+        if (bad) return bad;
+        if (count > 0) {
+            if (A == nullptr) return 10;
+            if (lda == nullptr) return 11;
+            if (B == nullptr) return 12;
+            if (ldb == nullptr) return 13;
+            if (C == nullptr) return 15;
+            if (ldc == nullptr) return 16;
+        }
+        if (flags & ~FIP_VB_GRAPH) return 17;
+        if (count == 0 || (alpha == 0.f && beta == 1.f)) return 0;
+        uint64_t sig;
+        const int rc = vb_prepare(handle, layout, count, m, n, k, transA, transB, -1, &sig);
+        if (rc) return rc;
+        VbState& v = *handle->vb;
+        if (v.total == 0) return 0;
+        const fip::VbLaunchDesc d = vb_desc(handle, alpha, A, lda, B, ldb, beta, C, ldc);
+        if (!(flags & FIP_VB_GRAPH))
+            return fip::launch_vbatched(d) == hipSuccess ? 0 : FIP_ERR_LAUNCH;
+        // graph replay: one kernel node, rebuilt only when the call changes
+        uint64_t key[12];
+        float ab[2] = {alpha, beta};
+        uint64_t abits;
+        memcpy(&abits, ab, 8);
+        const void* ptrs[] = {A, lda, B, ldb, C, ldc, handle->ws, handle->stream};
+        key[0] = v.sig; key[1] = (uint64_t)v.split; key[2] = abits;
+        for (int i = 0; i < 8; ++i) key[3 + i] = (uint64_t)(uintptr_t)ptrs[i];
+        key[11] = (uint64_t)v.total;
+        if (v.exec == nullptr || memcmp(key, v.gkey, sizeof key) != 0) {
+            if (v.exec) { (void)hipGraphExecDestroy(v.exec); v.exec = nullptr; }
+            if (fip::build_vbatched_graph(d, &v.exec) != hipSuccess) { v.exec = nullptr; return FIP_ERR_LAUNCH; }
+            memcpy(v.gkey, key, sizeof key);
+        }
+        return hipGraphLaunch(v.exec, handle->stream) == hipSuccess ? 0 : FIP_ERR_LAUNCH;
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+int fip_vbatched_tune(fip_handle_t handle, int layout, int64_t count, const int32_t* m,
+                      const int32_t* n, const int32_t* k, const char* transA, const char* transB,
+                      float alpha, const float* const* A, const int64_t* lda,
+                      const float* const* B, const int64_t* ldb, float beta, float* const* C,
+                      const int64_t* ldc, int* split_out)
+{
+    try {
+        if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+        const int bad = vb_check(layout, count, m, n, k, transA, transB);
+        if (bad) return bad;
+        if (count > 0 && (A == nullptr || lda == nullptr || B == nullptr || ldb == nullptr ||
+                          C == nullptr || ldc == nullptr))
+            return A == nullptr ? 10 : lda == nullptr ? 11 : B == nullptr ? 12
+                 : ldb == nullptr ? 13 : C == nullptr ? 15 : 16;
+        if (split_out == nullptr) return 17;
+        *split_out = kVbDefaultSplit;
+        if (count == 0) return 0;
+        // candidate thresholds on max(m, n) for 32 x 32 tiles
+        const int cands[] = {0, 16, 32, 48, 64, 96, 128, 192, 256, 1 << 30};
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return FIP_ERR_LAUNCH;
+        if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FIP_ERR_LAUNCH; }
+        float best_t = 1e30f;
+        int best = kVbDefaultSplit;
+        uint64_t sig = 0;
+        int rc = 0;
+        for (int c : cands) {
+            rc = vb_prepare(handle, layout, count, m, n, k, transA, transB, c, &sig);
+            if (rc) break;
+            const fip::VbLaunchDesc d = vb_desc(handle, alpha, A, lda, B, ldb, beta, C, ldc);
+            if (d.total == 0) { best = c; break; }
+            float t[3];
+            bool ok = fip::launch_vbatched(d) == hipSuccess;  // warm-up
+            for (int r = 0; r < 3 && ok; ++r) {
+                ok = hipEventRecord(e0, handle->stream) == hipSuccess &&
+                     fip::launch_vbatched(d) == hipSuccess &&
+                     hipEventRecord(e1, handle->stream) == hipSuccess &&
+                     hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&t[r], e0, e1) == hipSuccess;
+            }
+            if (!ok) { rc = FIP_ERR_LAUNCH; break; }
+            std::sort(t, t + 3);
+            if (t[1] < best_t) { best_t = t[1]; best = c; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        handle->vb->tuned[sig] = best;
+        *split_out = best;
+        return vb_prepare(handle, layout, count, m, n, k, transA, transB, -1, &sig);
     } catch (...) {
         return FIP_ERR_LAUNCH;
     }

@@ -27,6 +27,8 @@ MX_FORMS = (FIP_BF16, FIP_E4M3, FIP_BF16X3, FIP_BF16X3_FAST)
 FIP_ERR_HANDLE, FIP_ERR_WORKSPACE, FIP_ERR_LAUNCH, FIP_ERR_UNSUPPORTED, FIP_ERR_ALLOC = -1, -2, -3, -4, -5
 FIP_ATTR_PACK_POLICY, FIP_ATTR_TILE, FIP_ATTR_NO_PUBLISH, FIP_ATTR_STATS, FIP_ATTR_EPOCH = 1, 2, 3, 4, 5
 FIP_ATTR_ORDER = 7
+FIP_ATTR_VB_SPLIT = 8
+FIP_VB_GRAPH = 1
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
 
@@ -72,6 +74,12 @@ _SIGS = {
     "fip_gemm_mx": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64,
                     _ch, ctypes.c_float, _vp, _i64, _i32, _vp, _vp],
     "fip_quantize_fp8": [_vp, _i32, _i64, _i64, _vp, _i64, _i32, _vp, _i64, _vp],
+    "fip_vbatched_workspace": [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp,
+                               ctypes.POINTER(ctypes.c_size_t)],
+    "fip_sgemm_vbatched": [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, _vp, _vp,
+                           _vp, _vp, ctypes.c_float, _vp, _vp, _i32],
+    "fip_vbatched_tune": [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, _vp, _vp,
+                          _vp, _vp, ctypes.c_float, _vp, _vp, ctypes.POINTER(_i32)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -174,6 +182,38 @@ def fip_gemm_mx(h, dtype, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB
 def fip_quantize_fp8(h, layout, rows, cols, X, ldx, axis, Q, ldq, scales):
     return _lib.fip_quantize_fp8(h, layout, rows, cols, _addr(X), ldx, axis, _addr(Q), ldq,
                                  _addr(scales))
+
+
+def _host_ptr(a):
+    """Address of a host NumPy array (or None)."""
+    return None if a is None else a.ctypes.data
+
+
+def fip_vbatched_workspace(h, layout, count, m, n, k, transA, transB):
+    nbytes = ctypes.c_size_t()
+    rc = _lib.fip_vbatched_workspace(h, layout, count, _host_ptr(m), _host_ptr(n), _host_ptr(k),
+                                     _host_ptr(transA), _host_ptr(transB), ctypes.byref(nbytes))
+    return rc, nbytes.value
+
+
+def fip_sgemm_vbatched(h, layout, count, m, n, k, transA, transB, alpha, A, lda, B, ldb, beta,
+                       C, ldc, flags=0):
+    """m, n, k: host int32 arrays; transA/B: host uint8 arrays of b'N'/b'T'; A, B, C: device
+    arrays (tensors) of device pointers (int64); lda, ldb, ldc: device int64 arrays."""
+    return _lib.fip_sgemm_vbatched(h, layout, count, _host_ptr(m), _host_ptr(n), _host_ptr(k),
+                                   _host_ptr(transA), _host_ptr(transB), alpha, _addr(A),
+                                   _addr(lda), _addr(B), _addr(ldb), beta, _addr(C), _addr(ldc),
+                                   flags)
+
+
+def fip_vbatched_tune(h, layout, count, m, n, k, transA, transB, alpha, A, lda, B, ldb, beta,
+                      C, ldc):
+    split = _i32()
+    rc = _lib.fip_vbatched_tune(h, layout, count, _host_ptr(m), _host_ptr(n), _host_ptr(k),
+                                _host_ptr(transA), _host_ptr(transB), alpha, _addr(A), _addr(lda),
+                                _addr(B), _addr(ldb), beta, _addr(C), _addr(ldc),
+                                ctypes.byref(split))
+    return rc, split.value
 
 
 # ---- convenience handle (torch owns the workspace and the stream) ----------------------

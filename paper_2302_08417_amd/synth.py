@@ -226,3 +226,59 @@ def make_mx_case(form, layout=COL, m=64, n=64, k=64, transA="N", transB="N", ld_
         C = fill_stored(layout, m, n, ldc, Cv, np.float32)
     return MxCase(form, layout, m, n, k, transA, transB, lda, ldb, ldc, alpha, beta, A, B, C,
                   c_bf16, a_scale, b_scale, A32, B32)
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent, unevenly sized problems: m, n, k each
+# round(exp(U[ln lo, ln hi])) (log-uniform), transA / transB each 'N' or 'T'
+# with probability 1/2, entries U[-1, 1], optional ld padding (NaN-filled).
+
+@dataclass
+class Batch:
+    layout: int
+    count: int
+    m: np.ndarray        # int32
+    n: np.ndarray
+    k: np.ndarray
+    transA: np.ndarray   # uint8 codes of 'N' / 'T'
+    transB: np.ndarray
+    lda: np.ndarray      # int64
+    ldb: np.ndarray
+    ldc: np.ndarray
+    alpha: float
+    beta: float
+    A: list              # per problem: flat float32 buffers
+    B: list
+    C: list
+
+
+def make_batch(count, layout=COL, lo=4, hi=512, ld_pad=0, alpha=1.5, beta=0.5,
+               seed=BASE_SEED, zero_sizes=False) -> Batch:
+    g = rng(seed)
+
+    def dims():
+        return np.rint(np.exp(g.uniform(np.log(lo), np.log(hi), size=count))).astype(np.int32)
+
+    m, n, k = dims(), dims(), dims()
+    if zero_sizes and count >= 3:   # a few degenerate problems
+        m[0] = 0
+        n[1] = 0
+        k[2] = 0
+    tA = np.where(g.random(count) < 0.5, ord("N"), ord("T")).astype(np.uint8)
+    tB = np.where(g.random(count) < 0.5, ord("N"), ord("T")).astype(np.uint8)
+    lda = np.empty(count, np.int64)
+    ldb = np.empty(count, np.int64)
+    ldc = np.empty(count, np.int64)
+    As, Bs, Cs = [], [], []
+    for i in range(count):
+        ta, tb = chr(tA[i]), chr(tB[i])
+        sa = stored_shape(ta, int(m[i]), int(k[i]))
+        sb = stored_shape(tb, int(k[i]), int(n[i]))
+        lda[i] = min_ld(layout, *sa) + ld_pad
+        ldb[i] = min_ld(layout, *sb) + ld_pad
+        ldc[i] = min_ld(layout, int(m[i]), int(n[i])) + ld_pad
+        As.append(fill_stored(layout, sa[0], sa[1], int(lda[i]), g.uniform(-1, 1, sa), np.float32))
+        Bs.append(fill_stored(layout, sb[0], sb[1], int(ldb[i]), g.uniform(-1, 1, sb), np.float32))
+        Cs.append(fill_stored(layout, int(m[i]), int(n[i]), int(ldc[i]),
+                              g.uniform(-1, 1, (int(m[i]), int(n[i]))), np.float32))
+    return Batch(layout, count, m, n, k, tA, tB, lda, ldb, ldc, alpha, beta, As, Bs, Cs)

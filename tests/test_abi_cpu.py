@@ -171,3 +171,93 @@ def test_plan_orientation_matches_oracle_rule(h):
                 p = plan(h, 300, 200, 77, layout=layout, policy=F.FIP_PACK_ALL, tile=2, t=tA + tB)
                 assert p.a_kmajor == (not oracle.mn_contiguous(0, layout, tA))
                 assert p.b_kmajor == (not oracle.mn_contiguous(1, layout, tB))
+
+
+# ---- mixed-precision forms and batched calls: host-side checks only ----------------------
+
+def test_mx_argument_positions(h):
+    def call(dtype=F.FIP_BF16, layout=0, m=4, n=5, k=6, alpha=1.0, A=FAKE, lda=4, tA="N",
+             B=FAKE, ldb=6, tB="N", beta=0.5, C=FAKE, ldc=4, c_type=F.FIP_F32, sa=None, sb=None):
+        return F.fip_gemm_mx(h, dtype, layout, m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C,
+                             ldc, c_type, sa, sb)
+    assert call(dtype=F.FIP_F64) == 2 and call(dtype=9) == 2
+    assert call(layout=5) == 3
+    assert call(m=-1) == 4 and call(n=-1) == 5 and call(k=-1) == 6
+    assert call(A=None) == 8 and call(lda=3) == 9 and call(tA="x") == 10
+    assert call(B=None) == 11 and call(ldb=5) == 12 and call(tB="q") == 13
+    assert call(C=None) == 15 and call(ldc=3) == 16
+    assert call(c_type=F.FIP_F64) == 17
+    assert call(sa=FAKE) == 18 and call(sb=FAKE) == 19          # scales only with E4M3
+    assert call(m=0) == 0                                       # quick return, no launch
+    assert call(dtype=F.FIP_E4M3, alpha=0.0, beta=1.0, sa=FAKE, sb=FAKE) == 0
+
+
+def test_quantize_argument_positions(h):
+    def call(layout=0, rows=4, cols=5, X=FAKE, ldx=4, axis=0, Q=FAKE, ldq=4, s=FAKE):
+        return F.fip_quantize_fp8(h, layout, rows, cols, X, ldx, axis, Q, ldq, s)
+    assert call(layout=3) == 2 and call(rows=-1) == 3 and call(cols=-2) == 4
+    assert call(X=None) == 5 and call(ldx=3) == 6 and call(axis=2) == 7
+    assert call(Q=None) == 8 and call(ldq=1) == 9 and call(s=None) == 10
+    assert call(rows=0) == 0
+
+
+@pytest.mark.parametrize("dtype,KT,planes,eb", [(F.FIP_BF16, 64, 1, 2), (F.FIP_E4M3, 128, 1, 1),
+                                                (F.FIP_BF16X3, 32, 3, 2),
+                                                (F.FIP_BF16X3_FAST, 32, 2, 2)])
+def test_mx_plans(h, dtype, KT, planes, eb):
+    assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_ALL) == 0
+    rc, p = F.fip_plan(h, dtype, 1, 300, 200, 333, "T", "N")
+    assert rc == 0
+    assert (p.MT, p.NT, p.KT) == (128, 128, KT)
+    assert p.a_kmajor == 1 and p.b_kmajor == 1      # mixed forms pack K-major always
+    nk = -(-333 // KT)
+    # row-major: op(A) is the kernel's B side; sizes are reported in the caller's terms
+    assert p.a_copy_bytes == 3 * nk * KT * 128 * planes * eb
+    assert p.b_copy_bytes == 2 * nk * KT * 128 * planes * eb
+    assert p.copies == 8 and p.workspace_bytes >= 8 * (p.a_copy_bytes + p.b_copy_bytes)
+    assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO) == 0
+    rc, p = F.fip_plan(h, dtype, 0, 300, 200, 333, "N", "N")
+    assert rc == 0 and p.workspace_bytes == 0      # one round of tiles: nothing to reuse
+
+
+def _vb_arrays():
+    import numpy as np
+    m = np.array([5, 0, 300, 64], np.int32)
+    n = np.array([7, 3, 33, 65], np.int32)
+    k = np.array([9, 4, 0, 128], np.int32)
+    tA = np.frombuffer(b"NTNT", np.uint8).copy()
+    tB = np.frombuffer(b"TNNn", np.uint8).copy()
+    return m, n, k, tA, tB
+
+
+def test_vbatched_workspace_and_positions(h):
+    import numpy as np
+    m, n, k, tA, tB = _vb_arrays()
+    rc, nbytes = F.fip_vbatched_workspace(h, 0, 4, m, n, k, tA, tB)
+    assert rc == 0
+    # 256 B of counters, 4 x 32 B problems, items of the 32 x 32 class, each 8 B
+    tiles = sum(-(-int(a) // 32) * -(-int(b) // 32) for a, b in zip(m, n))
+    expect = 256 + 256 + -(-tiles * 8 // 256) * 256
+    assert nbytes == expect
+    rc, nrow = F.fip_vbatched_workspace(h, 1, 4, m, n, k, tA, tB)   # row-major: same tiles
+    assert rc == 0 and nrow == nbytes
+    bad = m.copy()
+    bad[2] = -3
+    assert F.fip_vbatched_workspace(h, 0, 4, bad, n, k, tA, tB)[0] == 4
+    badt = tB.copy()
+    badt[1] = ord("z")
+    assert F.fip_vbatched_workspace(h, 0, 4, m, n, k, tA, badt)[0] == 8
+    assert F.fip_vbatched_workspace(h, 2, 4, m, n, k, tA, tB)[0] == 2
+    assert F.fip_vbatched_workspace(h, 0, -1, m, n, k, tA, tB)[0] == 3
+    # run-time argument checks happen before any HIP call
+    args = (h, 0, 4, m, n, k, tA, tB, 1.0, FAKE, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE)
+    assert F.fip_sgemm_vbatched(*args, 2) == 17
+    assert F.fip_sgemm_vbatched(h, 0, 4, m, n, k, tA, tB, 1.0, None, FAKE, FAKE, FAKE, 0.0, FAKE,
+                                FAKE, 0) == 10
+    assert F.fip_sgemm_vbatched(h, 0, 0, m, n, k, tA, tB, 1.0, None, None, None, None, 0.0, None,
+                                None, 0) == 0
+    assert F.fip_sgemm_vbatched(h, 0, 4, m, n, k, tA, tB, 0.0, FAKE, FAKE, FAKE, FAKE, 1.0, FAKE,
+                                FAKE, 0) == 0     # alpha = 0, beta = 1: nothing to do
+    assert F.fip_set_attr(h, F.FIP_ATTR_VB_SPLIT, 96) == 0
+    assert F.fip_get_attr(h, F.FIP_ATTR_VB_SPLIT) == (0, 96)
+    assert F.fip_set_attr(h, F.FIP_ATTR_VB_SPLIT, -2) == 3
