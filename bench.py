@@ -12,6 +12,12 @@ paths in FP64 and FP32 (median over interleaved rounds; pack-then-compute time i
 its pack launch).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu-baseline]
+                    [--no-mx] [--no-autograd] [--no-batched]
+
+Further sections of the same JSON line: the mixed-precision forms (bfloat16, FP8 E4M3,
+3- and 2-term bfloat16 splits) at m = n = k in {1024, 4096, 16384} with their error
+against the binary64 oracle; the bfloat16 autograd linear layer (8192 x 4096 x 4096,
+forward and backward); the 10,000-problem batched binary32 GEMM (eager and graph).
 """
 import argparse
 import hashlib
@@ -137,6 +143,147 @@ def time_interleaved(g, policies, rounds=11, warmup=3):
     return {pol: statistics.median(v) for pol, v in times.items()}, rounds * reps
 
 
+MX_FORMS = [("bf16", 2, 2516.6, 1), ("e4m3", 3, 5033.2, 1), ("bf16x3", 4, 2516.6, 6),
+            ("bf16x3_fast", 5, 2516.6, 3)]   # name, dtype code, MFMA peak (TFLOP/s), products
+
+
+def _median_times(torch, calls, rounds, reps):
+    """Median per-call ms of each callable, interleaved over rounds (HIP events)."""
+    import statistics
+    times = {k: [] for k in calls}
+    for r in range(rounds):
+        for key in (list(calls) if r % 2 == 0 else list(calls)[::-1]):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                calls[key]()
+            b.record()
+            torch.cuda.synchronize()
+            times[key].append(a.elapsed_time(b) / reps)
+    return {k: statistics.median(v) for k, v in times.items()}
+
+
+def mx_section(F, torch, sizes):
+    """Mixed-precision forms, square column-major NN, alpha = 1, beta = 0, C binary32:
+    fused (AUTO) vs pack-then-compute vs unpacked, and the error of the fused result on a
+    sampled 32 x 32 block of C against the binary64 oracle product of the binary32 values
+    the operands were made from (max |dC| / max |A||B|)."""
+    import numpy as np
+    import oracle
+    from paper_2302_08417_amd import synth
+    out = []
+    for n in sizes:
+        for name, dt, peak, prods in MX_FORMS:
+            A, B, sa, sb, A32, B32 = synth.mx_device_operands(dt, n, seed=synth.BASE_SEED + n)
+            C = torch.zeros(n, n, device="cuda")
+            hs = {pol: F.Handle(policy=pol) for pol in (F.FIP_PACK_AUTO, F.FIP_PACK_CONSUME_ONLY,
+                                                         F.FIP_PACK_NONE)}
+
+            def mk(pol):
+                h = hs[pol]
+
+                def call():
+                    if pol == F.FIP_PACK_CONSUME_ONLY:
+                        h.pack(0, n, n, n, A, n, "N", B, n, "N", dtype=dt)
+                    h.gemm_mx(dt, 0, n, n, n, 1.0, A, n, "N", B, n, "N", 0.0, C, n, sa, sb)
+                return call
+            calls = {pol: mk(pol) for pol in hs}
+            for c in calls.values():
+                c()
+            torch.cuda.synchronize()
+            est = 2.0 * n ** 3 * prods / (peak * 0.25e12)
+            med = _median_times(torch, calls, 5, max(1, min(50, int(0.01 / est))))
+            calls[F.FIP_PACK_AUTO]()
+            torch.cuda.synchronize()
+            g = np.random.default_rng(n + dt)
+            ri = np.sort(g.choice(n, 32, replace=False))
+            ci = np.sort(g.choice(n, 32, replace=False))
+            # A32[p, i] holds A(i, p) (column-major storage); B32[j, p] holds B(p, j)
+            subA = A32[:, torch.as_tensor(ri, device="cuda")].double().cpu().numpy()  # k x 32
+            subB = B32[torch.as_tensor(ci, device="cuda"), :].double().cpu().numpy()  # 32 x k
+            got = C[torch.as_tensor(ci, device="cuda")][:, torch.as_tensor(ri, device="cuda")]
+            got = got.double().cpu().numpy().T                                          # 32 x 32
+            Aop = np.ascontiguousarray(subA.T).reshape(-1, order="F")                   # 32 x k
+            Bop = np.ascontiguousarray(subB.T).reshape(-1, order="F")                   # k x 32
+            ref, D = oracle.gemm(0, 32, 32, n, 1.0, Aop, 32, "N", Bop, n, "N", 0.0,
+                                 np.zeros(32 * 32), 32)
+            err = float(np.abs(got - ref.reshape(32, 32, order="F")).max() / D.max())
+            fl = 2.0 * n ** 3
+            row = {"form": name, "m": n, "n": n, "k": n}
+            for key, pol in (("fused", F.FIP_PACK_AUTO), ("pack_then_compute", F.FIP_PACK_CONSUME_ONLY),
+                             ("no_pack", F.FIP_PACK_NONE)):
+                row[key + "_us"] = round(med[pol] * 1e3, 2)
+                row[key + "_tflops"] = round(fl / (med[pol] * 1e-3) / 1e12, 1)
+            row["mfma_peak_tflops"] = peak
+            row["fused_pct_mfma_peak"] = round(100 * row["fused_tflops"] * prods / peak, 2)
+            row["err_vs_fp64_oracle_rel_to_max_absAB"] = float(f"{err:.3e}")
+            log(f"[mx] {row}")
+            out.append(row)
+            for h in hs.values():
+                h.close()
+            del A, B, A32, B32, C
+            torch.cuda.empty_cache()
+    return out
+
+
+def autograd_section(F, torch):
+    """bfloat16 linear layer, forward Y = X W^T and backward dX = dY W, dW = dY^T X, all
+    through the fused-pack GEMM: X 8192 x 4096 ~ N(0,1), W 4096 x 4096 ~ N(0, 1/4096),
+    dY ~ N(0,1)."""
+    from paper_2302_08417_amd import autograd as AG
+    g = torch.Generator(device="cuda").manual_seed(3)
+    X = torch.randn(8192, 4096, device="cuda", generator=g).to(torch.bfloat16).requires_grad_()
+    W = (torch.randn(4096, 4096, device="cuda", generator=g) / 64).to(torch.bfloat16)
+    W.requires_grad_()
+    dY = torch.randn(8192, 4096, device="cuda", generator=g).to(torch.bfloat16)
+
+    def step():
+        X.grad = None
+        W.grad = None
+        AG.fip_linear(X, W).backward(dY)
+    step()
+    torch.cuda.synchronize()
+    t = _median_times(torch, {"s": step}, 7, 5)["s"]
+    fl = 3 * 2.0 * 8192 * 4096 * 4096
+    res = {"workload": "bf16 linear fwd+bwd X 8192x4096, W 4096x4096", "ms_per_step": round(t, 4),
+           "tflops": round(fl / (t * 1e-3) / 1e12, 1),
+           "pct_bf16_mfma_peak": round(100 * fl / (t * 1e-3) / 2516.6e12, 2)}
+    log(f"[autograd] {res}")
+    return res
+
+
+def batched_section(F, torch, count=10000):
+    """10,000 binary32 problems, m, n, k log-uniform in [4, 512], random transposes, ragged
+    storage through device pointer arrays, alpha = 1.5, beta = 0.5; tile threshold from the
+    autotuner; eager launch and graph replay."""
+    from paper_2302_08417_amd import synth
+    from paper_2302_08417_amd.batched import DeviceBatch
+    b = synth.make_batch(count, synth.COL, lo=4, hi=512, seed=synth.BASE_SEED + 3)
+    db = DeviceBatch(b)
+    h = F.Handle()
+    split = db.tune(h)
+    db.run(h)
+    db.run(h, graph=True)
+    torch.cuda.synchronize()
+    med = _median_times(torch, {"eager": lambda: db.run(h), "graph": lambda: db.run(h, graph=True)},
+                        7, 10)
+    m, n, k = (x.astype("float64") for x in (b.m, b.n, b.k))
+    fl = float((2 * m * n * k).sum())
+    nbytes = float((4 * (m * k + k * n + 2 * m * n)).sum())
+    res = {"workload": f"{count} fp32 problems, m,n,k log-uniform [4,512], random transposes",
+           "tuned_split": split, "total_gflop": round(fl / 1e9, 3),
+           "algorithmic_gbytes": round(nbytes / 1e9, 4)}
+    for key in ("eager", "graph"):
+        t = med[key]
+        res[key + "_us"] = round(t * 1e3, 1)
+        res[key + "_tflops"] = round(fl / (t * 1e-3) / 1e12, 2)
+        res[key + "_algorithmic_gbs"] = round(nbytes / (t * 1e-3) / 1e9, 1)
+    res["pct_hbm_peak_graph"] = round(100 * res["graph_algorithmic_gbs"] / 8000.0, 2)
+    log(f"[batched] {res}")
+    return res
+
+
 def cpu_baseline(n, target_s=12.0):
     """The oracle, as it stands, on a column sample of the headline workload."""
     import numpy as np
@@ -177,6 +324,10 @@ def main():
                     help="comma-separated sizes for the sweep (default: 16..8192 powers of two)")
     ap.add_argument("--sweep-dtypes", default="f64,f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mx", action="store_true", help="skip the mixed-precision section")
+    ap.add_argument("--mx-sizes", default="1024,4096,16384")
+    ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), to "
                          "calibrate HBM byte counters against a kernel of known traffic")
@@ -274,6 +425,13 @@ def main():
                 del gs
                 torch.cuda.empty_cache()
         result["sweep"] = sweep
+
+    if not args.no_mx:
+        result["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
+    if not args.no_autograd:
+        result["autograd"] = autograd_section(F, torch)
+    if not args.no_batched:
+        result["batched"] = batched_section(F, torch)
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -36,7 +36,8 @@ __device__ __forceinline__ void wait_all_memory()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs,
+// Workgroup -> tile (also replayed on the host by the planner to see which
+// panels a later round reads).  Workgroups are dispatched round-robin over the 8 XCDs,
 // so w % 8 is (normally) the XCD.  Each XCD gets one contiguous run of a
 // grouped tile order: bands of GROUP_M tile rows, swept column by column.
 // That keeps the tiles running together on an XCD compact for its L2 and most
@@ -46,17 +47,17 @@ __device__ __forceinline__ void wait_all_memory()
 //            slot s -> column s, row (s + r) mod GROUP_M), so the first round of
 //            workgroups touches every column panel of the band once and later
 //            rounds find them all packed.
-__device__ __forceinline__ void tile_coords(int w, int tilesM, int tilesN, int group_m, int order,
+__host__ __device__ inline void tile_coords(int w, int tilesM, int tilesN, int group_m, int order,
                                             int& tm, int& tn)
 {
     const int T = tilesM * tilesN;
     const int xcd = w & 7, local = w >> 3;
     const int q = T >> 3, rr = T & 7;
-    const int t = xcd * q + min(xcd, rr) + local;
+    const int t = xcd * q + (xcd < rr ? xcd : rr) + local;
     const int per_group = group_m * tilesN;
     const int g = t / per_group;
     const int first_m = g * group_m;
-    const int gsize = min(tilesM - first_m, group_m);
+    const int gsize = tilesM - first_m < group_m ? tilesM - first_m : group_m;
     const int rem = t - g * per_group;
     if (order == 0) {
         tm = first_m + rem % gsize;

@@ -18,6 +18,9 @@ enum Mode : int32_t {
     kModeUnpacked = 2,     // never pack
 };
 
+// Tile rows per band of the XCD-aware tile order (see tile_coords).
+constexpr int kGroupM = 8;
+
 // Tile classes: C tile MT x NT, k-step KT (KT depends on the element type).
 constexpr int kNumTileClasses = 3;
 inline int tile_mt(int cls) { return cls == 0 ? 128 : cls == 1 ? 64 : 32; }

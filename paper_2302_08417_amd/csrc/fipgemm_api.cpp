@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "fip_internal.h"
+#include "fip_device.h"
 
 namespace {
 
@@ -118,6 +119,39 @@ int choose_tile_class(int64_t M, int64_t N)
     return 2;
 }
 
+// Which panels does a later round read again?  Replays the launch order:
+// workgroup w runs on XCD w % 8 and computes tile tile_coords(w); an XCD runs
+// about per_xcd workgroups at a time, in dispatch order, so its local index
+// divided by per_xcd is the round.  A panel (tile row of A, tile column of B)
+// that an XCD touches in two different rounds is re-read by a pass that
+// starts after an earlier pass over it could have finished: the reuse the
+// paper's Sec. 3.3 table is about, as it happens on this schedule.  Returns
+// the fraction of (XCD, panel) pairs that are reused, per operand.
+void later_round_reuse(int64_t tilesM, int64_t tilesN, int order, int64_t per_xcd, double* fracA,
+                       double* fracB)
+{
+    const int64_t T = tilesM * tilesN;
+    *fracA = *fracB = 0.0;
+    if (T <= 0 || per_xcd <= 0 || T > ((int64_t)1 << 24)) return;
+    std::vector<int32_t> firstA(8 * tilesM, -1), firstB(8 * tilesN, -1);
+    std::vector<char> reA(8 * tilesM, 0), reB(8 * tilesN, 0);
+    for (int64_t w = 0; w < T; ++w) {
+        int tm, tn;
+        fip::tile_coords((int)w, (int)tilesM, (int)tilesN, fip::kGroupM, order, tm, tn);
+        const int64_t x = w & 7;
+        const int32_t r = (int32_t)((w >> 3) / per_xcd);
+        int32_t& fa = firstA[x * tilesM + tm];
+        if (fa < 0) fa = r; else if (fa != r) reA[x * tilesM + tm] = 1;
+        int32_t& fb = firstB[x * tilesN + tn];
+        if (fb < 0) fb = r; else if (fb != r) reB[x * tilesN + tn] = 1;
+    }
+    int64_t tA = 0, uA = 0, tB = 0, uB = 0;
+    for (int64_t i = 0; i < 8 * tilesM; ++i) { tA += firstA[i] >= 0; uA += reA[i]; }
+    for (int64_t i = 0; i < 8 * tilesN; ++i) { tB += firstB[i] >= 0; uB += reB[i]; }
+    *fracA = tA ? (double)uA / tA : 0.0;
+    *fracB = tB ? (double)uB / tB : 0.0;
+}
+
 // Internal plan: kernel-side quantities plus the caller-facing fip_plan_t.
 struct Plan {
     fip_plan_t pub;
@@ -190,11 +224,18 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
             // reuse it (n > n_R), B's panel only if several tile rows do (m > m_R).
             // On the GPU the tiles of one launch run concurrently: a later pass
             // can read a packed panel without waiting only if it starts after
-            // the first pass finished, i.e. when the launch has more tiles than
-            // fit on the device at once.  Otherwise nobody could reuse the pack.
+            // the first pass finished, i.e. in a later round of workgroups on
+            // the same XCD (each XCD keeps its own copy).  The planner replays
+            // the launch order and packs an operand when most of its panels are
+            // read again in a later round; with a single round nobody could
+            // reuse a pack.
             const bool later_passes = pl->tilesKM * pl->tilesKN > resident;
-            pl->kpack_a = pl->tilesKN > 1 && later_passes;
-            pl->kpack_b = pl->tilesKM > 1 && later_passes;
+            double fa = 0.0, fb = 0.0;
+            if (later_passes)
+                later_round_reuse(pl->tilesKM, pl->tilesKN, h->order, resident / fip::kCopies,
+                                  &fa, &fb);
+            pl->kpack_a = pl->tilesKN > 1 && fa >= 0.5;
+            pl->kpack_b = pl->tilesKM > 1 && fb >= 0.5;
         }
         if (pl->kpack_a || pl->kpack_b) copies = fip::kCopies;
     }

@@ -384,7 +384,7 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.tilesM = (int)((d.M + MT - 1) / MT);
     P.tilesN = (int)((d.N + NT - 1) / NT);
     P.nK = (int)((d.K + KT - 1) / KT);
-    P.group_m = 8;
+    P.group_m = kGroupM;
     P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
     P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
     const int64_t a_far = d.a_kmajor ? d.a_smn : d.a_sk;  // the leading dimension

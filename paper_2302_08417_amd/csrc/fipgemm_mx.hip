@@ -742,7 +742,7 @@ MxParams make_mx_params(const MxLaunchDesc& d)
     P.tilesM = (int)((d.M + MT - 1) / MT);
     P.tilesN = (int)((d.N + MT - 1) / MT);
     P.nK = (int)((d.K + KT - 1) / KT);
-    P.group_m = 8;
+    P.group_m = kGroupM;
     P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
     P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
     P.order = d.order;

@@ -282,3 +282,29 @@ def make_batch(count, layout=COL, lo=4, hi=512, ld_pad=0, alpha=1.5, beta=0.5,
         Cs.append(fill_stored(layout, int(m[i]), int(n[i]), int(ldc[i]),
                               g.uniform(-1, 1, (int(m[i]), int(n[i]))), np.float32))
     return Batch(layout, count, m, n, k, tA, tB, lda, ldb, ldc, alpha, beta, As, Bs, Cs)
+
+
+def mx_device_operands(form, n, seed=BASE_SEED, device="cuda"):
+    """Large square mixed-precision operands drawn directly on the GPU (torch's seeded
+    generator; same value recipe as make_mx_case: U[-1, 1] with rows of A and columns of B
+    scaled by 2^u, u ~ U[-8, 8]), column-major, no transpose, ld = n.  Returns
+    (A, B, a_scale, b_scale, A32, B32) as torch tensors; A32/B32 are the binary32 values
+    (None for the E4M3 form, whose codes are drawn from scaled values)."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    u_row = torch.rand(n, device=device, generator=g) * 16 - 8
+    u_col = torch.rand(n, device=device, generator=g) * 16 - 8
+    # column-major storage: element (i, p) of A at A[p, i] of a row-major (k, m) tensor
+    A32 = (torch.rand(n, n, device=device, generator=g) * 2 - 1) * torch.exp2(u_row)[None, :]
+    B32 = (torch.rand(n, n, device=device, generator=g) * 2 - 1) * torch.exp2(u_col)[:, None]
+    sa = sb = None
+    if form == FORM_BF16:
+        A, B = A32.to(torch.bfloat16), B32.to(torch.bfloat16)
+    elif form == FORM_E4M3:
+        sa = torch.exp2(8 - torch.round(u_row))
+        sb = torch.exp2(8 - torch.round(u_col))
+        A = (A32 * sa[None, :]).to(torch.float8_e4m3fn).view(torch.uint8)
+        B = (B32 * sb[:, None]).to(torch.float8_e4m3fn).view(torch.uint8)
+    else:
+        A, B = A32, B32
+    return A, B, sa, sb, A32, B32

@@ -101,19 +101,70 @@ def plan(h, m, n, k, layout=0, dtype=F.FIP_F64, policy=F.FIP_PACK_AUTO, tile=-1,
     return p
 
 
+def _tile_of(w, tilesM, tilesN, order, group=8):
+    """Python replica of the launch's workgroup -> tile map (XCD w % 8 takes one contiguous
+    run of a grouped order)."""
+    T = tilesM * tilesN
+    xcd, local = w & 7, w >> 3
+    q, rr = T >> 3, T & 7
+    t = xcd * q + min(xcd, rr) + local
+    g = t // (group * tilesN)
+    first = g * group
+    gsize = min(tilesM - first, group)
+    rem = t - g * group * tilesN
+    if order == 0:
+        return first + rem % gsize, rem // gsize
+    rnd, slot = divmod(rem, tilesN)
+    return first + (slot + rnd) % gsize, slot
+
+
+def _expected_pack(tilesM, tilesN, resident, order=0):
+    """Sec. 3.3 on the GPU schedule: pack an operand when most (XCD, panel) pairs see the
+    panel again in a later round of that XCD (round = local index // (resident / 8))."""
+    T = tilesM * tilesN
+    if T <= resident:
+        return 0, 0
+    per = resident // 8
+    seenA, seenB = {}, {}
+    for w in range(T):
+        tm, tn = _tile_of(w, tilesM, tilesN, order)
+        r = (w >> 3) // per
+        seenA.setdefault((w & 7, tm), set()).add(r)
+        seenB.setdefault((w & 7, tn), set()).add(r)
+    fa = sum(len(v) > 1 for v in seenA.values()) / len(seenA)
+    fb = sum(len(v) > 1 for v in seenB.values()) / len(seenB)
+    return int(tilesN > 1 and fa >= 0.5), int(tilesM > 1 and fb >= 0.5)
+
+
 def test_pack_table_of_the_paper(h):
-    """Sec. 3.3: n <= n_R -> do not pack A; m <= m_R -> do not pack B (tile = MT x NT),
-    applied to launches with more tiles than fit on the device at once."""
+    """Sec. 3.3: n <= n_R -> do not pack A; m <= m_R -> do not pack B (tile = MT x NT); and
+    on the GPU a pack only pays when a later round of workgroups on the same XCD reads the
+    panel again (a single round, or a panel used by one round only, is not packed)."""
     for tile, T, slots in [(0, 128, 512), (1, 64, 1024), (2, 32, 1536)]:
-        big = (slots + 1) * T  # one tile row or column that alone needs several rounds
-        for m, n, pa, pb in [(T, T, 0, 0), (T, big, 1, 0), (big, T, 0, 1),
-                             (40 * T, 40 * T, 1, 1)]:
+        for m, n in [(T, T), (T, (2 * slots + 1) * T), ((2 * slots + 1) * T, T),
+                     (T, (slots + 1) * T), (40 * T, 40 * T), (64 * T, 64 * T),
+                     (128 * T, 128 * T), (200 * T, 30 * T), (30 * T, 200 * T)]:
             for layout in (0, 1):
-                p = plan(h, m, n, 64, layout=layout, tile=tile)
-                assert (p.pack_a, p.pack_b) == (pa, pb), (tile, m, n, layout)
-                assert p.MT == T and p.NT == T
-                if not pa and not pb:
-                    assert p.workspace_bytes == 0 and p.copies == 0
+                for order in (0, 1):
+                    assert F.fip_set_attr(h, F.FIP_ATTR_ORDER, order) == 0
+                    p = plan(h, m, n, 64, layout=layout, tile=tile)
+                    # kernel terms: row-major storage swaps the operands
+                    tM, tN = (m // T, n // T) if layout == 0 else (n // T, m // T)
+                    ea, eb = _expected_pack(tM, tN, slots, order)
+                    if layout == 1:
+                        ea, eb = eb, ea
+                    assert (p.pack_a, p.pack_b) == (ea, eb), (tile, m, n, layout, order)
+                    assert p.MT == T and p.NT == T
+                    if not p.pack_a and not p.pack_b:
+                        assert p.workspace_bytes == 0 and p.copies == 0
+    assert F.fip_set_attr(h, F.FIP_ATTR_ORDER, 0) == 0
+    # the shapes the rule is about: one tile row reused by many later rounds packs A only
+    p = plan(h, 128, (2 * 512 + 1) * 128 * 8, 64, tile=0)
+    assert (p.pack_a, p.pack_b) == (1, 0)
+    p = plan(h, 64 * 128, 64 * 128, 64, tile=0)     # one band per XCD: B columns never recur
+    assert (p.pack_a, p.pack_b) == (1, 0)
+    p = plan(h, 128 * 128, 128 * 128, 64, tile=0)   # several bands per XCD: both recur
+    assert (p.pack_a, p.pack_b) == (1, 1)
 
 
 def test_single_round_launches_do_not_pack(h):
