@@ -85,10 +85,13 @@ enum {
     /* Tile order inside an XCD's run: 0 = GROUP_M tiles of a column
        consecutive, 1 = consecutive tiles in distinct columns.  Default 0. */
     FIP_ATTR_ORDER = 7,
-    /* Batched calls: problems with max(m, n) <= value use 32 x 32 C tiles,
-       the others 64 x 64.  -1 (default): the value fip_vbatched_tune chose for
-       the batch's shapes, else 64. */
+    /* Batched calls: problems with max(m, n) <= value use 16 x 16 C tiles,
+       the others 32 x 32.  -1 (default): the value fip_vbatched_tune chose for
+       the batch's shapes, else 16. */
     FIP_ATTR_VB_SPLIT = 8,
+    /* Read only: workgroups (one wave each) a batched launch keeps resident
+       on the device; the batch's tiles are dealt round-robin over them. */
+    FIP_ATTR_VB_GRID = 9,
     /* Read only: the 64-bit epoch stamp of the most recent fused call
        (claims and publish flags of that call hold this value; stamps are
        unique within the process). */
@@ -264,6 +267,8 @@ int fip_quantize_fp8(fip_handle_t handle, int layout, int64_t rows, int64_t cols
  * op(A_i) m[i] x k[i], op(B_i) k[i] x n[i], all in one persistent launch (the
  * paper's single code path applied to a whole batch of small and uneven
  * problems: every problem runs the unpacked tile path, Sec. 2.3 and 3.3).
+ * Each tile (32 x 32 or 16 x 16, see FIP_ATTR_VB_SPLIT) is computed by one
+ * wave; the waves of the grid take tiles from a longest-first list.
  *   m, n, k, transA, transB: HOST arrays of count entries (the planner needs
  *     them; a batch with the same shapes reuses the plan uploaded by the
  *     previous call).
@@ -273,9 +278,8 @@ int fip_quantize_fp8(fip_handle_t handle, int layout, int64_t rows, int64_t cols
  *   flags: 0, or FIP_VB_GRAPH: run the batch as a HIP graph, instantiated on
  *     the first call and replayed while the call repeats with the same shapes,
  *     pointer arrays, alpha, beta, workspace and stream.
- * Workspace: fip_vbatched_workspace bytes (problem table, tile list, two
- * counters that each launch leaves at zero); it must hold the plan between
- * calls of the same batch.  A call with a new batch waits for the stream and
+ * Workspace: fip_vbatched_workspace bytes (problem table and tile list); it
+ * must hold the plan between calls of the same batch.  A call with a new batch waits for the stream and
  * copies the new plan in (synchronous host-to-device copies).
  * Quick returns: count = 0, or alpha = 0 and beta = 1.  alpha = 0 reads no
  * A, B; beta = 0 reads no C.  k[i] = 0 gives C_i := beta*C_i.
@@ -294,10 +298,10 @@ int fip_sgemm_vbatched(fip_handle_t handle, int layout, int64_t count, const int
 
 /*
  * Autotuner of the batched call: times the batch (median of 3 launches after
- * a warm-up) for each candidate FIP_ATTR_VB_SPLIT threshold (0, 16, 32, 48,
- * 64, 96, 128, 192, 256, all), keeps the fastest for this batch's shapes in
+ * a warm-up) for each candidate FIP_ATTR_VB_SPLIT threshold (0, 8, 16, 24,
+ * 32, 48, 64, all), keeps the fastest for this batch's shapes in
  * the handle (later fip_sgemm_vbatched calls with the same shapes use it) and
- * writes it to *split_out.  It runs the batch 40 times: C is overwritten with
+ * writes it to *split_out.  It runs the batch 32 times: C is overwritten with
  * unspecified values, so pass scratch C matrices of the same shapes.
  * Arguments as in fip_sgemm_vbatched; position 17 is split_out.  Synchronous.
  */

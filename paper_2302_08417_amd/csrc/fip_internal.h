@@ -114,7 +114,7 @@ enum VbFlags : int32_t { kVbAKmajor = 1, kVbBKmajor = 2, kVbSwapped = 4 };
 struct VbProblem {
     int32_t M, N, K;
     int32_t flags;   // VbFlags: kernel A-/B-side K-major; swapped = row-major storage
-    int32_t cls;     // tile class: 1 = 64 x 64, 2 = 32 x 32
+    int32_t cls;     // tile class: 1 = 32 x 32, 2 = 16 x 16 (one wave per tile)
     int32_t pad[3];
 };
 struct VbItem {
@@ -123,17 +123,16 @@ struct VbItem {
 };
 struct VbLaunchDesc {
     const VbProblem* probs;        // device
-    const VbItem* items;           // device, in execution order
+    const VbItem* items;           // device: XCD x's items at [xcd_off[x], xcd_off[x+1])
     int64_t total;                 // number of items
+    int64_t xcd_off[kCopies + 1];
     const float* const* A; const int64_t* lda;   // caller's device arrays
     const float* const* B; const int64_t* ldb;
     float* const* C; const int64_t* ldc;
     float alpha, beta;
-    uint32_t* ticket;              // device, 2 words, zero between launches
     hipStream_t stream;
 };
 hipError_t launch_vbatched(const VbLaunchDesc& d);
-hipError_t launch_vb_zero(uint32_t* ticket, hipStream_t stream);
 hipError_t build_vbatched_graph(const VbLaunchDesc& d, hipGraphExec_t* exec);
 int vbatched_grid();   // resident workgroups of the batched kernel on the device
 

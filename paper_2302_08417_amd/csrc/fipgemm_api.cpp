@@ -46,6 +46,7 @@ struct VbState {
     int split = -1;
     void* ws = nullptr;
     int64_t total = 0;
+    int64_t xcd_off[fip::kCopies + 1] = {};
     int64_t off_probs = 0, off_items = 0;
     std::vector<fip::VbProblem> probs;
     std::vector<fip::VbItem> items;
@@ -514,7 +515,7 @@ int gemm_mx_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, in
 
 // ---- batched binary32 GEMM ----------------------------------------------------
 
-constexpr int kVbDefaultSplit = 64;   // untuned: max(m, n) <= 64 -> 32 x 32 tiles
+constexpr int kVbDefaultSplit = 16;   // untuned: max(m, n) <= 16 -> 16 x 16 tiles
 constexpr int kVbMaxTiles = 65535;    // tile indices are 16-bit
 
 uint64_t fnv(uint64_t h, const void* p, size_t n)
@@ -542,15 +543,16 @@ uint64_t vb_signature(int layout, int64_t count, const int32_t* m, const int32_t
 
 int64_t vb_tiles(int64_t M, int64_t N, int mt) { return cdiv(M, mt) * cdiv(N, mt); }
 
-// Workspace bytes: counters, problem table, and the item list of the
-// smallest tile class for every problem (the most items any split yields).
+// Workspace bytes: a 256-byte reserved header, the problem table, and the
+// item list of the smallest tile class for every problem (the most items any
+// split yields).
 int64_t vb_workspace_bytes(int layout, int64_t count, const int32_t* m, const int32_t* n,
                            int64_t* off_probs, int64_t* off_items)
 {
     int64_t items = 0;
     for (int64_t i = 0; i < count; ++i) {
         const KernelShape ks = kernel_shape(layout, m[i], n[i]);
-        items += vb_tiles(ks.M, ks.N, 32);
+        items += vb_tiles(ks.M, ks.N, 16);
     }
     int64_t off = 256;
     *off_probs = off; off = align256(off + count * (int64_t)sizeof(fip::VbProblem));
@@ -570,8 +572,8 @@ int vb_check(int layout, int64_t count, const int32_t* m, const int32_t* n, cons
     if (tA == nullptr) return 7;
     if (tB == nullptr) return 8;
     for (int64_t i = 0; i < count; ++i) {
-        if (m[i] < 0 || m[i] > 32 * kVbMaxTiles) return 4;
-        if (n[i] < 0 || n[i] > 32 * kVbMaxTiles) return 5;
+        if (m[i] < 0 || m[i] > 16 * kVbMaxTiles) return 4;
+        if (n[i] < 0 || n[i] > 16 * kVbMaxTiles) return 5;
         if (k[i] < 0) return 6;
         if (!valid_trans(tA[i])) return 7;
         if (!valid_trans(tB[i])) return 8;
@@ -600,23 +602,47 @@ int vb_upload(fip_handle_s* h, int layout, int64_t count, const int32_t* m, cons
         p.flags = (akm ? fip::kVbAKmajor : 0) | (bkm ? fip::kVbBKmajor : 0) |
                   (ks.swapped ? fip::kVbSwapped : 0);
         p.cls = std::max(ks.M, ks.N) <= split ? 2 : 1;
-        const int mt = p.cls == 1 ? 64 : 32;
-        cost[i] = (cdiv(k[i], 32) + 1) * mt * mt;   // one tile's k-steps plus its epilogue
+        const int mt = p.cls == 1 ? 32 : 16;
+        cost[i] = (cdiv(k[i], 16) + 1) * mt * mt;   // one tile's k-blocks plus its epilogue
         order[i] = i;
     }
-    // longest tiles first; a problem's tiles stay together
+    // Whole problems to XCDs, longest problem first to the least loaded XCD
+    // (a problem's tiles then share one L2), then each XCD's problems longest
+    // tile first, a problem's tiles together.
+    std::vector<int64_t> total_cost(count);
+    for (int64_t i = 0; i < count; ++i) {
+        const fip::VbProblem& p = v.probs[i];
+        const int mt = p.cls == 1 ? 32 : 16;
+        total_cost[i] = cost[i] * cdiv(p.M, mt) * cdiv(p.N, mt);
+    }
     std::stable_sort(order.begin(), order.end(),
-                     [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-    v.items.clear();
+                     [&](int64_t a, int64_t b) { return total_cost[a] > total_cost[b]; });
+    std::vector<std::vector<int64_t>> bins(fip::kCopies);
+    int64_t load[fip::kCopies] = {};
     for (int64_t oi = 0; oi < count; ++oi) {
         const int64_t i = order[oi];
-        const fip::VbProblem& p = v.probs[i];
-        const int mt = p.cls == 1 ? 64 : 32;
-        const int64_t tm_n = cdiv(p.M, mt), tn_n = cdiv(p.N, mt);
-        for (int64_t tn = 0; tn < tn_n; ++tn)
-            for (int64_t tm = 0; tm < tm_n; ++tm)
-                v.items.push_back(fip::VbItem{(int32_t)i, (uint16_t)tm, (uint16_t)tn});
+        if (total_cost[i] == 0) continue;
+        int best = 0;
+        for (int x = 1; x < fip::kCopies; ++x)
+            if (load[x] < load[best]) best = x;
+        load[best] += total_cost[i];
+        bins[best].push_back(i);
     }
+    v.items.clear();
+    for (int x = 0; x < fip::kCopies; ++x) {
+        std::vector<int64_t>& b = bins[x];
+        std::stable_sort(b.begin(), b.end(), [&](int64_t p, int64_t q) { return cost[p] > cost[q]; });
+        v.xcd_off[x] = (int64_t)v.items.size();
+        for (int64_t i : b) {
+            const fip::VbProblem& p = v.probs[i];
+            const int mt = p.cls == 1 ? 32 : 16;
+            const int64_t tm_n = cdiv(p.M, mt), tn_n = cdiv(p.N, mt);
+            for (int64_t tn = 0; tn < tn_n; ++tn)
+                for (int64_t tm = 0; tm < tm_n; ++tm)
+                    v.items.push_back(fip::VbItem{(int32_t)i, (uint16_t)tm, (uint16_t)tn});
+        }
+    }
+    v.xcd_off[fip::kCopies] = (int64_t)v.items.size();
     if (hipStreamSynchronize(h->stream) != hipSuccess) return FIP_ERR_LAUNCH;
     char* ws = static_cast<char*>(h->ws);
     if (count > 0 &&
@@ -626,8 +652,6 @@ int vb_upload(fip_handle_s* h, int layout, int64_t count, const int32_t* m, cons
     if (!v.items.empty() &&
         hipMemcpy(ws + off_items, v.items.data(), v.items.size() * sizeof(fip::VbItem),
                   hipMemcpyHostToDevice) != hipSuccess)
-        return FIP_ERR_LAUNCH;
-    if (fip::launch_vb_zero(reinterpret_cast<uint32_t*>(ws), h->stream) != hipSuccess)
         return FIP_ERR_LAUNCH;
     v.sig = sig;
     v.split = split;
@@ -649,9 +673,9 @@ fip::VbLaunchDesc vb_desc(const fip_handle_s* h, float alpha, const float* const
     d.probs = reinterpret_cast<const fip::VbProblem*>(ws + v.off_probs);
     d.items = reinterpret_cast<const fip::VbItem*>(ws + v.off_items);
     d.total = v.total;
+    for (int x = 0; x <= fip::kCopies; ++x) d.xcd_off[x] = v.xcd_off[x];
     d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = C; d.ldc = ldc;
     d.alpha = alpha; d.beta = beta;
-    d.ticket = reinterpret_cast<uint32_t*>(ws);
     d.stream = h->stream;
     return d;
 }
@@ -764,6 +788,7 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_ORDER: *value = handle->order; return 0;
     case FIP_ATTR_EPOCH: *value = (int64_t)handle->epoch; return 0;
     case FIP_ATTR_VB_SPLIT: *value = handle->vb_split; return 0;
+    case FIP_ATTR_VB_GRID: *value = fip::vbatched_grid(); return 0;
     default: return 2;
     }
 }
@@ -980,7 +1005,7 @@ int fip_vbatched_tune(fip_handle_t handle, int layout, int64_t count, const int3
         *split_out = kVbDefaultSplit;
         if (count == 0) return 0;
         // candidate thresholds on max(m, n) for 32 x 32 tiles
-        const int cands[] = {0, 16, 32, 48, 64, 96, 128, 192, 256, 1 << 30};
+        const int cands[] = {0, 8, 16, 24, 32, 48, 64, 1 << 30};
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return FIP_ERR_LAUNCH;
         if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FIP_ERR_LAUNCH; }

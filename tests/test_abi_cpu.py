@@ -286,8 +286,8 @@ def test_vbatched_workspace_and_positions(h):
     m, n, k, tA, tB = _vb_arrays()
     rc, nbytes = F.fip_vbatched_workspace(h, 0, 4, m, n, k, tA, tB)
     assert rc == 0
-    # 256 B of counters, 4 x 32 B problems, items of the 32 x 32 class, each 8 B
-    tiles = sum(-(-int(a) // 32) * -(-int(b) // 32) for a, b in zip(m, n))
+    # a 256 B header, 4 x 32 B problems, items of the 16 x 16 class, each 8 B
+    tiles = sum(-(-int(a) // 16) * -(-int(b) // 16) for a, b in zip(m, n))
     expect = 256 + 256 + -(-tiles * 8 // 256) * 256
     assert nbytes == expect
     rc, nrow = F.fip_vbatched_workspace(h, 1, 4, m, n, k, tA, tB)   # row-major: same tiles
