@@ -70,15 +70,18 @@ enum MxForm : int32_t {
     kMxX3Fast = 3,   // A, B binary32, two bfloat16 terms, three products
 };
 constexpr int kMxTile = 128;                     // C tile 128 x 128, 2 x 2 waves
+constexpr int kMxTileBig = 256;                  // bfloat16 / E4M3 only: 128 x 128 per wave
 inline int mx_kt(int form) { return form == kMxBF16 ? 64 : form == kMxFP8 ? 128 : 32; }
 inline int mx_planes(int form) { return form == kMxX3 ? 3 : form == kMxX3Fast ? 2 : 1; }
 inline int mx_src_bytes(int form) { return form == kMxBF16 ? 2 : form == kMxFP8 ? 1 : 4; }
 inline int mx_pack_bytes(int form) { return form == kMxFP8 ? 1 : 2; }  // per plane element
 // Workgroups of one mixed-precision tile kernel that fit on a CU (LDS-bound).
-inline int mx_per_cu(int form) { return form == kMxBF16 || form == kMxFP8 ? 2 : 1; }
+inline int mx_per_cu(int form, int mt) { return mt == 128 && (form == kMxBF16 || form == kMxFP8) ? 2 : 1; }
+inline bool mx_has_big(int form) { return form == kMxBF16 || form == kMxFP8; }
 
 struct MxLaunchDesc {
     int form;              // MxForm
+    int mt;                // tile extent: 128, or 256 (bfloat16 / E4M3)
     int mode;              // Mode
     int pack_a, pack_b, no_publish, stats, order;
     int c_bf16;            // C stored as bfloat16 (else binary32)

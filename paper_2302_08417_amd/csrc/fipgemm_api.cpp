@@ -73,6 +73,7 @@ struct fip_handle_s {
     fip_plan_t last;
     int has_last;
     int vb_split;     // FIP_ATTR_VB_SPLIT (-1: tuned or default)
+    int mx_tile;      // FIP_ATTR_MX_TILE (-1: planner's choice, 128, 256)
     VbState* vb;
 };
 
@@ -190,12 +191,16 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     int cls, MT, KT;
     int64_t resident;
     if (form >= 0) {
-        // one tile shape; a packed element is PLANES values of the packed type
+        // 128 x 128 tiles (256 x 256 for bfloat16 / E4M3 on request); a
+        // packed element is PLANES values of the packed type
         cls = 0;
-        MT = fip::kMxTile;
+        // 256 x 256 runs one wave per SIMD and measured slower than 128 x 128
+        // at every size tried (1024 .. 16384), so it is used only on request
+        const bool big = h->mx_tile == 256 && fip::mx_has_big(form);
+        MT = big ? fip::kMxTileBig : fip::kMxTile;
         KT = fip::mx_kt(form);
         pl->elem = fip::mx_planes(form) * fip::mx_pack_bytes(form);
-        resident = 256 * fip::mx_per_cu(form);
+        resident = 256 * fip::mx_per_cu(form, MT);
     } else {
         pl->elem = dtype == FIP_F64 ? 8 : 4;
         cls = h->tile_override >= 0 ? h->tile_override : choose_tile_class(pl->ks.M, pl->ks.N);
@@ -434,6 +439,7 @@ void fill_mx_desc(const fip_handle_s* h, const Plan& pl, int form, int layout, i
 {
     memset(d, 0, sizeof(*d));
     d->form = form;
+    d->mt = pl.pub.MT;
     d->mode = pl.mode;
     d->pack_a = pl.kpack_a; d->pack_b = pl.kpack_b;
     d->no_publish = h->no_publish;
@@ -722,6 +728,7 @@ int fip_create(fip_handle_t* handle)
     h->tile_override = -1;
     h->order = 0;
     h->vb_split = -1;
+    h->mx_tile = -1;
     h->vb = nullptr;
     *handle = h;
     return 0;
@@ -771,6 +778,10 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
         if (value < -1 || value > (int64_t)1 << 30) return 3;
         handle->vb_split = (int)value;
         return 0;
+    case FIP_ATTR_MX_TILE:
+        if (value != -1 && value != 128 && value != 256) return 3;
+        handle->mx_tile = (int)value;
+        return 0;
     default:
         return 2;
     }
@@ -789,6 +800,7 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_EPOCH: *value = (int64_t)handle->epoch; return 0;
     case FIP_ATTR_VB_SPLIT: *value = handle->vb_split; return 0;
     case FIP_ATTR_VB_GRID: *value = fip::vbatched_grid(); return 0;
+    case FIP_ATTR_MX_TILE: *value = handle->mx_tile; return 0;
     default: return 2;
     }
 }

@@ -17,8 +17,12 @@
 //   BF16X3F   the same with two terms and three products.
 // Accumulation is binary32 in every form (MFMA 16x16x32 bf16, 16x16x128 fp8).
 //
-// Structure (shared with the FP64/FP32 kernel): one workgroup per 128 x 128 C
-// tile, 2 x 2 waves of 64 x 64, k-steps of KT, two LDS buffers.  Fused
+// Structure (shared with the FP64/FP32 kernel): one workgroup per MT x MT C
+// tile, 2 x 2 waves of MT/2 x MT/2, k-steps of KT, two LDS buffers.  MT = 128
+// for every form; bfloat16 and E4M3 also have MT = 256 on request (128 x 128
+// per wave, accumulators in the AGPRs), which doubles a wave's MFMA work per
+// byte read from LDS but leaves one wave per SIMD to hide LDS latency; it
+// measured slower, so 128 is the default.  Fused
 // packing per operand panel: first toucher per XCD claims and packs, publishes
 // a completion flag once its stores are acknowledged; other workgroups read
 // the packed copy from the moment they see the flag, the unpacked operand
@@ -47,16 +51,13 @@ typedef unsigned u2 __attribute__((ext_vector_type(2)));
 typedef unsigned u4a __attribute__((ext_vector_type(4), aligned(4)));
 typedef unsigned u2a __attribute__((ext_vector_type(2), aligned(4)));
 
-constexpr int MT = kMxTile;   // 128: C tile is MT x MT
-constexpr int NTHR = 256;     // 2 x 2 waves
-constexpr int NR = 4;         // operand rows per thread's micro-block
-constexpr int WT = 64;        // per-wave C sub-tile
-constexpr int FB = WT / 16;   // 16 x 16 MFMA blocks per wave side
+constexpr int NTHR = 256;     // 2 x 2 waves; C tile MT x MT (128 or 256), per wave MT/2
 
 // Per-form constants.  KT: k-step; SB: bytes per source element; PL: packed
 // planes; EB: bytes per packed element; VK: k extent of a thread's micro-block
 // (a micro-block is NR rows x VK k-values of the operand chunk; 256 threads
-// cover the 128 x KT chunk); WPR: 32-bit words per micro-block row and plane.
+// cover the MT x KT chunk, NR = 4 for MT = 128, 8 for MT = 256); WPR: 32-bit
+// words per micro-block row and plane.
 template <int FORM> struct Form;
 template <> struct Form<kMxBF16> {
     typedef uint16_t S;
@@ -75,11 +76,15 @@ template <> struct Form<kMxX3Fast> {
     static constexpr int KT = 32, SB = 4, PL = 2, EB = 2, VK = 4;
 };
 
-template <int FORM> struct Geo {
+template <int FORM, int MT_> struct Geo {
     typedef Form<FORM> Fm;
+    static constexpr int MT = MT_;
     static constexpr int KT = Fm::KT, PL = Fm::PL, EB = Fm::EB, VK = Fm::VK, SB = Fm::SB;
     static constexpr int WPR = VK * EB / 4;
     static constexpr int KGROUPS = KT / VK;               // micro-blocks along k (8)
+    static constexpr int NR = MT * KT / (NTHR * VK);      // rows per thread's micro-block
+    static constexpr int WT = MT / 2;                     // per-wave C sub-tile
+    static constexpr int FB = WT / 16;                    // 16 x 16 MFMA blocks per wave side
     static constexpr int PITCH = KT * EB + 16;            // LDS row pitch in bytes
     static constexpr int LDS_PLANE = MT * PITCH;
     static constexpr int LDS_OPERAND = PL * LDS_PLANE;    // one buffer of one operand
@@ -101,9 +106,10 @@ __device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float
 // producer, to the pack buffer): thread b holds rows x0 .. x0+3 (x0 = 4*(b/8))
 // and k-values p0 .. p0+VK-1 (p0 = VK*(b%8)) of the chunk, already in packed
 // form: for each plane and row, WPR words of consecutive k.
-template <int FORM, bool KC>
+template <int FORM, bool KC, int MT>
 struct Stage {
-    typedef Geo<FORM> G;
+    typedef Geo<FORM, MT> G;
+    static constexpr int NR = G::NR;
     typedef typename Form<FORM>::S S;
     static constexpr int PL = G::PL, WPR = G::WPR, VK = G::VK, EB = G::EB, SB = G::SB;
     uint32_t w[PL][NR][WPR];
@@ -164,26 +170,37 @@ struct Stage {
                 }
             }
         } else {
-            // columns are contiguous along mn: VK loads of NR elements each,
-            // transposed into rows in registers
+            // columns are contiguous along mn: VK loads of NR elements each
+            // (NR*SB bytes, in 16-, 8- or 4-byte pieces), transposed into rows
+            // in registers
             clear();
+            constexpr int NW = NR * SB / 4;   // words per load
 #pragma unroll
             for (int i = 0; i < VK; ++i) {
                 const char* p = src + i * ldb;
-                if constexpr (FORM == kMxBF16) {
-                    const u2 v = *reinterpret_cast<const u2a*>(p);
-                    put(0, i, (S)(v[0] & 0xFFFFu));
-                    put(1, i, (S)(v[0] >> 16));
-                    put(2, i, (S)(v[1] & 0xFFFFu));
-                    put(3, i, (S)(v[1] >> 16));
-                } else if constexpr (FORM == kMxFP8) {
-                    const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+                uint32_t v[NW];
+                if constexpr (NW % 4 == 0) {
 #pragma unroll
-                    for (int j = 0; j < NR; ++j) put(j, i, (S)((v >> (8 * j)) & 0xFFu));
+                    for (int c = 0; c < NW / 4; ++c) {
+                        const u4 x = *reinterpret_cast<const u4a*>(p + 16 * c);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) v[4 * c + u] = x[u];
+                    }
+                } else if constexpr (NW == 2) {
+                    const u2 x = *reinterpret_cast<const u2a*>(p);
+                    v[0] = x[0];
+                    v[1] = x[1];
                 } else {
-                    const u4 v = *reinterpret_cast<const u4a*>(p);
+                    v[0] = *reinterpret_cast<const uint32_t*>(p);
+                }
 #pragma unroll
-                    for (int j = 0; j < NR; ++j) put(j, i, __uint_as_float(v[j]));
+                for (int j = 0; j < NR; ++j) {
+                    if constexpr (FORM == kMxBF16)
+                        put(j, i, (S)((v[j >> 1] >> (16 * (j & 1))) & 0xFFFFu));
+                    else if constexpr (FORM == kMxFP8)
+                        put(j, i, (S)((v[j >> 2] >> (8 * (j & 3))) & 0xFFu));
+                    else
+                        put(j, i, __uint_as_float(v[j]));
                 }
             }
         }
@@ -285,47 +302,48 @@ struct MxParams {
 // of k (8 bf16 = 16 bytes, or 32 fp8 bytes) starting at run (l/16); A and B
 // use the same k assignment, which is all the product needs.  Output item r
 // of lane l is C[4*(l/16) + r][l%16].
-template <int FORM>
+template <int FORM, int MT>
 struct Mma {
-    typedef Geo<FORM> G;
+    typedef Geo<FORM, MT> G;
     static constexpr int NACC = (FORM == kMxX3 || FORM == kMxX3Fast) ? 2 : 1;
+    static constexpr int FB = G::FB;
 
     __device__ __forceinline__ static void step(const char* la, const char* lb, int lane,
                                                 f4 (&acc)[NACC][FB][FB])
     {
         const int row = lane & 15, run = lane >> 4;
+        // B fragments of the whole wave row first, then one A fragment at a
+        // time against all of them (FB x FB MFMAs per A fragment)
         if constexpr (FORM == kMxFP8) {
-            i8v fa[FB], fb[FB];
-#pragma unroll
-            for (int a = 0; a < FB; ++a)
-                fa[a] = *reinterpret_cast<const i8v*>(la + (a * 16 + row) * G::PITCH + run * 32);
+            i8v fb[FB];
 #pragma unroll
             for (int b = 0; b < FB; ++b)
                 fb[b] = *reinterpret_cast<const i8v*>(lb + (b * 16 + row) * G::PITCH + run * 32);
 #pragma unroll
-            for (int a = 0; a < FB; ++a)
+            for (int a = 0; a < FB; ++a) {
+                const i8v fa = *reinterpret_cast<const i8v*>(la + (a * 16 + row) * G::PITCH + run * 32);
 #pragma unroll
                 for (int b = 0; b < FB; ++b)
                     acc[0][a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                        fa[a], fb[b], acc[0][a][b], 0, 0, 0, 0, 0, 0);
+                        fa, fb[b], acc[0][a][b], 0, 0, 0, 0, 0, 0);
+            }
         } else if constexpr (FORM == kMxBF16) {
 #pragma unroll
             for (int s = 0; s < G::KT / 32; ++s) {
-                bf8v fa[FB], fb[FB];
-#pragma unroll
-                for (int a = 0; a < FB; ++a)
-                    fa[a] = *reinterpret_cast<const bf8v*>(la + (a * 16 + row) * G::PITCH +
-                                                           (s * 32 + run * 8) * 2);
+                bf8v fb[FB];
 #pragma unroll
                 for (int b = 0; b < FB; ++b)
                     fb[b] = *reinterpret_cast<const bf8v*>(lb + (b * 16 + row) * G::PITCH +
                                                            (s * 32 + run * 8) * 2);
 #pragma unroll
-                for (int a = 0; a < FB; ++a)
+                for (int a = 0; a < FB; ++a) {
+                    const bf8v fa = *reinterpret_cast<const bf8v*>(la + (a * 16 + row) * G::PITCH +
+                                                                   (s * 32 + run * 8) * 2);
 #pragma unroll
                     for (int b = 0; b < FB; ++b)
-                        acc[0][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b],
+                        acc[0][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[b],
                                                                                acc[0][a][b], 0, 0, 0);
+                }
             }
         } else {
             // split forms: KT = 32, one substep; planes PL of each operand
@@ -363,16 +381,16 @@ struct Mma {
     }
 };
 
-template <int FORM, bool AKC, bool BKC>
-__global__ void __launch_bounds__(NTHR, (FORM == kMxBF16 || FORM == kMxFP8) ? 2 : 1)
+template <int FORM, int MT, bool AKC, bool BKC>
+__global__ void __launch_bounds__(NTHR, (MT == 128 && (FORM == kMxBF16 || FORM == kMxFP8)) ? 2 : 1)
 gemm_mx_kernel(const MxParams P)
 {
-    typedef Geo<FORM> G;
-    typedef Stage<FORM, AKC> StA;
-    typedef Stage<FORM, BKC> StB;
+    typedef Geo<FORM, MT> G;
+    typedef Stage<FORM, AKC, MT> StA;
+    typedef Stage<FORM, BKC, MT> StB;
     typedef typename Form<FORM>::S S;
-    constexpr int KT = G::KT, SB = G::SB;
-    constexpr int NACC = Mma<FORM>::NACC;
+    constexpr int KT = G::KT, SB = G::SB, WT = G::WT, FB = G::FB;
+    constexpr int NACC = Mma<FORM, MT>::NACC;
 
     __shared__ __attribute__((aligned(16))) char sA[2][G::LDS_OPERAND];
     __shared__ __attribute__((aligned(16))) char sB[2][G::LDS_OPERAND];
@@ -485,7 +503,7 @@ gemm_mx_kernel(const MxParams P)
             if (wantB && !bpk) fb = load_flag(bdone);
         }
         if (more) load_chunks(q + 1);
-        Mma<FORM>::step(sA[cur] + wm * WT * G::PITCH, sB[cur] + wn * WT * G::PITCH, lane, acc);
+        Mma<FORM, MT>::step(sA[cur] + wm * WT * G::PITCH, sB[cur] + wn * WT * G::PITCH, lane, acc);
         if (more) {
             ra.store_lds(sA[cur ^ 1], tid);
             rb.store_lds(sB[cur ^ 1], tid);
@@ -581,10 +599,10 @@ gemm_mx_kernel(const MxParams P)
 
 // Standalone pack of both operands into copy 0 (pack-then-compute baseline):
 // one chunk per workgroup, same registers and stores as a producer.
-template <int FORM, bool AKC, bool BKC>
+template <int FORM, int MT, bool AKC, bool BKC>
 __global__ void __launch_bounds__(NTHR) pack_mx_kernel(const MxParams P)
 {
-    typedef Geo<FORM> G;
+    typedef Geo<FORM, MT> G;
     typedef typename Form<FORM>::S S;
     const int tid = threadIdx.x;
     const int nK = P.nK;
@@ -592,13 +610,13 @@ __global__ void __launch_bounds__(NTHR) pack_mx_kernel(const MxParams P)
     const int64_t b = blockIdx.x;
     if (b < nA) {
         const int64_t t = b / nK, q = b % nK;
-        Stage<FORM, AKC> r;
+        Stage<FORM, AKC, MT> r;
         r.load_edge(reinterpret_cast<const S*>(P.A), P.a_ld, P.M, P.K, t * MT, q * G::KT, tid);
         r.store_pack(P.apack + (t * nK + q) * G::PACK_CHUNK, tid);
     } else {
         const int64_t bb = b - nA;
         const int64_t t = bb / nK, q = bb % nK;
-        Stage<FORM, BKC> r;
+        Stage<FORM, BKC, MT> r;
         r.load_edge(reinterpret_cast<const S*>(P.B), P.b_ld, P.N, P.K, t * MT, q * G::KT, tid);
         r.store_pack(P.bpack + (t * nK + q) * G::PACK_CHUNK, tid);
     }
@@ -723,7 +741,7 @@ unsigned grid_for(int64_t total)
     return (unsigned)b;
 }
 
-MxParams make_mx_params(const MxLaunchDesc& d)
+MxParams make_mx_params(const MxLaunchDesc& d, int MT)
 {
     const int KT = mx_kt(d.form), SB = mx_src_bytes(d.form);
     MxParams P{};
@@ -755,35 +773,36 @@ MxParams make_mx_params(const MxLaunchDesc& d)
     return P;
 }
 
-template <int FORM>
+template <int FORM, int MT>
 hipError_t launch_form(const MxLaunchDesc& d, bool pack)
 {
-    const MxParams P = make_mx_params(d);
+    const MxParams P = make_mx_params(d, MT);
     const bool akc = d.a_kmajor, bkc = d.b_kmajor;
     const dim3 block(NTHR);
     if (!pack) {
         const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN));
-        if (!akc && !bkc) gemm_mx_kernel<FORM, false, false><<<grid, block, 0, d.stream>>>(P);
-        else if (!akc && bkc) gemm_mx_kernel<FORM, false, true><<<grid, block, 0, d.stream>>>(P);
-        else if (akc && !bkc) gemm_mx_kernel<FORM, true, false><<<grid, block, 0, d.stream>>>(P);
-        else gemm_mx_kernel<FORM, true, true><<<grid, block, 0, d.stream>>>(P);
+        if (!akc && !bkc) gemm_mx_kernel<FORM, MT, false, false><<<grid, block, 0, d.stream>>>(P);
+        else if (!akc && bkc) gemm_mx_kernel<FORM, MT, false, true><<<grid, block, 0, d.stream>>>(P);
+        else if (akc && !bkc) gemm_mx_kernel<FORM, MT, true, false><<<grid, block, 0, d.stream>>>(P);
+        else gemm_mx_kernel<FORM, MT, true, true><<<grid, block, 0, d.stream>>>(P);
     } else {
         const dim3 grid((unsigned)(((int64_t)P.tilesM + P.tilesN) * P.nK));
-        if (!akc && !bkc) pack_mx_kernel<FORM, false, false><<<grid, block, 0, d.stream>>>(P);
-        else if (!akc && bkc) pack_mx_kernel<FORM, false, true><<<grid, block, 0, d.stream>>>(P);
-        else if (akc && !bkc) pack_mx_kernel<FORM, true, false><<<grid, block, 0, d.stream>>>(P);
-        else pack_mx_kernel<FORM, true, true><<<grid, block, 0, d.stream>>>(P);
+        if (!akc && !bkc) pack_mx_kernel<FORM, MT, false, false><<<grid, block, 0, d.stream>>>(P);
+        else if (!akc && bkc) pack_mx_kernel<FORM, MT, false, true><<<grid, block, 0, d.stream>>>(P);
+        else if (akc && !bkc) pack_mx_kernel<FORM, MT, true, false><<<grid, block, 0, d.stream>>>(P);
+        else pack_mx_kernel<FORM, MT, true, true><<<grid, block, 0, d.stream>>>(P);
     }
     return hipGetLastError();
 }
 
 hipError_t dispatch_mx(const MxLaunchDesc& d, bool pack)
 {
+    const bool big = d.mt == 256;
     switch (d.form) {
-    case kMxBF16: return launch_form<kMxBF16>(d, pack);
-    case kMxFP8: return launch_form<kMxFP8>(d, pack);
-    case kMxX3: return launch_form<kMxX3>(d, pack);
-    case kMxX3Fast: return launch_form<kMxX3Fast>(d, pack);
+    case kMxBF16: return big ? launch_form<kMxBF16, 256>(d, pack) : launch_form<kMxBF16, 128>(d, pack);
+    case kMxFP8: return big ? launch_form<kMxFP8, 256>(d, pack) : launch_form<kMxFP8, 128>(d, pack);
+    case kMxX3: return launch_form<kMxX3, 128>(d, pack);
+    case kMxX3Fast: return launch_form<kMxX3Fast, 128>(d, pack);
     default: return hipErrorInvalidValue;
     }
 }

@@ -29,6 +29,7 @@ FIP_ATTR_PACK_POLICY, FIP_ATTR_TILE, FIP_ATTR_NO_PUBLISH, FIP_ATTR_STATS, FIP_AT
 FIP_ATTR_ORDER = 7
 FIP_ATTR_VB_SPLIT = 8
 FIP_ATTR_VB_GRID = 9
+FIP_ATTR_MX_TILE = 10
 FIP_VB_GRAPH = 1
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8

@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 FORMS = [synth.FORM_BF16, synth.FORM_E4M3, synth.FORM_BF16X3, synth.FORM_BF16X3_FAST]
 FORM_IDS = ["bf16", "e4m3", "bf16x3", "bf16x3f"]
 COL, ROW = synth.COL, synth.ROW
+BIG = [(synth.FORM_BF16, 256), (synth.FORM_E4M3, 256)]   # forms with 256 x 256 tiles
 
 
 @pytest.fixture(scope="module")
@@ -36,11 +37,12 @@ def dev(buf):
     return to_dev(buf)
 
 
-def run_mx(F, c, policy=0, order=0, no_publish=0, h=None, stats=0):
+def run_mx(F, c, policy=0, order=0, no_publish=0, h=None, stats=0, tile=-1):
     import torch
     own = h is None
     if own:
         h = F.Handle(policy=policy)
+    h.set_attr(F.FIP_ATTR_MX_TILE, tile)
     h.set_attr(F.FIP_ATTR_ORDER, order)
     h.set_attr(F.FIP_ATTR_NO_PUBLISH, no_publish)
     h.set_attr(F.FIP_ATTR_STATS, stats)
@@ -95,7 +97,8 @@ def test_mx_modes_bitwise(F, form, layout, tA, tB):
     arithmetic in the same k order: C must agree bit for bit.  The launch has more tiles than
     fit on the GPU at once, so later tiles do read packed panels."""
     say("modes", form, layout, tA, tB)
-    m = n = 4096
+    # several rounds of tiles: 256 x 256 tiles (bfloat16, E4M3) need 8192^2
+    m = n = 8192 if form in (synth.FORM_BF16, synth.FORM_E4M3) else 4096
     k = 160 if form != synth.FORM_E4M3 else 300
     c = synth.make_mx_case(form, layout, m, n, k, tA, tB, alpha=1.0, beta=0.5, seed=77 + form)
     ref, _ = run_mx(F, c, F.FIP_PACK_NONE)
@@ -142,15 +145,33 @@ def mx_reference_sampled(c, rows, cols):
     return Cref.reshape(nn, mm).T[ri, ci], D.reshape(nn, mm).T[ri, ci]
 
 
-@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+
+
+@pytest.mark.parametrize("form,tile", BIG, ids=["bf16-256", "e4m3-256"])
+@pytest.mark.parametrize("layout,tA,tB", [(COL, "N", "N"), (COL, "T", "N"), (ROW, "N", "T"),
+                                          (ROW, "T", "T")])
+@pytest.mark.parametrize("c_bf16", [False, True], ids=["c32", "c16"])
+def test_mx_big_tile_matches_oracle(F, form, tile, layout, tA, tB, c_bf16):
+    """256 x 256 tiles (128 x 128 per wave): several tiles, ragged m, n and k."""
+    say("big tile", form, layout, tA, tB, c_bf16)
+    c = synth.make_mx_case(form, layout, 600, 520, 333, tA, tB, ld_pad=4, alpha=1.5, beta=0.5,
+                           seed=form * 13 + layout * 5 + (tA == "T") * 3 + (tB == "T") + 1000,
+                           c_bf16=c_bf16)
+    out, h = run_mx(F, c, F.FIP_PACK_ALL, tile=tile)
+    assert h.last_plan().MT == 256
+    check_mx(c, out)
+
+
+@pytest.mark.parametrize("form,tile", [(f, 128) for f in FORMS] + BIG,
+                         ids=[i + "-128" for i in FORM_IDS] + ["bf16-256", "e4m3-256"])
 @pytest.mark.parametrize("layout,tA,tB", [(COL, "N", "N"), (COL, "T", "T"), (ROW, "N", "T"),
                                           (ROW, "T", "N")])
-def test_mx_packed_buffers_bit_exact(F, form, layout, tA, tB):
+def test_mx_packed_buffers_bit_exact(F, form, tile, layout, tA, tB):
     """Every claimed and published panel equals the oracle's reference pack byte for byte
     (K-major planes; the split forms hold the bfloat16 terms)."""
-    say("mx pack bits", form, layout, tA, tB)
-    c = synth.make_mx_case(form, layout, 300, 200, 170, tA, tB, ld_pad=4, seed=19 + form)
-    out, h = run_mx(F, c, F.FIP_PACK_ALL)
+    say("mx pack bits", form, tile, layout, tA, tB)
+    c = synth.make_mx_case(form, layout, 600, 400, 170, tA, tB, ld_pad=4, seed=19 + form)
+    out, h = run_mx(F, c, F.FIP_PACK_ALL, tile=tile)
     check_mx(c, out)
     p = h.last_plan()
     ws = h.workspace
@@ -179,12 +200,14 @@ def test_mx_packed_buffers_bit_exact(F, form, layout, tA, tB):
     assert kt == oracle.MX_KT[form]
 
 
-@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
-def test_mx_standalone_pack_bit_exact(F, form):
+@pytest.mark.parametrize("form,tile", [(f, 128) for f in FORMS] + BIG,
+                         ids=[i + "-128" for i in FORM_IDS] + ["bf16-256", "e4m3-256"])
+def test_mx_standalone_pack_bit_exact(F, form, tile):
     import torch
-    say("standalone mx pack", form)
-    c = synth.make_mx_case(form, ROW, 260, 130, 150, "T", "N", ld_pad=4, seed=23 + form)
+    say("standalone mx pack", form, tile)
+    c = synth.make_mx_case(form, ROW, 560, 300, 150, "T", "N", ld_pad=4, seed=23 + form)
     h = F.Handle(policy=F.FIP_PACK_CONSUME_ONLY)
+    h.set_attr(F.FIP_ATTR_MX_TILE, tile)
     A, B = dev(c.A), dev(c.B)
     h.pack(c.layout, c.m, c.n, c.k, A, c.lda, c.transA, B, c.ldb, c.transB, dtype=form)
     torch.cuda.synchronize()
@@ -193,9 +216,10 @@ def test_mx_standalone_pack_bit_exact(F, form):
                                              c.m, 0),
                                             (p.b_pack_offset, p.b_copy_bytes, c.B, c.ldb, "N",
                                              c.n, 1)]:
-        exp = oracle.pack_mx(form, X, is_b, c.layout, t, mn, c.k, ld)
+        exp = oracle.pack_mx(form, X, is_b, c.layout, t, mn, c.k, ld, p.MT)
         got = h.workspace[off: off + nbytes].cpu().numpy()
         assert np.array_equal(got, exp)
+    assert p.MT == tile
 
 
 @pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
