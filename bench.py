@@ -128,12 +128,12 @@ class Gemm:
         self.handles.clear()
 
 
-def time_interleaved(g, policies, rounds=11, warmup=3):
+def time_interleaved(g, policies, rounds=11, warmup=3, batch_s=0.01):
     """Median per-call time (ms) of each policy.  Every round times one batch of each policy,
     alternating the order between rounds, so that clock ramps and drift hit all of them alike."""
     import statistics
     est = g.flops() / (40e12 if g.case.A.dtype.itemsize == 8 else 80e12) + 5e-6
-    reps = max(1, min(200, int(0.01 / est)))
+    reps = max(1, min(200, int(batch_s / est)))
     for pol in policies:
         g.time(pol, 1, warmup)
     times = {pol: [] for pol in policies}
@@ -284,6 +284,88 @@ def batched_section(F, torch, count=10000):
     return res
 
 
+VARIANTS_ALL = [(layout, tA, tB, pad) for layout in (0, 1) for tA in "NT" for tB in "NT"
+                for pad in (0, 7)]
+VARIANTS_FEW = [(0, "N", "N", 0), (0, "T", "N", 7), (1, "N", "T", 0), (1, "T", "T", 7)]
+
+
+def _policy_names(F):
+    return {F.FIP_PACK_AUTO: "fused", F.FIP_PACK_CONSUME_ONLY: "pack_then_compute",
+            F.FIP_PACK_NONE: "no_pack"}
+
+
+def _time_row(F, torch, g, row, rounds, batch_s):
+    names = _policy_names(F)
+    med, calls = time_interleaved(g, list(names), rounds=rounds, batch_s=batch_s)
+    row["calls_per_variant"] = calls
+    for pol, name in names.items():
+        t = med[pol]
+        row[name + "_us"] = round(t * 1e3, 2)
+        row[name + "_gflops"] = round(g.flops() / (t * 1e-3) / 1e9, 2)
+    row["fused_speedup_vs_pack_then_compute"] = round(row["pack_then_compute_us"] / row["fused_us"], 3)
+    return row
+
+
+def sweep_section(F, torch, sizes, dtypes):
+    """Square m = n = k sweep, fused vs pack-then-compute vs unpacked: every combination of
+    layout, transposes and ld in {rows, rows + 7} up to 1024, four of them above."""
+    from paper_2302_08417_amd import synth
+    out = []
+    for sdt in dtypes:
+        for s in sizes:
+            for layout, tA, tB, pad in (VARIANTS_ALL if s <= 1024 else VARIANTS_FEW):
+                g = Gemm(F, torch, s, sdt, seed=synth.BASE_SEED + 17 * s, layout=layout, tA=tA,
+                         tB=tB, ld_pad=pad)
+                row = {"dtype": sdt, "m": s, "n": s, "k": s, "layout": "col" if layout == 0 else "row",
+                       "trans": tA + tB, "ld_pad": pad}
+                _time_row(F, torch, g, row, rounds=5, batch_s=0.003 if s <= 1024 else 0.01)
+                row["fused_pct_peak"] = round(100 * row["fused_gflops"] / (PEAK_TFLOPS[sdt] * 1e3), 2)
+                log(f"[sweep] {row}")
+                out.append(row)
+                g.release()
+                del g
+            torch.cuda.empty_cache()
+    return out
+
+
+def skinny_section(F, torch, dtypes):
+    """Skinny shapes (HBM-bound): every layout / transpose / ld variant; algorithmic GB/s =
+    elem (mk + kn + 2mn) / time."""
+    from paper_2302_08417_amd import synth
+    out = []
+    for sdt in dtypes:
+        es = 8 if sdt == "f64" else 4
+        for (m, n, k) in ((4096, 4096, 32), (32, 4096, 4096), (4096, 32, 4096)):
+            for layout, tA, tB, pad in VARIANTS_ALL:
+                g = Gemm(F, torch, n, sdt, seed=synth.BASE_SEED + m + 3 * n + 7 * k, layout=layout,
+                         tA=tA, tB=tB, m=m, k=k, ld_pad=pad)
+                row = {"dtype": sdt, "m": m, "n": n, "k": k, "layout": "col" if layout == 0 else "row",
+                       "trans": tA + tB, "ld_pad": pad}
+                _time_row(F, torch, g, row, rounds=5, batch_s=0.003)
+                nbytes = es * (m * k + k * n + 2 * m * n)
+                row["fused_algorithmic_gbs"] = round(nbytes / (row["fused_us"] * 1e-6) / 1e9, 1)
+                row["fused_pct_hbm_peak"] = round(100 * row["fused_algorithmic_gbs"] / 8000.0, 2)
+                log(f"[skinny] {row}")
+                out.append(row)
+                g.release()
+                del g
+        torch.cuda.empty_cache()
+    return out
+
+
+def plain_dgemm_section(F, torch):
+    """C := A B + C, m = n = k = 256, column-major NN, alpha = beta = 1 (FP64)."""
+    from paper_2302_08417_amd import synth
+    g = Gemm(F, torch, 256, "f64", seed=synth.BASE_SEED + 1)
+    g.case.alpha, g.case.beta = 1.0, 1.0
+    row = {"dtype": "f64", "m": 256, "n": 256, "k": 256, "alpha": 1.0, "beta": 1.0}
+    _time_row(F, torch, g, row, rounds=7, batch_s=0.003)
+    row["fused_pct_peak"] = round(100 * row["fused_gflops"] / (PEAK_TFLOPS["f64"] * 1e3), 3)
+    log(f"[plain] {row}")
+    g.release()
+    return row
+
+
 def cpu_baseline(n, target_s=12.0):
     """The oracle, as it stands, on a column sample of the headline workload."""
     import numpy as np
@@ -402,29 +484,17 @@ def main():
     }
 
     if not args.no_sweep:
-        sweep = []
+        result["plain_dgemm_256"] = plain_dgemm_section(F, torch)
         sizes = [int(x) for x in args.sweep_sizes.split(",")] if args.sweep_sizes else SWEEP_SIZES
-        for sdt in args.sweep_dtypes.split(","):
-            for s in sizes:
-                gs = Gemm(F, torch, s, sdt, seed=synth.BASE_SEED + 17 * s)
-                row = {"dtype": sdt, "m": s, "n": s, "k": s}
-                names = {F.FIP_PACK_AUTO: "fused", F.FIP_PACK_CONSUME_ONLY: "pack_then_compute",
-                         F.FIP_PACK_NONE: "no_pack"}
-                med, calls = time_interleaved(gs, list(names))
-                row["calls_per_variant"] = calls
-                for pol, name in names.items():
-                    t = med[pol]
-                    row[name + "_us"] = round(t * 1e3, 2)
-                    row[name + "_gflops"] = round(gs.flops() / (t * 1e-3) / 1e9, 2)
-                row["fused_pct_peak"] = round(100 * row["fused_gflops"] / (PEAK_TFLOPS[sdt] * 1e3), 2)
-                row["fused_speedup_vs_pack_then_compute"] = round(
-                    row["pack_then_compute_us"] / row["fused_us"], 3)
-                log(f"[sweep] {row}")
-                sweep.append(row)
-                gs.release()
-                del gs
-                torch.cuda.empty_cache()
-        result["sweep"] = sweep
+        result["sweep"] = sweep_section(F, torch, sizes, args.sweep_dtypes.split(","))
+        result["skinny"] = skinny_section(F, torch, args.sweep_dtypes.split(","))
+        rows = result["sweep"] + result["skinny"]
+        sp = [r["fused_speedup_vs_pack_then_compute"] for r in rows]
+        result["sweep_summary"] = {
+            "rows": len(rows),
+            "rows_fused_faster_than_pack_then_compute": sum(x > 1.0 for x in sp),
+            "min_fused_speedup": min(sp), "median_fused_speedup": sorted(sp)[len(sp) // 2]}
+        log(f"[bench] sweep summary {result['sweep_summary']}")
 
     if not args.no_mx:
         result["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
