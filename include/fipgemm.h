@@ -92,9 +92,10 @@ enum {
     /* Read only: workgroups (one wave each) a batched launch keeps resident
        on the device; the batch's tiles are dealt round-robin over them. */
     FIP_ATTR_VB_GRID = 9,
-    /* Mixed-precision calls: C tile extent.  -1 (default) or 128: 128 x 128;
-       256: 256 x 256 (128 x 128 per wave) for bfloat16 / E4M3 (the split
-       forms always use 128). */
+    /* Mixed-precision calls: C tile extent.  128: 128 x 128; 256: 256 x 256
+       (128 x 128 per wave), bfloat16 only (other forms always use 128);
+       -1 (default): 256 for bfloat16 when the call has at least 4096 tiles of
+       256 x 256, else 128. */
     FIP_ATTR_MX_TILE = 10,
     /* Read only: the 64-bit epoch stamp of the most recent fused call
        (claims and publish flags of that call hold this value; stamps are
@@ -130,7 +131,8 @@ enum {
  * starts at workspace + a_pack_offset + c * a_copy_bytes.  The standalone
  * pack (fip_pack) and CONSUME_ONLY use copy 0.
  * Mixed-precision forms (dtype FIP_BF16 .. FIP_BF16X3_FAST): MT = NT = 128
- * or 256 (FIP_ATTR_MX_TILE), KT = 64 (bfloat16), 128 (E4M3) or 32 (split forms); every block is K-major
+ * (256 for bfloat16, see FIP_ATTR_MX_TILE), KT = 64 (bfloat16), 128 (E4M3) or
+ * 32 (split forms); every block is K-major
  * whatever the storage (a_kmajor = b_kmajor = 1), and holds PLANES planes of
  * MT*KT packed elements one after the other (PLANES = 3 for FIP_BF16X3, 2 for
  * FIP_BF16X3_FAST, else 1): plane t holds term t of the split (bfloat16 bits),

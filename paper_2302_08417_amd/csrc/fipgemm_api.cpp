@@ -191,12 +191,15 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     int cls, MT, KT;
     int64_t resident;
     if (form >= 0) {
-        // 128 x 128 tiles (256 x 256 for bfloat16 / E4M3 on request); a
-        // packed element is PLANES values of the packed type
+        // 128 x 128 tiles, or 256 x 256 (bfloat16 only); a packed element is
+        // PLANES values of the packed type.  Default: 256 once the launch has
+        // at least 16 rounds of 256-tiles (4096 tiles): measured ahead of 128
+        // at m = n = k = 16384, behind it at 8192, where the first round's
+        // unpacked reads weigh more.
         cls = 0;
-        // 256 x 256 runs one wave per SIMD and measured slower than 128 x 128
-        // at every size tried (1024 .. 16384), so it is used only on request
-        const bool big = h->mx_tile == 256 && fip::mx_has_big(form);
+        const int64_t big_tiles = cdiv(pl->ks.M, fip::kMxTileBig) * cdiv(pl->ks.N, fip::kMxTileBig);
+        const bool big = fip::mx_has_big(form) &&
+                         (h->mx_tile == 256 || (h->mx_tile == -1 && big_tiles >= 16 * 256));
         MT = big ? fip::kMxTileBig : fip::kMxTile;
         KT = fip::mx_kt(form);
         pl->elem = fip::mx_planes(form) * fip::mx_pack_bytes(form);

@@ -15,14 +15,17 @@
 //             again.  Six bfloat16 MFMA products per block (terms i + j <= 2),
 //             the small ones in their own accumulator, added to x0*y0 last.
 //   BF16X3F   the same with two terms and three products.
-// Accumulation is binary32 in every form (MFMA 16x16x32 bf16, 16x16x128 fp8).
+// Accumulation is binary32 in every form (MFMA 16x16x32 bf16, 16x16x128 fp8;
+// 32x32x16 bf16 for the 256 tile).
 //
 // Structure (shared with the FP64/FP32 kernel): one workgroup per MT x MT C
 // tile, 2 x 2 waves of MT/2 x MT/2, k-steps of KT, two LDS buffers.  MT = 128
-// for every form; bfloat16 and E4M3 also have MT = 256 on request (128 x 128
-// per wave, accumulators in the AGPRs), which doubles a wave's MFMA work per
-// byte read from LDS but leaves one wave per SIMD to hide LDS latency; it
-// measured slower, so 128 is the default.  Fused
+// for every form (two workgroups per CU).  bfloat16 also has MT = 256 (128 x
+// 128 per wave, accumulators in the AGPRs, one workgroup per CU): half the LDS
+// and L2 bytes per flop of the 128 tile, with one wave per SIMD, so its k-loop
+// is software-pipelined by hand (fragment reads one k-block ahead of the
+// MFMAs, one barrier per k-step placed before the last block, global loads
+// two k-steps ahead).  Fused
 // packing per operand panel: first toucher per XCD claims and packs, publishes
 // a completion flag once its stores are acknowledged; other workgroups read
 // the packed copy from the moment they see the flag, the unpacked operand
@@ -35,6 +38,8 @@
 // reads a contiguous k-run), so a packed chunk goes to LDS with plain vector
 // copies whatever the caller's storage order was: the first pass does the
 // transposition of MN-major operands once, later passes never.
+#include <type_traits>
+
 #include "fip_internal.h"
 #include "fip_device.h"
 
@@ -42,6 +47,7 @@ namespace fip {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
@@ -93,6 +99,15 @@ template <int FORM, int MT_> struct Geo {
     static_assert(KGROUPS * (MT / NR) == NTHR, "micro-blocks must cover the chunk");
     static_assert(WPR == 2 || WPR == 4, "8- or 16-byte rows");
 };
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
 
 // bfloat16 of a binary32, round to nearest even (the hardware conversion).
 __device__ __forceinline__ uint32_t bf16_bits(float v)
@@ -307,9 +322,34 @@ struct Mma {
     typedef Geo<FORM, MT> G;
     static constexpr int NACC = (FORM == kMxX3 || FORM == kMxX3Fast) ? 2 : 1;
     static constexpr int FB = G::FB;
+    typedef f4 Acc[NACC][FB][FB];
 
-    __device__ __forceinline__ static void step(const char* la, const char* lb, int lane,
-                                                f4 (&acc)[NACC][FB][FB])
+    __device__ __forceinline__ static void zero(Acc& acc)
+    {
+#pragma unroll
+        for (int t = 0; t < NACC; ++t)
+#pragma unroll
+            for (int a = 0; a < FB; ++a)
+#pragma unroll
+                for (int b = 0; b < FB; ++b) acc[t][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    // Visit the result as runs of four consecutive rows of one column:
+    // fn(v, row offset, column offset) within the wave's sub-tile.
+    template <class Fn>
+    __device__ __forceinline__ static void pieces(const Acc& acc, int lane, Fn&& fn)
+    {
+#pragma unroll
+        for (int a = 0; a < FB; ++a)
+#pragma unroll
+            for (int b = 0; b < FB; ++b) {
+                f4 v = acc[0][a][b];
+                if constexpr (NACC == 2) v = acc[1][a][b] + v;  // small terms first, then x0*y0
+                fn(v, a * 16 + 4 * (lane >> 4), b * 16 + (lane & 15));
+            }
+    }
+
+    __device__ __forceinline__ static void step(const char* la, const char* lb, int lane, Acc& acc)
     {
         const int row = lane & 15, run = lane >> 4;
         // B fragments of the whole wave row first, then one A fragment at a
@@ -381,6 +421,70 @@ struct Mma {
     }
 };
 
+// MT = 256 (bfloat16): 32 x 32 MFMA blocks (v_mfma 32x32x16 bf16), 4 x 4
+// blocks of 16 accumulators per wave.  The 32 x 32 form keeps a wave's 256
+// accumulators in the AGPRs without the register shuffling the compiler
+// inserts around 64 separate 16 x 16 accumulators.  Fragment: lane l supplies
+// row l%32 and 8 consecutive k (16 bytes) at run l/32; output item r of lane l
+// is C[8*(r/4) + 4*(l/32) + r%4][l%32].
+template <int FORM>
+struct Mma<FORM, 256> {
+    static_assert(FORM == kMxBF16, "256 x 256 tiles: bfloat16 only");
+    typedef Geo<FORM, 256> G;
+    static constexpr int NACC = 1;
+    static constexpr int FB = G::WT / 32;   // 4
+    typedef f16v Acc[FB][FB];
+
+    __device__ __forceinline__ static void zero(Acc& acc)
+    {
+#pragma unroll
+        for (int a = 0; a < FB; ++a)
+#pragma unroll
+            for (int b = 0; b < FB; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+    }
+
+    template <class Fn>
+    __device__ __forceinline__ static void pieces(const Acc& acc, int lane, Fn&& fn)
+    {
+        static_for<0, FB * FB * 4>([&](auto k) {
+            constexpr int a = decltype(k)::value / (4 * FB), b = decltype(k)::value / 4 % FB,
+                          g = decltype(k)::value % 4;
+            fn(f4{acc[a][b][4 * g], acc[a][b][4 * g + 1], acc[a][b][4 * g + 2], acc[a][b][4 * g + 3]},
+               a * 32 + 8 * g + 4 * (lane >> 5), b * 32 + (lane & 31));
+        });
+    }
+
+    // k-blocks of one MFMA: 16 k-values; NB per k-step.
+    static constexpr int KB = 16;
+    static constexpr int NB = G::KT / KB;
+    struct Frags {
+        bf8v a[FB], b[FB];
+    };
+
+    // Fragments of k-block s of the wave's rows (la) and columns (lb).
+    __device__ __forceinline__ static void read(const char* la, const char* lb, int lane, int s,
+                                                Frags& f)
+    {
+        const int off = (lane & 31) * G::PITCH + (s * KB + (lane >> 5) * 8) * 2;
+#pragma unroll
+        for (int b = 0; b < FB; ++b) f.b[b] = *reinterpret_cast<const bf8v*>(lb + b * 32 * G::PITCH + off);
+#pragma unroll
+        for (int a = 0; a < FB; ++a) f.a[a] = *reinterpret_cast<const bf8v*>(la + a * 32 * G::PITCH + off);
+    }
+
+    __device__ __forceinline__ static void mma(const Frags& f, Acc& acc)
+    {
+#pragma unroll
+        for (int a = 0; a < FB; ++a)
+#pragma unroll
+            for (int b = 0; b < FB; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[a], f.b[b], acc[a][b], 0, 0, 0);
+    }
+
+};
+
 template <int FORM, int MT, bool AKC, bool BKC>
 __global__ void __launch_bounds__(NTHR, (MT == 128 && (FORM == kMxBF16 || FORM == kMxFP8)) ? 2 : 1)
 gemm_mx_kernel(const MxParams P)
@@ -389,8 +493,7 @@ gemm_mx_kernel(const MxParams P)
     typedef Stage<FORM, AKC, MT> StA;
     typedef Stage<FORM, BKC, MT> StB;
     typedef typename Form<FORM>::S S;
-    constexpr int KT = G::KT, SB = G::SB, WT = G::WT, FB = G::FB;
-    constexpr int NACC = Mma<FORM, MT>::NACC;
+    constexpr int KT = G::KT, SB = G::SB, WT = G::WT;
 
     __shared__ __attribute__((aligned(16))) char sA[2][G::LDS_OPERAND];
     __shared__ __attribute__((aligned(16))) char sB[2][G::LDS_OPERAND];
@@ -478,44 +581,93 @@ gemm_mx_kernel(const MxParams P)
         }
     };
 
-    f4 acc[NACC][FB][FB];
-#pragma unroll
-    for (int t = 0; t < NACC; ++t)
-#pragma unroll
-        for (int a = 0; a < FB; ++a)
-#pragma unroll
-            for (int b = 0; b < FB; ++b) acc[t][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    typedef Mma<FORM, MT> MM;
+    typename MM::Acc acc;
+    MM::zero(acc);
 
-    load_chunks(0);
-    ra.store_lds(sA[0], tid);
-    rb.store_lds(sB[0], tid);
-    if (prodA) ra.store_pack(apanel, tid);
-    if (prodB) rb.store_pack(bpanel, tid);
-    __syncthreads();
-
-    for (int q = 0; q < nK; ++q) {
-        const int cur = q & 1;
-        const bool more = q + 1 < nK;
-        const bool poll = ((wantA && !apk) || (wantB && !bpk)) && q % REPOLL == REPOLL - 1;
-        uint64_t fa = 0, fb = 0;
-        if (poll) {
-            if (wantA && !apk) fa = load_flag(adone);
-            if (wantB && !bpk) fb = load_flag(bdone);
+    // Flag polls while an operand still comes unpacked: the loads are issued
+    // in one place and their values used later, off the critical path.
+    bool polling = false;
+    uint64_t pfa = 0, pfb = 0;
+    auto poll_issue = [&](int q) {
+        polling = ((wantA && !apk) || (wantB && !bpk)) && q % REPOLL == REPOLL - 1;
+        if (polling) {
+            pfa = wantA && !apk ? load_flag(adone) : 0;
+            pfb = wantB && !bpk ? load_flag(bdone) : 0;
         }
-        if (more) load_chunks(q + 1);
-        Mma<FORM, MT>::step(sA[cur] + wm * WT * G::PITCH, sB[cur] + wn * WT * G::PITCH, lane, acc);
-        if (more) {
-            ra.store_lds(sA[cur ^ 1], tid);
-            rb.store_lds(sB[cur ^ 1], tid);
-            if (prodA) ra.store_pack(apanel + (int64_t)(q + 1) * G::PACK_CHUNK, tid);
-            if (prodB) rb.store_pack(bpanel + (int64_t)(q + 1) * G::PACK_CHUNK, tid);
-        }
-        if (poll) {
-            apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
-            bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+    };
+    auto poll_finish = [&]() {
+        if (polling) {
+            apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(pfa == epoch)) != 0);
+            bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(pfb == epoch)) != 0);
             if (P.do_stats && tid == 0) ++n_polls;
         }
+    };
+    auto put_chunks = [&](int buf, int c) {
+        ra.store_lds(sA[buf], tid);
+        rb.store_lds(sB[buf], tid);
+        if (prodA) ra.store_pack(apanel + (int64_t)c * G::PACK_CHUNK, tid);
+        if (prodB) rb.store_pack(bpanel + (int64_t)c * G::PACK_CHUNK, tid);
+    };
+
+    load_chunks(0);
+    put_chunks(0, 0);
+    if constexpr (MT == 256) {
+        // Software pipeline with one wave per SIMD: the fragments of k-block
+        // s + 1 are read while the MFMAs of block s issue; the next chunk goes
+        // from registers to the other LDS buffer after block NB - 2, and the
+        // one barrier per k-step sits before the last block, so the next
+        // k-step's first fragments arrive while that block's MFMAs run.
+        // Global loads run two k-steps ahead (one chunk in registers).
+        constexpr int NB = MM::NB;
+        static_assert(NB >= 2, "at least two k-blocks per k-step");
+        typename MM::Frags fr[2];
+        if (nK > 1) load_chunks(1);
         __syncthreads();
+        const int aoff = wm * WT * G::PITCH, boff = wn * WT * G::PITCH;
+        MM::read(sA[0] + aoff, sB[0] + boff, lane, 0, fr[0]);
+        // The last k-step is peeled off (MORE = false), so inside the loop
+        // the path through the barrier is straight-line code and the MFMAs of
+        // the last block do not wait for the next k-step's fragment reads.
+        // sched_barrier(0) keeps the compiler from moving MFMAs across the
+        // phase boundaries (it would otherwise hoist the last block's MFMAs
+        // above the barrier and leave the barrier wait uncovered).
+        auto kstep = [&](int q, auto more_c) {
+            constexpr bool more = decltype(more_c)::value;
+            const int cur = q & 1;
+#pragma unroll
+            for (int s = 0; s < NB; ++s) {
+                if (s + 1 < NB) MM::read(sA[cur] + aoff, sB[cur] + boff, lane, s + 1, fr[(s + 1) & 1]);
+                if (s == NB - 1 && more) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    __syncthreads();
+                    MM::read(sA[cur ^ 1] + aoff, sB[cur ^ 1] + boff, lane, 0, fr[0]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                MM::mma(fr[s & 1], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                if (s == NB - 2 && more) {
+                    put_chunks(cur ^ 1, q + 1);
+                    poll_issue(q);
+                    if (q + 2 < nK) load_chunks(q + 2);
+                }
+                if (s == NB - 1) poll_finish();
+            }
+        };
+        for (int q = 0; q + 1 < nK; ++q) kstep(q, std::true_type{});
+        kstep(nK - 1, std::false_type{});
+    } else {
+        __syncthreads();
+        for (int q = 0; q < nK; ++q) {
+            const int cur = q & 1;
+            const bool more = q + 1 < nK;
+            poll_issue(q);
+            if (more) load_chunks(q + 1);
+            MM::step(sA[cur] + wm * WT * G::PITCH, sB[cur] + wn * WT * G::PITCH, lane, acc);
+            if (more) put_chunks(cur ^ 1, q + 1);
+            poll_finish();
+            __syncthreads();
+        }
     }
 
     if (producer) {
@@ -533,68 +685,64 @@ gemm_mx_kernel(const MxParams P)
         atomicAdd(P.stats + 3, n_polls);
     }
 
-    // Epilogue: item r of lane l of block (a, b) is C[r0 + 4*(l/16) + r][c0 + l%16]:
-    // four consecutive rows of one column of the column-major C.  FP8 scales:
+    // Epilogue: the accumulators come as runs of four consecutive rows of one
+    // column of the column-major C (16 x 16 blocks: rows 4*(l/16) .. +3 of
+    // column l%16; 32 x 32 blocks: four such runs per block).  FP8 scales:
     // the stored codes are x*s, so the product is divided by s_row * s_col
     // (powers of two, applied one factor at a time: exact).
     const float alpha = P.alpha, beta = P.beta;
     const int64_t r0w = x0a + wm * WT, c0w = x0b + wn * WT;
     const bool c_in = x0a + MT <= P.M && x0b + MT <= P.N;
+    MM::pieces(acc, lane, [&](f4 v, int di, int dj) {
+        const int64_t i0 = r0w + di, j = c0w + dj;
+        float ib = 1.f;
+        if (FORM == kMxFP8 && P.b_scale != nullptr && j < P.N) ib = 1.f / P.b_scale[j];
+        if (P.c_bf16) {
+            uint16_t* cp = reinterpret_cast<uint16_t*>(P.C) + j * P.ldc;
 #pragma unroll
-    for (int a = 0; a < FB; ++a)
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + r;
+                if (c_in || (i < P.M && j < P.N)) {
+                    float t = v[r];
+                    if (FORM == kMxFP8 && P.a_scale != nullptr) t = t * (1.f / P.a_scale[i]);
+                    t = t * ib;
+                    const float c = beta != 0.f ? bf16_float(cp[i]) : 0.f;
+                    const float o = beta != 0.f ? axpby(alpha, t, beta, c) : alpha * t;
+                    cp[i] = (uint16_t)bf16_bits(o);
+                }
+            }
+        } else {
+            float* cp = reinterpret_cast<float*>(P.C) + j * P.ldc;
+            if (c_in) {
+                f4 c = f4{0.f, 0.f, 0.f, 0.f};
+                if (beta != 0.f) {
+                    const u4 cu = *reinterpret_cast<const u4a*>(cp + i0);
+                    c = f4{__uint_as_float(cu[0]), __uint_as_float(cu[1]),
+                           __uint_as_float(cu[2]), __uint_as_float(cu[3])};
+                }
+                u4 o;
 #pragma unroll
-        for (int b = 0; b < FB; ++b) {
-            const int64_t i0 = r0w + a * 16 + 4 * (lane >> 4), j = c0w + b * 16 + (lane & 15);
-            f4 v = acc[0][a][b];
-            if constexpr (NACC == 2) v = acc[1][a][b] + v;  // small terms first, then x0*y0
-            float ib = 1.f;
-            if (FORM == kMxFP8 && P.b_scale != nullptr && j < P.N) ib = 1.f / P.b_scale[j];
-            if (P.c_bf16) {
-                uint16_t* cp = reinterpret_cast<uint16_t*>(P.C) + j * P.ldc;
+                for (int r = 0; r < 4; ++r) {
+                    float t = v[r];
+                    if (FORM == kMxFP8 && P.a_scale != nullptr) t = t * (1.f / P.a_scale[i0 + r]);
+                    t = t * ib;
+                    o[r] = __float_as_uint(beta != 0.f ? axpby(alpha, t, beta, c[r]) : alpha * t);
+                }
+                *reinterpret_cast<u4a*>(cp + i0) = o;
+            } else {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t i = i0 + r;
-                    if (c_in || (i < P.M && j < P.N)) {
+                    if (i < P.M && j < P.N) {
                         float t = v[r];
                         if (FORM == kMxFP8 && P.a_scale != nullptr) t = t * (1.f / P.a_scale[i]);
                         t = t * ib;
-                        const float c = beta != 0.f ? bf16_float(cp[i]) : 0.f;
-                        const float o = beta != 0.f ? axpby(alpha, t, beta, c) : alpha * t;
-                        cp[i] = (uint16_t)bf16_bits(o);
-                    }
-                }
-            } else {
-                float* cp = reinterpret_cast<float*>(P.C) + j * P.ldc;
-                if (c_in) {
-                    f4 c = f4{0.f, 0.f, 0.f, 0.f};
-                    if (beta != 0.f) {
-                        const u4 cu = *reinterpret_cast<const u4a*>(cp + i0);
-                        c = f4{__uint_as_float(cu[0]), __uint_as_float(cu[1]),
-                               __uint_as_float(cu[2]), __uint_as_float(cu[3])};
-                    }
-                    u4 o;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        float t = v[r];
-                        if (FORM == kMxFP8 && P.a_scale != nullptr) t = t * (1.f / P.a_scale[i0 + r]);
-                        t = t * ib;
-                        o[r] = __float_as_uint(beta != 0.f ? axpby(alpha, t, beta, c[r]) : alpha * t);
-                    }
-                    *reinterpret_cast<u4a*>(cp + i0) = o;
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t i = i0 + r;
-                        if (i < P.M && j < P.N) {
-                            float t = v[r];
-                            if (FORM == kMxFP8 && P.a_scale != nullptr) t = t * (1.f / P.a_scale[i]);
-                            t = t * ib;
-                            cp[i] = beta != 0.f ? axpby(alpha, t, beta, cp[i]) : alpha * t;
-                        }
+                        cp[i] = beta != 0.f ? axpby(alpha, t, beta, cp[i]) : alpha * t;
                     }
                 }
             }
         }
+    });
 }
 
 // Standalone pack of both operands into copy 0 (pack-then-compute baseline):
@@ -800,7 +948,7 @@ hipError_t dispatch_mx(const MxLaunchDesc& d, bool pack)
     const bool big = d.mt == 256;
     switch (d.form) {
     case kMxBF16: return big ? launch_form<kMxBF16, 256>(d, pack) : launch_form<kMxBF16, 128>(d, pack);
-    case kMxFP8: return big ? launch_form<kMxFP8, 256>(d, pack) : launch_form<kMxFP8, 128>(d, pack);
+    case kMxFP8: return launch_form<kMxFP8, 128>(d, pack);
     case kMxX3: return launch_form<kMxX3, 128>(d, pack);
     case kMxX3Fast: return launch_form<kMxX3Fast, 128>(d, pack);
     default: return hipErrorInvalidValue;

@@ -271,6 +271,23 @@ def test_mx_plans(h, dtype, KT, planes, eb):
     assert rc == 0 and p.workspace_bytes == 0      # one round of tiles: nothing to reuse
 
 
+def test_mx_tile_choice(h):
+    """256 x 256 tiles: bfloat16 only; by default once a call has >= 4096 of them."""
+    def mt(dtype, n, tile=-1):
+        assert F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, tile) == 0
+        rc, p = F.fip_plan(h, dtype, 0, n, n, 512, "N", "N")
+        assert rc == 0
+        return p.MT
+    try:
+        assert mt(F.FIP_BF16, 16384) == 256 and mt(F.FIP_BF16, 8192) == 128
+        assert mt(F.FIP_BF16, 8192, 256) == 256 and mt(F.FIP_BF16, 16384, 128) == 128
+        for other in (F.FIP_E4M3, F.FIP_BF16X3, F.FIP_BF16X3_FAST):
+            assert mt(other, 16384) == 128 and mt(other, 16384, 256) == 128
+        assert F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, 64) == 3
+    finally:
+        F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, -1)
+
+
 def _vb_arrays():
     import numpy as np
     m = np.array([5, 0, 300, 64], np.int32)
