@@ -61,6 +61,64 @@ def load_traffic(name):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _pmc_rows(folder, counter):
+    """(kernel name, grid size, value) of every dispatch in a rocprofv3 --pmc csv output."""
+    import csv
+    path = os.path.join(folder, "run_counter_collection.csv")
+    with open(path, newline="") as f:
+        return [(r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"]))
+                for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+
+
+def write_traffic_summary(args, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
+    """HBM bytes per launch of the headline GEMM kernel from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the same counter reads for a device copy of known size."""
+    import statistics
+    n, dt = args.size, args.dtype
+    ctype = "double" if dt == "f64" else "float"
+
+    def gemm_mean(folder, counter):
+        rows = [r for r in _pmc_rows(folder, counter)
+                if f"::gemm_kernel<{ctype}," in r[0]]
+        if not rows:
+            raise SystemExit(f"no gemm_kernel<{ctype}, ...> dispatch in {folder}")
+        grid = max(r[1] for r in rows)          # the headline launch is the largest
+        vals = [r[2] for r in rows if r[1] == grid]
+        name = [r[0] for r in rows if r[1] == grid][0]
+        return statistics.mean(vals), len(vals), name
+
+    def copy_kib(folder, counter):
+        rows = [r for r in _pmc_rows(folder, counter) if "copyBuffer" in r[0]]
+        if not rows:
+            raise SystemExit(f"no copy kernel dispatch in {folder}")
+        return statistics.median(r[2] for r in rows)
+
+    probe = 1 << 30
+    fetch, nf, name = gemm_mean(fetch_dir, "FETCH_SIZE")
+    write, nw, _ = gemm_mean(write_dir, "WRITE_SIZE")
+    cf, cw = copy_kib(cfetch_dir, "FETCH_SIZE"), copy_kib(cwrite_dir, "WRITE_SIZE")
+    fs, ws = probe / (cf * 1024), probe / (cw * 1024)
+    rd, wr = fetch * 1024 * fs, write * 1024 * ws
+    esize = 8 if dt == "f64" else 4
+    rec = {
+        "kernel": name.replace("void fip::(anonymous namespace)::", "").split("(")[0],
+        "workload": f"fused-pack {'DGEMM' if dt == 'f64' else 'SGEMM'} m=n=k={n} column-major NN, "
+                    "AUTO policy",
+        "fetch_kib_per_dispatch": round(fetch, 1), "write_kib_per_dispatch": round(write, 1),
+        "copy_probe_bytes": probe, "copy_fetch_kib": round(cf, 1), "copy_write_kib": round(cw, 1),
+        "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+        "hbm_read_bytes_per_launch": int(rd), "hbm_write_bytes_per_launch": int(wr),
+        "hbm_bytes_per_launch": int(rd + wr),
+        "algorithmic_bytes_per_launch": esize * 4 * n * n,
+        "dispatches_averaged": min(nf, nw),
+        "kernel_source_sha256": kernel_source_hash(),
+    }
+    out = os.path.join(ROOT, "profiles", f"traffic_gemm_{dt}_{n}.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
 class Gemm:
     """One prepared GEMM (device operands + a handle per policy) timed with HIP events."""
 
@@ -413,7 +471,16 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), to "
                          "calibrate HBM byte counters against a kernel of known traffic")
+    ap.add_argument("--traffic-summary", nargs=4, default=None,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="no GPU work: read four rocprofv3 --pmc output folders (FETCH_SIZE and\n"
+                         "WRITE_SIZE of the headline run, then of the --copy-probe run) and write\n"
+                         "profiles/traffic_gemm_<dtype>_<size>.json for the roofline 'traffic'")
     args = ap.parse_args()
+
+    if args.traffic_summary:
+        write_traffic_summary(args, *args.traffic_summary)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
