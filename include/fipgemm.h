@@ -97,6 +97,16 @@ enum {
        -1 (default): 256 for bfloat16 when the call has at least 4096 tiles of
        256 x 256, else 128. */
     FIP_ATTR_MX_TILE = 10,
+    /* FP64/FP32 calls: split k into slices computed by separate workgroups;
+       each slice writes its partial product to the workspace and a second
+       kernel sums the slices in slice order and applies alpha and beta.
+       -1 (default): the planner splits when the tiles would occupy at most
+       half of the resident workgroups (slices of >= 16 k-steps, at most 32
+       slices); 1: never; 2..32: slices of ceil(ksteps / value) k-steps (fewer
+       slices if that leaves some empty).  The split depends on the shape and
+       this attribute only, so every pack policy gives bit-identical C for a
+       given split. */
+    FIP_ATTR_SPLIT_K = 11,
     /* Read only: the 64-bit epoch stamp of the most recent fused call
        (claims and publish flags of that call hold this value; stamps are
        unique within the process). */
@@ -150,11 +160,17 @@ typedef struct {
     int32_t a_kmajor, b_kmajor;/* packed block orientation: 1 = k-runs contiguous */
     int64_t a_pack_offset, a_copy_bytes;
     int64_t b_pack_offset, b_copy_bytes;
-    int64_t a_flag_offset, b_flag_offset;   /* uint64 [copies][tiles]: panel complete */
-    int64_t a_claim_offset, b_claim_offset; /* uint64 [copies][tiles] */
+    int64_t a_flag_offset, b_flag_offset;   /* uint64 [copies][tiles][split_k]: panel
+                                               (k-slice) complete */
+    int64_t a_claim_offset, b_claim_offset; /* uint64 [copies][tiles][split_k] */
     int64_t stats_offset;      /* 4 x uint64: chunks packed, chunks read packed,
                                   chunks of packed panels read unpacked, re-polls */
     int64_t workspace_bytes;   /* bytes this call needs */
+    int32_t split_k;           /* k-slices (1: k not split) */
+    int32_t slice_ksteps;      /* k-steps per slice (the last one may have fewer) */
+    int64_t partial_offset;    /* split_k > 1: the slices' partial products, elem
+                                  [split_k][kernel N][kernel M] (C's shape, column-major;
+                                  transposed for row-major calls); -1 otherwise */
 } fip_plan_t;
 
 int fip_create(fip_handle_t* handle);

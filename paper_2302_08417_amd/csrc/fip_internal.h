@@ -45,10 +45,13 @@ struct LaunchDesc {
     // workspace pieces (device pointers; null when unused)
     void* apack; int64_t apack_copy_elems;
     void* bpack; int64_t bpack_copy_elems;
-    uint64_t* aflag; uint64_t* bflag;   // panel complete: [copies][tiles]
-    uint64_t* aclaim; uint64_t* bclaim; // [copies][tiles]
+    uint64_t* aflag; uint64_t* bflag;   // panel complete: [copies][tiles][split]
+    uint64_t* aclaim; uint64_t* bclaim; // [copies][tiles][split]
     unsigned long long* stats_ptr;      // 4 counters
     uint64_t epoch;                     // unique per fused call in this process
+    // split k: `split` slices of `slice_ksteps` k-steps each (split = 1: none)
+    int split, slice_ksteps;
+    void* part;                         // slice partials [split][N][M] (column-major)
     hipStream_t stream;
 };
 

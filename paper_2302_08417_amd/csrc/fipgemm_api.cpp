@@ -18,6 +18,8 @@
 namespace {
 
 constexpr uint32_t kMagic = 0xF1F6E77u;
+constexpr int64_t kMinSliceKsteps = 16;  // split k: at least this many k-steps per slice
+constexpr int kMaxSplit = 32;            // split k: at most this many slices
 
 // Epoch stamps of fused calls.  Claims and publish flags in a workspace are
 // compared for equality with the current call's stamp, so a stamp must never
@@ -74,6 +76,7 @@ struct fip_handle_s {
     int has_last;
     int vb_split;     // FIP_ATTR_VB_SPLIT (-1: tuned or default)
     int mx_tile;      // FIP_ATTR_MX_TILE (-1: planner's choice, 128, 256)
+    int split_k;      // FIP_ATTR_SPLIT_K (-1: planner's choice, 1: off, 2..64: forced)
     VbState* vb;
 };
 
@@ -129,27 +132,31 @@ int choose_tile_class(int64_t M, int64_t N)
 // starts after an earlier pass over it could have finished: the reuse the
 // paper's Sec. 3.3 table is about, as it happens on this schedule.  Returns
 // the fraction of (XCD, panel) pairs that are reused, per operand.
-void later_round_reuse(int64_t tilesM, int64_t tilesN, int order, int64_t per_xcd, double* fracA,
-                       double* fracB)
+void later_round_reuse(int64_t tilesM, int64_t tilesN, int order, int64_t per_xcd, int split,
+                       double* fracA, double* fracB)
 {
     const int64_t T = tilesM * tilesN;
     *fracA = *fracB = 0.0;
-    if (T <= 0 || per_xcd <= 0 || T > ((int64_t)1 << 24)) return;
-    std::vector<int32_t> firstA(8 * tilesM, -1), firstB(8 * tilesN, -1);
-    std::vector<char> reA(8 * tilesM, 0), reB(8 * tilesN, 0);
-    for (int64_t w = 0; w < T; ++w) {
+    if (T <= 0 || per_xcd <= 0 || T * split > ((int64_t)1 << 24)) return;
+    // a claim unit is (XCD, panel, k-slice); workgroup w runs slice w / T of tile w % T
+    const int64_t nA = 8 * tilesM * split, nB = 8 * tilesN * split;
+    std::vector<int32_t> firstA(nA, -1), firstB(nB, -1);
+    std::vector<char> reA(nA, 0), reB(nB, 0);
+    for (int64_t w = 0; w < T * split; ++w) {
+        const int64_t sl = w / T, wt = w - sl * T;
         int tm, tn;
-        fip::tile_coords((int)w, (int)tilesM, (int)tilesN, fip::kGroupM, order, tm, tn);
+        fip::tile_coords((int)wt, (int)tilesM, (int)tilesN, fip::kGroupM, order, tm, tn);
         const int64_t x = w & 7;
         const int32_t r = (int32_t)((w >> 3) / per_xcd);
-        int32_t& fa = firstA[x * tilesM + tm];
-        if (fa < 0) fa = r; else if (fa != r) reA[x * tilesM + tm] = 1;
-        int32_t& fb = firstB[x * tilesN + tn];
-        if (fb < 0) fb = r; else if (fb != r) reB[x * tilesN + tn] = 1;
+        const int64_t ia = (x * tilesM + tm) * split + sl, ib = (x * tilesN + tn) * split + sl;
+        int32_t& fa = firstA[ia];
+        if (fa < 0) fa = r; else if (fa != r) reA[ia] = 1;
+        int32_t& fb = firstB[ib];
+        if (fb < 0) fb = r; else if (fb != r) reB[ib] = 1;
     }
     int64_t tA = 0, uA = 0, tB = 0, uB = 0;
-    for (int64_t i = 0; i < 8 * tilesM; ++i) { tA += firstA[i] >= 0; uA += reA[i]; }
-    for (int64_t i = 0; i < 8 * tilesN; ++i) { tB += firstB[i] >= 0; uB += reB[i]; }
+    for (int64_t i = 0; i < nA; ++i) { tA += firstA[i] >= 0; uA += reA[i]; }
+    for (int64_t i = 0; i < nB; ++i) { tB += firstB[i] >= 0; uB += reB[i]; }
     *fracA = tA ? (double)uA / tA : 0.0;
     *fracB = tB ? (double)uB / tB : 0.0;
 }
@@ -164,6 +171,8 @@ struct Plan {
     int64_t tilesKM, tilesKN, nK;
     int64_t off_stats, off_aflag, off_bflag, off_aclaim, off_bclaim, off_apack, off_bpack;
     int64_t apack_copy_elems, bpack_copy_elems;
+    int split, slice_ksteps;        // k split (FP64/FP32 kernel only; 1 = none)
+    int64_t off_part;
 };
 
 bool mn_major(bool is_b, int layout, char trans);
@@ -216,6 +225,32 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     pl->tilesKN = cdiv(pl->ks.N, NT);
     pl->nK = cdiv(k, KT);
 
+    // Split k (FP64/FP32): when the tiles leave most of the device idle (at
+    // most half the resident workgroups), k is cut into slices of at least
+    // kMinSliceKsteps k-steps, one workgroup per (tile, slice), up to the
+    // resident count; a second kernel sums the slices' partial products.
+    // The choice depends on the shape only (not on the pack policy), so every
+    // policy runs the same arithmetic.
+    pl->split = 1;
+    pl->slice_ksteps = (int)pl->nK;
+    if (form < 0 && pl->nK > 1) {
+        const int64_t tiles = pl->tilesKM * pl->tilesKN;
+        int64_t sp = 1;
+        if (h->split_k > 0) {
+            sp = h->split_k;
+        } else if (h->split_k == -1 && tiles > 0 && 2 * tiles <= resident) {
+            sp = resident / tiles;
+            if (sp > pl->nK / kMinSliceKsteps) sp = pl->nK / kMinSliceKsteps;
+            if (sp > kMaxSplit) sp = kMaxSplit;
+        }
+        if (sp > pl->nK) sp = pl->nK;
+        if (sp >= 2) {
+            const int64_t per = cdiv(pl->nK, sp);
+            pl->slice_ksteps = (int)per;
+            pl->split = (int)cdiv(pl->nK, per);   // no empty slice
+        }
+    }
+
     int policy = standalone_pack ? FIP_PACK_CONSUME_ONLY : h->policy;
     int copies = 0;
     if (policy == FIP_PACK_CONSUME_ONLY) {
@@ -238,11 +273,11 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
             // the launch order and packs an operand when most of its panels are
             // read again in a later round; with a single round nobody could
             // reuse a pack.
-            const bool later_passes = pl->tilesKM * pl->tilesKN > resident;
+            const bool later_passes = pl->tilesKM * pl->tilesKN * pl->split > resident;
             double fa = 0.0, fb = 0.0;
             if (later_passes)
                 later_round_reuse(pl->tilesKM, pl->tilesKN, h->order, resident / fip::kCopies,
-                                  &fa, &fb);
+                                  pl->split, &fa, &fb);
             pl->kpack_a = pl->tilesKN > 1 && fa >= 0.5;
             pl->kpack_b = pl->tilesKM > 1 && fb >= 0.5;
         }
@@ -250,16 +285,20 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     }
     if (k == 0 || m == 0 || n == 0) { pl->kpack_a = pl->kpack_b = 0; copies = 0; }
 
+    if (k == 0 || m == 0 || n == 0) { pl->split = 1; pl->slice_ksteps = (int)pl->nK; }
+    const bool fz = pl->mode == fip::kModeFused;
+    const int64_t sp = pl->split;
     int64_t off = 0;
     pl->off_stats = off; off = align256(off + 4 * 8);
-    pl->off_aflag = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * 8 : 0));
-    pl->off_bflag = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * 8 : 0));
-    pl->off_aclaim = off; off = align256(off + (pl->kpack_a && pl->mode == fip::kModeFused ? copies * pl->tilesKM * 8 : 0));
-    pl->off_bclaim = off; off = align256(off + (pl->kpack_b && pl->mode == fip::kModeFused ? copies * pl->tilesKN * 8 : 0));
+    pl->off_aflag = off; off = align256(off + (pl->kpack_a && fz ? copies * pl->tilesKM * sp * 8 : 0));
+    pl->off_bflag = off; off = align256(off + (pl->kpack_b && fz ? copies * pl->tilesKN * sp * 8 : 0));
+    pl->off_aclaim = off; off = align256(off + (pl->kpack_a && fz ? copies * pl->tilesKM * sp * 8 : 0));
+    pl->off_bclaim = off; off = align256(off + (pl->kpack_b && fz ? copies * pl->tilesKN * sp * 8 : 0));
     pl->apack_copy_elems = pl->kpack_a ? pl->tilesKM * pl->nK * KT * MT : 0;
     pl->bpack_copy_elems = pl->kpack_b ? pl->tilesKN * pl->nK * KT * NT : 0;
     pl->off_apack = off; off = align256(off + copies * pl->apack_copy_elems * pl->elem);
     pl->off_bpack = off; off = align256(off + copies * pl->bpack_copy_elems * pl->elem);
+    pl->off_part = off; off = align256(off + (sp > 1 ? sp * pl->ks.M * pl->ks.N * pl->elem : 0));
 
     fip_plan_t& p = pl->pub;
     p.dtype = dtype; p.layout = layout; p.m = m; p.n = n; p.k = k;
@@ -274,7 +313,10 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     p.a_kmajor = form >= 0 ? 1 : !mn_major(false, layout, tA);
     p.b_kmajor = form >= 0 ? 1 : !mn_major(true, layout, tB);
     const bool fl = pl->mode == fip::kModeFused;
-    p.workspace_bytes = (pl->kpack_a || pl->kpack_b) ? off : 0;
+    p.workspace_bytes = (pl->kpack_a || pl->kpack_b || pl->split > 1) ? off : 0;
+    p.split_k = pl->split;
+    p.slice_ksteps = pl->slice_ksteps;
+    p.partial_offset = pl->split > 1 ? pl->off_part : -1;
     // Report in the caller's terms: op(A) is the kernel's B-side when swapped.
     if (!pl->ks.swapped) {
         p.tiles_m = (int32_t)pl->tilesKM; p.tiles_n = (int32_t)pl->tilesKN;
@@ -374,6 +416,7 @@ void fill_workspace(const fip_handle_s* h, const Plan& pl, fip::LaunchDesc* d)
     d->bpack = ws + pl.off_bpack;
     d->apack_copy_elems = pl.apack_copy_elems;
     d->bpack_copy_elems = pl.bpack_copy_elems;
+    if (pl.split > 1) d->part = ws + pl.off_part;
 }
 
 int prepare_workspace(fip_handle_s* h, const Plan& pl)
@@ -418,6 +461,8 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         fill_operands(pl, layout, A, lda, tA, B, ldb, tB, &d);
         d.C = C; d.ldc = ldc;
         d.alpha = (double)alpha; d.beta = (double)beta;
+        d.split = pl.split;
+        d.slice_ksteps = pl.slice_ksteps;
         if (pl.pub.workspace_bytes > 0) {
             fill_workspace(h, pl, &d);
             if (pl.mode == fip::kModeFused) d.epoch = h->epoch = next_epoch();
@@ -732,6 +777,7 @@ int fip_create(fip_handle_t* handle)
     h->order = 0;
     h->vb_split = -1;
     h->mx_tile = -1;
+    h->split_k = -1;
     h->vb = nullptr;
     *handle = h;
     return 0;
@@ -785,6 +831,10 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
         if (value != -1 && value != 128 && value != 256) return 3;
         handle->mx_tile = (int)value;
         return 0;
+    case FIP_ATTR_SPLIT_K:
+        if (value != -1 && (value < 1 || value > kMaxSplit)) return 3;
+        handle->split_k = (int)value;
+        return 0;
     default:
         return 2;
     }
@@ -804,6 +854,7 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_VB_SPLIT: *value = handle->vb_split; return 0;
     case FIP_ATTR_VB_GRID: *value = fip::vbatched_grid(); return 0;
     case FIP_ATTR_MX_TILE: *value = handle->mx_tile; return 0;
+    case FIP_ATTR_SPLIT_K: *value = handle->split_k; return 0;
     default: return 2;
     }
 }

@@ -48,6 +48,8 @@ struct Params {
     int a_vec, b_vec, c_vec;
     int a_fast, b_fast;  // interior chunks may use the 32-bit-offset vector loader
     int order;       // tile order inside an XCD's run: 0 grouped, 1 column-distinct rounds
+    int split, slice_ksteps;  // k split into `split` slices of slice_ksteps k-steps
+    T* part;                  // split partials: [split][N][M] (kernel view, column-major)
 };
 
 template <typename T, int MT, int NT, int KT, int WM, int WN, bool AKC, bool BKC>
@@ -67,10 +69,20 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
+    // Split k: workgroup w computes k-slice w / tiles of tile w % tiles
+    // (chunks [slice * slice_ksteps, +slice_ksteps)); the slices of one tile
+    // are `tiles` workgroups apart, so they fall on the same XCD whenever the
+    // tile count is a multiple of 8.
+    const int S = P.split;
+    const int ntiles = P.tilesM * P.tilesN;
+    const int slice = S > 1 ? (int)(blockIdx.x / (unsigned)ntiles) : 0;
+    const int wt = (int)blockIdx.x - slice * ntiles;
     int tm, tn;
-    tile_coords(blockIdx.x, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
+    tile_coords(wt, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
     const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * NT;
     const int nK = P.nK;
+    const int q0 = slice * P.slice_ksteps;
+    const int q1 = q0 + P.slice_ksteps < nK ? q0 + P.slice_ksteps : nK;
     const int nKfull = (int)(P.K / KT);  // chunks with all KT k-values present
     const uint64_t epoch = P.epoch;
 
@@ -103,9 +115,12 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     T* bpanel = nullptr;
     if (useA || consume) apanel = P.apack + (int64_t)copy * P.apack_copy + (int64_t)tm * nK * KT * MT;
     if (useB || consume) bpanel = P.bpack + (int64_t)copy * P.bpack_copy + (int64_t)tn * nK * KT * NT;
-    // One completion flag and one claim per (copy, panel).
-    uint64_t* adone = useA ? P.aflag + (int64_t)copy * P.tilesM + tm : nullptr;
-    uint64_t* bdone = useB ? P.bflag + (int64_t)copy * P.tilesN + tn : nullptr;
+    // One completion flag and one claim per (copy, panel, k-slice): a slice's
+    // chunks of a panel are packed by the first workgroup of that slice.
+    const int64_t aslot = ((int64_t)copy * P.tilesM + tm) * S + slice;
+    const int64_t bslot = ((int64_t)copy * P.tilesN + tn) * S + slice;
+    uint64_t* adone = useA ? P.aflag + aslot : nullptr;
+    uint64_t* bdone = useB ? P.bflag + bslot : nullptr;
     auto load_flag = [&](const uint64_t* f) -> uint64_t {
         return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
@@ -115,10 +130,10 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     // packed chunk, so thread 0 claims and broadcasts.
     if (tid == 0) {
         int role = 0;
-        if (useA && __hip_atomic_exchange(P.aclaim + copy * P.tilesM + tm, epoch, __ATOMIC_RELAXED,
+        if (useA && __hip_atomic_exchange(P.aclaim + aslot, epoch, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT) != epoch)
             role |= 1;
-        if (useB && __hip_atomic_exchange(P.bclaim + copy * P.tilesN + tn, epoch, __ATOMIC_RELAXED,
+        if (useB && __hip_atomic_exchange(P.bclaim + bslot, epoch, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT) != epoch)
             role |= 2;
         s_role = role;
@@ -184,17 +199,17 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
 
-    // Prologue: stage chunk 0.
-    load_chunks(0);
+    // Prologue: stage the slice's first chunk.
+    load_chunks(q0);
     ra.store_lds(sA[0], tid);
     rb.store_lds(sB[0], tid);
-    if (prodA) ra.store_pack(apanel, tid);
-    if (prodB) rb.store_pack(bpanel, tid);
+    if (prodA) ra.store_pack(apanel + (int64_t)q0 * KT * MT, tid);
+    if (prodB) rb.store_pack(bpanel + (int64_t)q0 * KT * NT, tid);
     __syncthreads();
 
-    for (int q = 0; q < nK; ++q) {
-        const int cur = q & 1;
-        const bool more = q + 1 < nK;
+    for (int q = q0; q < q1; ++q) {
+        const int cur = (q - q0) & 1;
+        const bool more = q + 1 < q1;
         // Re-poll while an operand is still read unpacked.  The flag load is
         // issued before this step's chunk loads and read after them, when the
         // loads have been waited for anyway.
@@ -252,6 +267,37 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         atomicAdd(P.stats + 1, n_pk);
         atomicAdd(P.stats + 2, n_unpk);
         atomicAdd(P.stats + 3, n_polls);
+    }
+
+    // Split k: each slice stores its raw partial product (no alpha, beta or
+    // C) into its own column-major M x N plane of the workspace; a second
+    // kernel sums the planes in slice order and applies the epilogue.
+    if (S > 1) {
+        T* pp = P.part + (int64_t)slice * P.M * P.N;
+        auto di_ = [&](int r) -> int { return sizeof(T) == 8 ? (lane & 15) : 4 * (lane >> 4) + r; };
+        auto dj_ = [&](int r) -> int { return sizeof(T) == 8 ? 4 * r + (lane >> 4) : (lane & 15); };
+        const int64_t r0 = x0a + wm * WTM, c0 = x0b + wn * WTN;
+        const bool vec = sizeof(T) == 4 && x0a + MT <= P.M && x0b + NT <= P.N && P.M % 4 == 0;
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+                if (vec) {
+                    // four consecutive rows of one column: one 16-byte store
+                    typedef typename Types<T>::uvec U;
+                    U u;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) u[r] = acc[a][b][r];
+                    *reinterpret_cast<U*>(pp + (r0 + a * 16 + di_(0)) + (c0 + b * 16 + dj_(0)) * P.M) = u;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t i = r0 + a * 16 + di_(r), j = c0 + b * 16 + dj_(r);
+                        if (i < P.M && j < P.N) pp[i + j * P.M] = acc[a][b][r];
+                    }
+                }
+            }
+        return;
     }
 
     // Epilogue: C = alpha*acc + beta*C (C not read when beta == 0).  Lane l of
@@ -319,6 +365,25 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
                                            : alpha * acc[a][b][r];
                     }
                 }
+    }
+}
+
+// Second half of a split-k call: C = alpha * (sum of the slice planes, in
+// slice order 0, 1, ...) + beta * C, with the tile kernel's epilogue rounding
+// (C not read when beta == 0).  One thread per C element, column by column.
+template <typename T>
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(const T* __restrict__ part, int S,
+                                                            int64_t M, int64_t N, T* C,
+                                                            int64_t ldc, T alpha, T beta)
+{
+    const int64_t MN = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < MN;
+         idx += (int64_t)gridDim.x * 256) {
+        T v = part[idx];
+        for (int sl = 1; sl < S; ++sl) v = v + part[(int64_t)sl * MN + idx];
+        const int64_t i = idx % M, j = idx / M;
+        T* cp = C + i + j * ldc;
+        *cp = beta != T(0) ? axpby(alpha, v, beta, *cp) : alpha * v;
     }
 }
 
@@ -401,6 +466,10 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.a_fast = P.a_vec && a_span < ((int64_t)1 << 31);
     P.b_fast = P.b_vec && b_span < ((int64_t)1 << 31);
     P.order = d.order;
+    // split k (the host sizes slice_ksteps so that no slice is empty)
+    P.split = d.split > 1 ? d.split : 1;
+    P.slice_ksteps = d.split > 1 ? d.slice_ksteps : P.nK;
+    P.part = static_cast<T*>(d.part);
     return P;
 }
 
@@ -410,11 +479,19 @@ hipError_t launch_tile(const LaunchDesc& d)
     constexpr int KT = sizeof(T) == 8 ? 16 : 32;
     const Params<T> P = make_params<T>(d, MT, NT, KT);
     const bool akc = d.a_kmajor, bkc = d.b_kmajor;
-    const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN)), block(WM * WN * 64);
+    const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN * P.split)), block(WM * WN * 64);
     if (!akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, false><<<grid, block, 0, d.stream>>>(P);
     else if (!akc && bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, true><<<grid, block, 0, d.stream>>>(P);
     else if (akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, true, false><<<grid, block, 0, d.stream>>>(P);
     else gemm_kernel<T, MT, NT, KT, WM, WN, true, true><<<grid, block, 0, d.stream>>>(P);
+    if (P.split > 1) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        int64_t blocks = (d.M * d.N + 255) / 256;
+        if (blocks > 16384) blocks = 16384;
+        splitk_reduce_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, d.stream>>>(
+            P.part, P.split, d.M, d.N, P.C, d.ldc, P.alpha, P.beta);
+    }
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ FIP_ATTR_ORDER = 7
 FIP_ATTR_VB_SPLIT = 8
 FIP_ATTR_VB_GRID = 9
 FIP_ATTR_MX_TILE = 10
+FIP_ATTR_SPLIT_K = 11
 FIP_VB_GRAPH = 1
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
@@ -51,6 +52,8 @@ class fip_plan_t(ctypes.Structure):
         ("a_claim_offset", ctypes.c_int64), ("b_claim_offset", ctypes.c_int64),
         ("stats_offset", ctypes.c_int64),
         ("workspace_bytes", ctypes.c_int64),
+        ("split_k", ctypes.c_int32), ("slice_ksteps", ctypes.c_int32),
+        ("partial_offset", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -1,0 +1,208 @@
+"""GPU parity of the split-k path (FP64 / FP32): k cut into slices computed by separate
+workgroups, their partial products summed in slice order by a second kernel.
+
+Checked against the oracle within 4 k u max D, and for bit-identical results across pack
+policies, tile classes (at one split), repeated calls and stale workspaces."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_08417_amd import synth
+from paper_2302_08417_amd.synth import COL, ROW
+
+from gemm_util import check_full, to_dev
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = np.float64, np.float32
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_08417_amd import fipgemm
+    return fipgemm
+
+
+def say(*a):
+    print("[splitk]", *a, flush=True)
+
+
+def dcode(F, dtype):
+    return F.FIP_F64 if dtype == F64 else F.FIP_F32
+
+
+def run(F, c, policy=0, split=-1, tile=-1, h=None, C0=None):
+    """One call on a fresh handle (or h); returns (C host buffer, handle)."""
+    import torch
+    if h is None:
+        h = F.Handle(policy=policy, tile=tile)
+        h.set_attr(F.FIP_ATTR_SPLIT_K, split)
+    A, B = to_dev(c.A), to_dev(c.B)
+    C = to_dev(c.C if C0 is None else C0)
+    if policy == F.FIP_PACK_CONSUME_ONLY:
+        h.pack(c.layout, c.m, c.n, c.k, A, c.lda, c.transA, B, c.ldb, c.transB)
+    h.gemm(c.layout, c.m, c.n, c.k, c.alpha, A, c.lda, c.transA, B, c.ldb, c.transB, c.beta, C,
+           c.ldc)
+    torch.cuda.synchronize()
+    return C.cpu().numpy(), h
+
+
+def same_bits(x, y):
+    return np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
+@pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("shape,layout,tA,tB,pad", [
+    ((32, 2500, 3000), COL, "N", "N", 0),      # the skinny k-heavy shapes, ragged
+    ((2100, 40, 2900), COL, "T", "N", 7),
+    ((40, 1900, 2700), ROW, "N", "T", 3),
+    ((300, 200, 1900), ROW, "T", "T", 0),
+])
+def test_auto_split_matches_oracle(F, dtype, shape, layout, tA, tB, pad):
+    m, n, k = shape
+    say("auto split", dtype.__name__, shape, layout, tA, tB, pad)
+    c = synth.make_case(layout, m, n, k, tA, tB, ld_pad=pad, alpha=1.5, beta=0.5, dtype=dtype,
+                        seed=m + 3 * n + 7 * k)
+    out, h = run(F, c)
+    p = h.last_plan()
+    say("  split", p.split_k, "x", p.slice_ksteps, "k-steps, class", p.tile_class)
+    assert p.split_k > 1
+    check_full(c, out)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
+def test_split_modes_bitwise(F, dtype):
+    """All pack policies run the same slices in the same k order: C agrees bit for bit
+    (ALL packs per (panel, k-slice) and publishes per slice)."""
+    say("modes", dtype.__name__)
+    c = synth.make_case(COL, 200, 170, 2300, "N", "T", ld_pad=5, dtype=dtype, seed=31)
+    for split in (-1, 3):
+        ref, h = run(F, c, F.FIP_PACK_NONE, split=split)
+        assert h.last_plan().split_k > 1
+        check_full(c, ref)
+        for pol in (F.FIP_PACK_AUTO, F.FIP_PACK_ALL, F.FIP_PACK_CONSUME_ONLY):
+            say("  split", split, "policy", pol)
+            out, h2 = run(F, c, pol, split=split)
+            assert h2.last_plan().split_k == h.last_plan().split_k
+            assert same_bits(out, ref), (split, pol)
+        hn = F.Handle(policy=F.FIP_PACK_ALL)
+        hn.set_attr(F.FIP_ATTR_SPLIT_K, split)
+        hn.set_attr(F.FIP_ATTR_NO_PUBLISH, 1)
+        out, _ = run(F, c, F.FIP_PACK_ALL, h=hn)
+        assert same_bits(out, ref), (split, "no publish")
+
+
+@pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("split", [1, 2, 5, 7, 32])
+def test_forced_split_values(F, dtype, split):
+    """Forced slice counts, k not a multiple of the k-step: within tolerance, and the plan
+    reports the slices it ran (no empty slice)."""
+    say("forced", dtype.__name__, split)
+    c = synth.make_case(COL, 70, 90, 1000, "T", "N", alpha=-0.75, beta=1.25, dtype=dtype,
+                        seed=41 + split)
+    out, h = run(F, c, split=split)
+    p = h.last_plan()
+    kt = p.KT
+    nk = -(-1000 // kt)
+    # slices of ceil(nk / split) k-steps; the count is trimmed so that none is empty
+    assert 1 <= p.split_k <= split and p.slice_ksteps == -(-nk // split)
+    assert (p.split_k - 1) * p.slice_ksteps < nk <= p.split_k * p.slice_ksteps
+    check_full(c, out)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
+def test_tile_classes_bitwise_at_one_split(F, dtype):
+    """The slices cut k at the same k-steps for every tile class, so the classes agree bit
+    for bit at one split."""
+    say("classes", dtype.__name__)
+    c = synth.make_case(COL, 260, 300, 1500, "N", "N", dtype=dtype, seed=51)
+    ref, _ = run(F, c, split=4, tile=0)
+    check_full(c, ref)
+    for tile in (1, 2):
+        out, h = run(F, c, split=4, tile=tile)
+        assert h.last_plan().split_k == 4 and h.last_plan().tile_class == tile
+        assert same_bits(out, ref), tile
+
+
+@pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
+def test_repeated_calls_and_stale_workspace(F, dtype):
+    """Partials left by earlier calls (or garbage) never leak into C: same handle, workspace
+    poisoned with 0xFF or zeroed between calls, identical bits."""
+    import torch
+    say("repeat", dtype.__name__)
+    c = synth.make_case(ROW, 36, 3100, 2600, "N", "N", dtype=dtype, seed=61)
+    h = F.Handle()
+    ref, _ = run(F, c, h=h)
+    assert h.last_plan().split_k > 1
+    check_full(c, ref)
+    for trial, fill in enumerate((0xFF, 0x00, None, 0xFF)):
+        if fill is not None:
+            h.workspace.fill_(fill)
+            torch.cuda.synchronize()
+        say("  trial", trial, "fill", fill)
+        out, _ = run(F, c, h=h)
+        assert same_bits(out, ref), trial
+
+
+@pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
+def test_split_special_cases(F, dtype):
+    """beta = 0 does not read C (NaN C stays out of the result); beta = 1 accumulates."""
+    say("special", dtype.__name__)
+    c = synth.make_case(COL, 48, 64, 2048, "N", "N", alpha=2.0, beta=0.0, dtype=dtype, seed=71)
+    nanC = c.C.copy()
+    mask = np.zeros(c.C.size, bool)
+    mask[: c.ldc * c.n].reshape(c.n, c.ldc)[:, : c.m] = True
+    nanC[mask] = np.nan
+    out, h = run(F, c, C0=nanC)
+    assert h.last_plan().split_k > 1
+    assert np.all(np.isfinite(out[mask]))
+    check_full(c, np.where(mask, out, c.C))
+    c1 = synth.make_case(COL, 48, 64, 2048, "N", "N", alpha=1.0, beta=1.0, dtype=dtype, seed=72)
+    out1, _ = run(F, c1)
+    check_full(c1, out1)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
+def test_split_packed_chunks_bit_exact(F, dtype):
+    """PACK_POLICY=ALL with k split: every (panel, k-slice) is claimed on some XCD and
+    published, and the chunks of each claimed slice equal the oracle's pack byte for byte."""
+    say("split pack bits", dtype.__name__)
+    m, n, k = 70, 100, 1500
+    c = synth.make_case(COL, m, n, k, "T", "N", ld_pad=3, dtype=dtype, seed=81)
+    h = F.Handle(policy=F.FIP_PACK_ALL)
+    h.set_attr(F.FIP_ATTR_SPLIT_K, 4)
+    out, _ = run(F, c, h=h)
+    check_full(c, out)
+    p = h.last_plan()
+    S, per, nk = p.split_k, p.slice_ksteps, p.ksteps
+    assert S == 4 and p.pack_a and p.pack_b
+    ws = h.workspace
+    epoch = np.uint64(h.get_attr(F.FIP_ATTR_EPOCH))
+
+    def u64(off, count):
+        return ws[off: off + 8 * count].cpu().numpy().view(np.uint64)
+
+    for which, ntiles, mnt, off_pack, copy_bytes, off_claim, off_flag, X, ld, t, mn in [
+            ("A", p.tiles_m, p.MT, p.a_pack_offset, p.a_copy_bytes, p.a_claim_offset,
+             p.a_flag_offset, c.A, c.lda, "T", m),
+            ("B", p.tiles_n, p.NT, p.b_pack_offset, p.b_copy_bytes, p.b_claim_offset,
+             p.b_flag_offset, c.B, c.ldb, "N", n)]:
+        ref = oracle.pack(X, which == "B", c.layout, t, mn, k, ld, mnt, p.KT).view(np.uint8)
+        claims = u64(off_claim, F.COPIES * ntiles * S).reshape(F.COPIES, ntiles, S)
+        flags = u64(off_flag, F.COPIES * ntiles * S).reshape(F.COPIES, ntiles, S)
+        assert np.all((claims == epoch).any(axis=0)), f"{which}: a (panel, slice) never packed"
+        chunk_bytes = p.KT * mnt * c.A.itemsize
+        for cp in range(F.COPIES):
+            buf = ws[off_pack + cp * copy_bytes: off_pack + (cp + 1) * copy_bytes].cpu().numpy()
+            for t_ in range(ntiles):
+                for sl in range(S):
+                    if claims[cp, t_, sl] != epoch:
+                        continue
+                    assert flags[cp, t_, sl] == epoch, (which, cp, t_, sl)
+                    q0, q1 = sl * per, min(nk, (sl + 1) * per)
+                    lo = (t_ * nk + q0) * chunk_bytes
+                    hi = (t_ * nk + q1) * chunk_bytes
+                    assert np.array_equal(buf[lo:hi], ref[lo:hi]), (which, cp, t_, sl)
