@@ -94,7 +94,7 @@ enum {
     FIP_ATTR_VB_GRID = 9,
     /* Mixed-precision calls: C tile extent.  128: 128 x 128; 256: 256 x 256
        (128 x 128 per wave), bfloat16 only (other forms always use 128);
-       -1 (default): 256 for bfloat16 when the call has at least 4096 tiles of
+       -1 (default): 256 for bfloat16 when the call has at least 256 tiles of
        256 x 256, else 128. */
     FIP_ATTR_MX_TILE = 10,
     /* FP64/FP32 calls: split k into slices computed by separate workgroups;
@@ -117,7 +117,9 @@ enum {
     FIP_PACK_AUTO = 0,         /* paper Sec. 3.3 reuse table, applied when the
                                   launch has more tiles than fit on the device
                                   at once (only then can a later pass reuse a
-                                  pack without waiting for it) */
+                                  pack without waiting for it); bfloat16 and
+                                  E4M3 operands are never packed under AUTO
+                                  (their unpacked reads are as fast) */
     FIP_PACK_ALL = 1,          /* pack both operands whatever the shape */
     FIP_PACK_NONE = 2,         /* never pack (the unpacked "SUP" path, Sec. 2.3) */
     FIP_PACK_CONSUME_ONLY = 3, /* read only packed panels written beforehand by
@@ -142,11 +144,11 @@ enum {
  * pack (fip_pack) and CONSUME_ONLY use copy 0.
  * Mixed-precision forms (dtype FIP_BF16 .. FIP_BF16X3_FAST): MT = NT = 128
  * (256 for bfloat16, see FIP_ATTR_MX_TILE), KT = 64 (bfloat16), 128 (E4M3) or
- * 32 (split forms); every block is K-major
- * whatever the storage (a_kmajor = b_kmajor = 1), and holds PLANES planes of
- * MT*KT packed elements one after the other (PLANES = 3 for FIP_BF16X3, 2 for
- * FIP_BF16X3_FAST, else 1): plane t holds term t of the split (bfloat16 bits),
- * or the operand's own bfloat16 / E4M3 bits.  a_copy_bytes counts all planes.
+ * 32 (split forms); blocks keep the operand's storage orientation as above
+ * (a_kmajor / b_kmajor), and each holds PLANES planes of MT*KT packed elements
+ * one after the other (PLANES = 3 for FIP_BF16X3, 2 for FIP_BF16X3_FAST,
+ * else 1): plane t holds term t of the split (bfloat16 bits), or the
+ * operand's own bfloat16 / E4M3 bits.  a_copy_bytes counts all planes.
  */
 typedef struct {
     int32_t dtype, layout;

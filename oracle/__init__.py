@@ -238,13 +238,14 @@ MX_PLANES = {2: 1, 3: 1, 4: 3, 5: 2}
 
 def pack_mx(form, X, is_b, layout, trans, mn, k, ld, MNT=128):
     """Reference pack of a mixed-precision operand as bytes: blocks (tile, k-step), each
-    holding PLANES K-major planes of MNT*KT elements.  bfloat16 / E4M3 operands: their bits;
-    the split forms: the bfloat16 terms of split3, plane t = term t."""
+    holding PLANES planes of MNT*KT elements in the orientation the operand has in storage
+    (as oracle.pack).  bfloat16 / E4M3 operands: their bits; the split forms: the bfloat16
+    terms of split3, plane t = term t."""
     KT, PL = MX_KT[form], MX_PLANES[form]
     if PL == 1:
-        return pack_oriented(X, is_b, layout, trans, mn, k, ld, MNT, KT, 1).view(np.uint8)
+        return pack_oriented(X, is_b, layout, trans, mn, k, ld, MNT, KT, -1).view(np.uint8)
     planes = split3(np.asarray(X, dtype=np.float32))
-    packs = [pack_oriented(planes[t], is_b, layout, trans, mn, k, ld, MNT, KT, 1)
+    packs = [pack_oriented(planes[t], is_b, layout, trans, mn, k, ld, MNT, KT, -1)
              .reshape(-1, MNT * KT) for t in range(PL)]
     return np.stack(packs, axis=1).reshape(-1).view(np.uint8)
 

@@ -201,14 +201,13 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     int64_t resident;
     if (form >= 0) {
         // 128 x 128 tiles, or 256 x 256 (bfloat16 only); a packed element is
-        // PLANES values of the packed type.  Default: 256 once the launch has
-        // at least 16 rounds of 256-tiles (4096 tiles): measured ahead of 128
-        // at m = n = k = 16384, behind it at 8192, where the first round's
-        // unpacked reads weigh more.
+        // PLANES values of the packed type.  Default: 256 once the launch
+        // fills the device with 256-tiles (one workgroup per CU, 256 tiles):
+        // measured ahead of 128 at m = n = k = 4096, 8192 and 16384.
         cls = 0;
         const int64_t big_tiles = cdiv(pl->ks.M, fip::kMxTileBig) * cdiv(pl->ks.N, fip::kMxTileBig);
         const bool big = fip::mx_has_big(form) &&
-                         (h->mx_tile == 256 || (h->mx_tile == -1 && big_tiles >= 16 * 256));
+                         (h->mx_tile == 256 || (h->mx_tile == -1 && big_tiles >= 256));
         MT = big ? fip::kMxTileBig : fip::kMxTile;
         KT = fip::mx_kt(form);
         pl->elem = fip::mx_planes(form) * fip::mx_pack_bytes(form);
@@ -280,6 +279,14 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
                                   pl->split, &fa, &fb);
             pl->kpack_a = pl->tilesKN > 1 && fa >= 0.5;
             pl->kpack_b = pl->tilesKM > 1 && fb >= 0.5;
+            // bfloat16 / E4M3: the pack is a plain copy in the operand's own
+            // orientation, and the kernel reads either orientation from the
+            // caller's buffer at full speed (MN-major through the transposing
+            // LDS reads); measured, packed re-reads were slower than unpacked
+            // ones, so (Sec. 3.3: skip the pack when the strides allow fast
+            // unpacked access) AUTO does not pack them.  The split forms pack:
+            // an unpacked read redoes the split.
+            if (form == fip::kMxBF16 || form == fip::kMxFP8) pl->kpack_a = pl->kpack_b = 0;
         }
         if (pl->kpack_a || pl->kpack_b) copies = fip::kCopies;
     }
@@ -308,10 +315,9 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     p.copies = copies;
     p.policy = policy;
     p.stats_offset = pl->off_stats;
-    // packed block orientation: the operand's own for FP64/FP32, always
-    // K-major (the MFMA operand form) for the mixed-precision forms
-    p.a_kmajor = form >= 0 ? 1 : !mn_major(false, layout, tA);
-    p.b_kmajor = form >= 0 ? 1 : !mn_major(true, layout, tB);
+    // packed block orientation: the operand's own (every form)
+    p.a_kmajor = !mn_major(false, layout, tA);
+    p.b_kmajor = !mn_major(true, layout, tB);
     const bool fl = pl->mode == fip::kModeFused;
     p.workspace_bytes = (pl->kpack_a || pl->kpack_b || pl->split > 1) ? off : 0;
     p.split_k = pl->split;

@@ -33,11 +33,12 @@
 // with the same elements, so each wave may choose its source independently.
 //
 // Packed layout (every form): chunk (tile t, k-step q) is block t*nK + q of
-// PLANES * 128 * KT elements; plane t of a block holds the chunk K-major,
-// element (x, p) at x*KT + p.  K-major is the MFMA operand form (each lane
-// reads a contiguous k-run), so a packed chunk goes to LDS with plain vector
-// copies whatever the caller's storage order was: the first pass does the
-// transposition of MN-major operands once, later passes never.
+// PLANES * MT * KT elements; plane t of a block holds the chunk in the
+// operand's storage orientation: element (x, p) at x*KT + p (K-major) or
+// p*MT + x (MN-major).  A chunk goes from HBM (packed or not) to registers,
+// LDS and the pack buffer as 16-byte vectors in that orientation; the MFMA
+// fragments of MN-major chunks are read from LDS with the transposing loads
+// (ds_read_b64_tr_b16 / _b8), so no pass transposes in registers.
 #include <type_traits>
 
 #include "fip_internal.h"
@@ -96,6 +97,13 @@ template <int FORM, int MT_> struct Geo {
     static constexpr int LDS_OPERAND = PL * LDS_PLANE;    // one buffer of one operand
     static constexpr int PACK_PLANE = MT * KT * EB;       // bytes of one plane of a chunk
     static constexpr int PACK_CHUNK = PL * PACK_PLANE;
+    // MN-major chunks (operand contiguous along m or n) sit in LDS as KT rows
+    // of MT elements.  Pitch: the transposing fragment reads fetch 4 rows x 32
+    // bytes (16-bit forms) or 8 rows x 16 bytes (E4M3) per 16 lanes; a row
+    // stride of 32 (mod 128) or 16 (mod 128) bytes puts them on distinct banks.
+    static constexpr int PITCH_MN = MT * EB + (FORM == kMxFP8 ? 16 : 32);
+    static constexpr int LDS_PLANE_MN = KT * PITCH_MN;
+    template <bool KC> static constexpr int lds_operand() { return PL * (KC ? LDS_PLANE : LDS_PLANE_MN); }
     static_assert(KGROUPS * (MT / NR) == NTHR, "micro-blocks must cover the chunk");
     static_assert(WPR == 2 || WPR == 4, "8- or 16-byte rows");
 };
@@ -117,12 +125,14 @@ __device__ __forceinline__ uint32_t bf16_bits(float v)
 }
 __device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
 
-// Registers of one operand chunk on their way from HBM to LDS (and, for a
-// producer, to the pack buffer): thread b holds rows x0 .. x0+3 (x0 = 4*(b/8))
-// and k-values p0 .. p0+VK-1 (p0 = VK*(b%8)) of the chunk, already in packed
-// form: for each plane and row, WPR words of consecutive k.
+// Registers of one K-major operand chunk (operand contiguous along k) on their
+// way from HBM to LDS (and, for a producer, to the pack buffer): thread b holds
+// rows x0 .. x0+NR-1 (x0 = NR*(b/8)) and k-values p0 .. p0+VK-1 (p0 =
+// VK*(b%8)) of the chunk, already in packed form: for each plane and row, WPR
+// words of consecutive k.  MN-major operands use the specialisation below.
 template <int FORM, bool KC, int MT>
 struct Stage {
+    static_assert(KC, "MN-major chunks: Stage<FORM, false, MT>");
     typedef Geo<FORM, MT> G;
     static constexpr int NR = G::NR;
     typedef typename Form<FORM>::S S;
@@ -131,6 +141,14 @@ struct Stage {
 
     __device__ __forceinline__ static int x0_of(int tid) { return NR * (tid / G::KGROUPS); }
     __device__ __forceinline__ static int p0_of(int tid) { return VK * (tid % G::KGROUPS); }
+    // This thread's first source byte of the chunk at (xc, k = 0); ldb: bytes per row.
+    __device__ __forceinline__ static const char* thread_src(const char* X, int64_t xc, int64_t ldb,
+                                                             int tid)
+    {
+        return X + (xc + x0_of(tid)) * ldb + (int64_t)p0_of(tid) * SB;
+    }
+    // Byte step from one chunk to the next along k.
+    __device__ __forceinline__ static int64_t chunk_step(int64_t ldb) { return (int64_t)G::KT * SB; }
 
     __device__ __forceinline__ void clear()
     {
@@ -184,40 +202,6 @@ struct Stage {
                     for (int i = 0; i < 4; ++i) put(j, i, __uint_as_float(v[i]));
                 }
             }
-        } else {
-            // columns are contiguous along mn: VK loads of NR elements each
-            // (NR*SB bytes, in 16-, 8- or 4-byte pieces), transposed into rows
-            // in registers
-            clear();
-            constexpr int NW = NR * SB / 4;   // words per load
-#pragma unroll
-            for (int i = 0; i < VK; ++i) {
-                const char* p = src + i * ldb;
-                uint32_t v[NW];
-                if constexpr (NW % 4 == 0) {
-#pragma unroll
-                    for (int c = 0; c < NW / 4; ++c) {
-                        const u4 x = *reinterpret_cast<const u4a*>(p + 16 * c);
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) v[4 * c + u] = x[u];
-                    }
-                } else if constexpr (NW == 2) {
-                    const u2 x = *reinterpret_cast<const u2a*>(p);
-                    v[0] = x[0];
-                    v[1] = x[1];
-                } else {
-                    v[0] = *reinterpret_cast<const uint32_t*>(p);
-                }
-#pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    if constexpr (FORM == kMxBF16)
-                        put(j, i, (S)((v[j >> 1] >> (16 * (j & 1))) & 0xFFFFu));
-                    else if constexpr (FORM == kMxFP8)
-                        put(j, i, (S)((v[j >> 2] >> (8 * (j & 3))) & 0xFFu));
-                    else
-                        put(j, i, __uint_as_float(v[j]));
-                }
-            }
         }
     }
 
@@ -235,7 +219,7 @@ struct Stage {
             for (int i = 0; i < VK; ++i) {
                 const int64_t x = x0 + j, p = p0 + i;
                 S v = S(0);
-                if (x < MN && p < K) v = KC ? X[x * ld + p] : X[x + p * ld];
+                if (x < MN && p < K) v = X[x * ld + p];
                 put(j, i, v);
             }
     }
@@ -295,6 +279,208 @@ struct Stage {
     }
 };
 
+// Registers of one MN-major operand chunk (operand contiguous along m or n):
+// the chunk's KT rows (one k each) of MT elements stay in that orientation,
+// in HBM, in registers, in the pack and in LDS; the MFMA fragments are read
+// from LDS with the transposing loads (ds_read_b64_tr_b16 / _b8), so no pass
+// ever transposes in registers.  Eight threads cover 128 contiguous bytes of a
+// row: thread b takes 16-byte source vectors (h, j) at row 32h + b/8, element
+// VE*(b%8 + 8j) (VE = elements per 16 bytes).
+template <int FORM, int MT>
+struct Stage<FORM, false, MT> {
+    typedef Geo<FORM, MT> G;
+    typedef typename Form<FORM>::S S;
+    static constexpr int KT = G::KT, PL = G::PL, EB = G::EB, SB = G::SB;
+    static constexpr int VE = 16 / SB;                    // elements per source vector
+    static constexpr int VT = MT * SB / 16 / 8;           // vectors per thread per row
+    static constexpr int NP = KT / 32;                    // rows per thread
+    static constexpr int NV = NP * VT;
+    static constexpr int WPV = VE * EB / 4;               // packed words per vector and plane
+    static_assert(VT >= 1 && NP >= 1 && (WPV == 2 || WPV == 4), "MN-major staging shape");
+    uint32_t w[PL][NV][WPV];
+
+    __device__ __forceinline__ static int row_of(int v, int tid) { return 32 * (v / VT) + (tid >> 3); }
+    __device__ __forceinline__ static int x_of(int v, int tid) { return VE * ((tid & 7) + 8 * (v % VT)); }
+    __device__ __forceinline__ static const char* thread_src(const char* X, int64_t xc, int64_t ldb,
+                                                             int tid)
+    {
+        return X + (xc + x_of(0, tid)) * SB + (int64_t)row_of(0, tid) * ldb;
+    }
+    __device__ __forceinline__ static int64_t chunk_step(int64_t ldb) { return (int64_t)G::KT * ldb; }
+
+    // Place the VE source elements of vector v (all planes).
+    __device__ __forceinline__ void put_vec(int v, const uint32_t (&src)[4])
+    {
+        if constexpr (FORM == kMxBF16 || FORM == kMxFP8) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[0][v][u] = src[u];
+        } else {
+#pragma unroll
+            for (int e = 0; e < VE; e += 2) {
+                uint32_t h[3][2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const float x = __uint_as_float(src[e + q]);
+                    h[0][q] = bf16_bits(x);
+                    const float r1 = x - bf16_float(h[0][q]);
+                    h[1][q] = bf16_bits(r1);
+                    h[2][q] = bf16_bits(r1 - bf16_float(h[1][q]));
+                }
+#pragma unroll
+                for (int t = 0; t < PL; ++t) w[t][v][e >> 1] = h[t][0] | (h[t][1] << 16);
+            }
+        }
+    }
+
+    // Unpacked source, whole chunk present, dword-aligned rows.  src: this
+    // thread's first source byte of the chunk; ldb: bytes per row (k).
+    __device__ __forceinline__ void load_full(const char* __restrict__ src, int64_t ldb)
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const u4 x = *reinterpret_cast<const u4a*>(src + (int64_t)(32 * (v / VT)) * ldb +
+                                                       16 * 8 * (v % VT));
+            const uint32_t a[4] = {x[0], x[1], x[2], x[3]};
+            put_vec(v, a);
+        }
+    }
+
+    // Unpacked source, fringe chunk or unaligned operand: element loads with
+    // predicates; elements outside the operand are +0.
+    __device__ __forceinline__ void load_edge(const S* __restrict__ X, int64_t ld, int64_t MN,
+                                              int64_t K, int64_t xc, int64_t pc, int tid)
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int64_t p = pc + row_of(v, tid), x0 = xc + x_of(v, tid);
+            uint32_t a[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+                const int64_t x = x0 + e;
+                uint32_t b = 0u;
+                if (x < MN && p < K) {
+                    if constexpr (SB == 4) b = __float_as_uint(X[x + p * ld]);
+                    else b = (uint32_t)X[x + p * ld];
+                }
+                a[e * SB / 4] |= b << (8 * ((e * SB) & 3));
+            }
+            put_vec(v, a);
+        }
+    }
+
+    // Packed source (MN-major planes): element (x, p) of plane t at (p*MT + x)*EB.
+    __device__ __forceinline__ void load_packed(const char* __restrict__ chunk, int tid)
+    {
+#pragma unroll
+        for (int t = 0; t < PL; ++t)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const char* q = chunk + t * G::PACK_PLANE + (row_of(v, tid) * MT + x_of(v, tid)) * EB;
+                if constexpr (WPV == 4) {
+                    const u4 x = *reinterpret_cast<const u4*>(q);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) w[t][v][u] = x[u];
+                } else {
+                    const u2 x = *reinterpret_cast<const u2*>(q);
+                    w[t][v][0] = x[0];
+                    w[t][v][1] = x[1];
+                }
+            }
+    }
+
+    __device__ __forceinline__ void store_pack(char* __restrict__ chunk, int tid) const
+    {
+#pragma unroll
+        for (int t = 0; t < PL; ++t)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                char* q = chunk + t * G::PACK_PLANE + (row_of(v, tid) * MT + x_of(v, tid)) * EB;
+                if constexpr (WPV == 4)
+                    *reinterpret_cast<u4*>(q) = u4{w[t][v][0], w[t][v][1], w[t][v][2], w[t][v][3]};
+                else
+                    *reinterpret_cast<u2*>(q) = u2{w[t][v][0], w[t][v][1]};
+            }
+    }
+
+    __device__ __forceinline__ void store_lds(char* lds, int tid) const
+    {
+#pragma unroll
+        for (int t = 0; t < PL; ++t)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                char* q = lds + t * G::LDS_PLANE_MN + row_of(v, tid) * G::PITCH_MN + x_of(v, tid) * EB;
+                if constexpr (WPV == 4)
+                    *reinterpret_cast<u4*>(q) = u4{w[t][v][0], w[t][v][1], w[t][v][2], w[t][v][3]};
+                else
+                    *reinterpret_cast<u2*>(q) = u2{w[t][v][0], w[t][v][1]};
+            }
+    }
+};
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef int i2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) s4v lds_s4v;
+typedef __attribute__((address_space(3))) i2v lds_i2v;
+
+// MFMA operand fragments from one LDS plane.  Every fragment is "lane l gives
+// element x = x0 + (l % R) and a run of k starting at k0 + run(l)".
+//   K-major plane (rows x, pitch PITCH): one or two 16-byte reads.
+//   MN-major plane (rows k, pitch PITCH_MN): transposing reads.  Within each
+//   16 lanes, ds_read_b64_tr_b16 gives lane i, item r, element i%4 of the
+//   8 bytes that lane 4r + i/4 addressed (tr_b8: byte i%8 of lane 2r + i/8),
+//   so lane c addressing row k + c/4 (c/2), column x + 4*(c%4) (8*(c%2))
+//   hands lane i the k-run of column x + i.
+template <int FORM, int MT, bool KC>
+struct Frag {
+    typedef Geo<FORM, MT> G;
+
+    __device__ __forceinline__ static s4v tr16(const char* p)
+    {
+        return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4v*)(p));
+    }
+    __device__ __forceinline__ static i2v tr8(const char* p)
+    {
+        return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_i2v*)(p));
+    }
+    // 8 bfloat16 k-values: x = x0 + l%16 (sixteen-row form) or x0 + l%32
+    // (thirty-two-row form, R = 32), k = k0 + 8*(l/R) .. +8.
+    template <int R>
+    __device__ __forceinline__ static bf8v bf16(const char* plane, int x0, int k0, int lane)
+    {
+        const int x = x0 + (lane & (R - 1)), run = lane / R;
+        if constexpr (KC) {
+            return *reinterpret_cast<const bf8v*>(plane + x * G::PITCH + (k0 + 8 * run) * 2);
+        } else {
+            const int c = lane & 15;
+            const int xb = x0 + (lane & (R - 1) & ~15) + 4 * (c & 3);
+            const char* q = plane + (k0 + 8 * run + (c >> 2)) * G::PITCH_MN + xb * 2;
+            const s4v lo = tr16(q), hi = tr16(q + 4 * G::PITCH_MN);
+            const s8v v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+            return __builtin_bit_cast(bf8v, v);
+        }
+    }
+    // 32 E4M3 k-values: x = x0 + l%16, k = k0 + 32*(l/16) .. +32.
+    __device__ __forceinline__ static i8v fp8(const char* plane, int x0, int k0, int lane)
+    {
+        const int run = lane >> 4;
+        if constexpr (KC) {
+            return *reinterpret_cast<const i8v*>(plane + (x0 + (lane & 15)) * G::PITCH + k0 + 32 * run);
+        } else {
+            const int c = lane & 15;
+            const char* q = plane + (k0 + 32 * run + (c >> 1)) * G::PITCH_MN + x0 + 8 * (c & 1);
+            i8v v;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const i2v t = tr8(q + 8 * h * G::PITCH_MN);
+                v[2 * h] = t[0];
+                v[2 * h + 1] = t[1];
+            }
+            return v;
+        }
+    }
+};
+
 struct MxParams {
     const char* A; const char* B; char* C;
     int64_t a_ld, b_ld, ldc;        // in elements
@@ -349,19 +535,23 @@ struct Mma {
             }
     }
 
-    __device__ __forceinline__ static void step(const char* la, const char* lb, int lane, Acc& acc)
+    // One k-step on the LDS buffers sa, sb (plane 0 of each operand); xa, xb:
+    // the wave's first row / column.
+    template <bool AKC, bool BKC>
+    __device__ __forceinline__ static void step(const char* sa, const char* sb, int xa, int xb,
+                                                int lane, Acc& acc)
     {
-        const int row = lane & 15, run = lane >> 4;
+        typedef Frag<FORM, MT, AKC> FA;
+        typedef Frag<FORM, MT, BKC> FB_;
         // B fragments of the whole wave row first, then one A fragment at a
         // time against all of them (FB x FB MFMAs per A fragment)
         if constexpr (FORM == kMxFP8) {
             i8v fb[FB];
 #pragma unroll
-            for (int b = 0; b < FB; ++b)
-                fb[b] = *reinterpret_cast<const i8v*>(lb + (b * 16 + row) * G::PITCH + run * 32);
+            for (int b = 0; b < FB; ++b) fb[b] = FB_::fp8(sb, xb + b * 16, 0, lane);
 #pragma unroll
             for (int a = 0; a < FB; ++a) {
-                const i8v fa = *reinterpret_cast<const i8v*>(la + (a * 16 + row) * G::PITCH + run * 32);
+                const i8v fa = FA::fp8(sa, xa + a * 16, 0, lane);
 #pragma unroll
                 for (int b = 0; b < FB; ++b)
                     acc[0][a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
@@ -372,13 +562,10 @@ struct Mma {
             for (int s = 0; s < G::KT / 32; ++s) {
                 bf8v fb[FB];
 #pragma unroll
-                for (int b = 0; b < FB; ++b)
-                    fb[b] = *reinterpret_cast<const bf8v*>(lb + (b * 16 + row) * G::PITCH +
-                                                           (s * 32 + run * 8) * 2);
+                for (int b = 0; b < FB; ++b) fb[b] = FB_::template bf16<16>(sb, xb + b * 16, s * 32, lane);
 #pragma unroll
                 for (int a = 0; a < FB; ++a) {
-                    const bf8v fa = *reinterpret_cast<const bf8v*>(la + (a * 16 + row) * G::PITCH +
-                                                                   (s * 32 + run * 8) * 2);
+                    const bf8v fa = FA::template bf16<16>(sa, xa + a * 16, s * 32, lane);
 #pragma unroll
                     for (int b = 0; b < FB; ++b)
                         acc[0][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[b],
@@ -388,20 +575,18 @@ struct Mma {
         } else {
             // split forms: KT = 32, one substep; planes PL of each operand
             constexpr int PL = G::PL;
+            constexpr int PA = G::template lds_operand<AKC>() / PL;   // plane stride
+            constexpr int PB = G::template lds_operand<BKC>() / PL;
             bf8v fb[PL][FB];
 #pragma unroll
             for (int t = 0; t < PL; ++t)
 #pragma unroll
-                for (int b = 0; b < FB; ++b)
-                    fb[t][b] = *reinterpret_cast<const bf8v*>(lb + t * G::LDS_PLANE +
-                                                              (b * 16 + row) * G::PITCH + run * 16);
+                for (int b = 0; b < FB; ++b) fb[t][b] = FB_::template bf16<16>(sb + t * PB, xb + b * 16, 0, lane);
 #pragma unroll
             for (int a = 0; a < FB; ++a) {
                 bf8v fa[PL];
 #pragma unroll
-                for (int t = 0; t < PL; ++t)
-                    fa[t] = *reinterpret_cast<const bf8v*>(la + t * G::LDS_PLANE +
-                                                           (a * 16 + row) * G::PITCH + run * 16);
+                for (int t = 0; t < PL; ++t) fa[t] = FA::template bf16<16>(sa + t * PA, xa + a * 16, 0, lane);
 #pragma unroll
                 for (int b = 0; b < FB; ++b) {
                     f4 big = acc[0][a][b], small = acc[1][a][b];
@@ -463,15 +648,17 @@ struct Mma<FORM, 256> {
         bf8v a[FB], b[FB];
     };
 
-    // Fragments of k-block s of the wave's rows (la) and columns (lb).
-    __device__ __forceinline__ static void read(const char* la, const char* lb, int lane, int s,
-                                                Frags& f)
+    // Fragments of k-block s of the wave's rows (from xa) and columns (from xb).
+    template <bool AKC, bool BKC>
+    __device__ __forceinline__ static void read(const char* sa, const char* sb, int xa, int xb,
+                                                int lane, int s, Frags& f)
     {
-        const int off = (lane & 31) * G::PITCH + (s * KB + (lane >> 5) * 8) * 2;
 #pragma unroll
-        for (int b = 0; b < FB; ++b) f.b[b] = *reinterpret_cast<const bf8v*>(lb + b * 32 * G::PITCH + off);
+        for (int b = 0; b < FB; ++b)
+            f.b[b] = Frag<FORM, 256, BKC>::template bf16<32>(sb, xb + b * 32, s * KB, lane);
 #pragma unroll
-        for (int a = 0; a < FB; ++a) f.a[a] = *reinterpret_cast<const bf8v*>(la + a * 32 * G::PITCH + off);
+        for (int a = 0; a < FB; ++a)
+            f.a[a] = Frag<FORM, 256, AKC>::template bf16<32>(sa, xa + a * 32, s * KB, lane);
     }
 
     __device__ __forceinline__ static void mma(const Frags& f, Acc& acc)
@@ -495,8 +682,8 @@ gemm_mx_kernel(const MxParams P)
     typedef typename Form<FORM>::S S;
     constexpr int KT = G::KT, SB = G::SB, WT = G::WT;
 
-    __shared__ __attribute__((aligned(16))) char sA[2][G::LDS_OPERAND];
-    __shared__ __attribute__((aligned(16))) char sB[2][G::LDS_OPERAND];
+    __shared__ __attribute__((aligned(16))) char sA[2][G::template lds_operand<AKC>()];
+    __shared__ __attribute__((aligned(16))) char sB[2][G::template lds_operand<BKC>()];
     __shared__ int s_role;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -512,12 +699,9 @@ gemm_mx_kernel(const MxParams P)
     // byte step from one chunk to the next.
     const bool a_in = P.a_vec && x0a + MT <= P.M, b_in = P.b_vec && x0b + MT <= P.N;
     const int64_t a_ldb = P.a_ld * SB, b_ldb = P.b_ld * SB;
-    const char* a_src = P.A + (AKC ? (x0a + StA::x0_of(tid)) * a_ldb + StA::p0_of(tid) * SB
-                                   : (x0a + StA::x0_of(tid)) * SB + StA::p0_of(tid) * a_ldb);
-    const char* b_src = P.B + (BKC ? (x0b + StB::x0_of(tid)) * b_ldb + StB::p0_of(tid) * SB
-                                   : (x0b + StB::x0_of(tid)) * SB + StB::p0_of(tid) * b_ldb);
-    const int64_t a_step = AKC ? (int64_t)KT * SB : (int64_t)KT * a_ldb;
-    const int64_t b_step = BKC ? (int64_t)KT * SB : (int64_t)KT * b_ldb;
+    const char* a_src = StA::thread_src(P.A, x0a, a_ldb, tid);
+    const char* b_src = StB::thread_src(P.B, x0b, b_ldb, tid);
+    const int64_t a_step = StA::chunk_step(a_ldb), b_step = StB::chunk_step(b_ldb);
 
     const bool consume = P.mode == kModeConsumePacked;
     bool fused = P.mode == kModeFused;
@@ -624,8 +808,8 @@ gemm_mx_kernel(const MxParams P)
         typename MM::Frags fr[2];
         if (nK > 1) load_chunks(1);
         __syncthreads();
-        const int aoff = wm * WT * G::PITCH, boff = wn * WT * G::PITCH;
-        MM::read(sA[0] + aoff, sB[0] + boff, lane, 0, fr[0]);
+        const int xa = wm * WT, xb = wn * WT;
+        MM::template read<AKC, BKC>(sA[0], sB[0], xa, xb, lane, 0, fr[0]);
         // The last k-step is peeled off (MORE = false), so inside the loop
         // the path through the barrier is straight-line code and the MFMAs of
         // the last block do not wait for the next k-step's fragment reads.
@@ -637,11 +821,11 @@ gemm_mx_kernel(const MxParams P)
             const int cur = q & 1;
 #pragma unroll
             for (int s = 0; s < NB; ++s) {
-                if (s + 1 < NB) MM::read(sA[cur] + aoff, sB[cur] + boff, lane, s + 1, fr[(s + 1) & 1]);
+                if (s + 1 < NB) MM::template read<AKC, BKC>(sA[cur], sB[cur], xa, xb, lane, s + 1, fr[(s + 1) & 1]);
                 if (s == NB - 1 && more) {
                     __builtin_amdgcn_sched_barrier(0);
                     __syncthreads();
-                    MM::read(sA[cur ^ 1] + aoff, sB[cur ^ 1] + boff, lane, 0, fr[0]);
+                    MM::template read<AKC, BKC>(sA[cur ^ 1], sB[cur ^ 1], xa, xb, lane, 0, fr[0]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 MM::mma(fr[s & 1], acc);
@@ -663,7 +847,7 @@ gemm_mx_kernel(const MxParams P)
             const bool more = q + 1 < nK;
             poll_issue(q);
             if (more) load_chunks(q + 1);
-            MM::step(sA[cur] + wm * WT * G::PITCH, sB[cur] + wn * WT * G::PITCH, lane, acc);
+            MM::template step<AKC, BKC>(sA[cur], sB[cur], wm * WT, wn * WT, lane, acc);
             if (more) put_chunks(cur ^ 1, q + 1);
             poll_finish();
             __syncthreads();

@@ -260,7 +260,10 @@ def test_mx_plans(h, dtype, KT, planes, eb):
     rc, p = F.fip_plan(h, dtype, 1, 300, 200, 333, "T", "N")
     assert rc == 0
     assert (p.MT, p.NT, p.KT) == (128, 128, KT)
-    assert p.a_kmajor == 1 and p.b_kmajor == 1      # mixed forms pack K-major always
+    # packs keep the storage orientation: row-major op(A) = A^T runs along m, op(B) = B along n
+    assert p.a_kmajor == 0 and p.b_kmajor == 0
+    rc, q = F.fip_plan(h, dtype, 0, 300, 200, 333, "T", "N")   # column-major: both along k
+    assert rc == 0 and q.a_kmajor == 1 and q.b_kmajor == 1
     nk = -(-333 // KT)
     # row-major: op(A) is the kernel's B side; sizes are reported in the caller's terms
     assert p.a_copy_bytes == 3 * nk * KT * 128 * planes * eb
@@ -272,20 +275,33 @@ def test_mx_plans(h, dtype, KT, planes, eb):
 
 
 def test_mx_tile_choice(h):
-    """256 x 256 tiles: bfloat16 only; by default once a call has >= 4096 of them."""
+    """256 x 256 tiles: bfloat16 only; by default once a call has >= 256 of them."""
     def mt(dtype, n, tile=-1):
         assert F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, tile) == 0
         rc, p = F.fip_plan(h, dtype, 0, n, n, 512, "N", "N")
         assert rc == 0
         return p.MT
     try:
-        assert mt(F.FIP_BF16, 16384) == 256 and mt(F.FIP_BF16, 8192) == 128
-        assert mt(F.FIP_BF16, 8192, 256) == 256 and mt(F.FIP_BF16, 16384, 128) == 128
+        assert mt(F.FIP_BF16, 16384) == 256 and mt(F.FIP_BF16, 4096) == 256
+        assert mt(F.FIP_BF16, 3840) == 128 and mt(F.FIP_BF16, 2048) == 128
+        assert mt(F.FIP_BF16, 2048, 256) == 256 and mt(F.FIP_BF16, 16384, 128) == 128
         for other in (F.FIP_E4M3, F.FIP_BF16X3, F.FIP_BF16X3_FAST):
             assert mt(other, 16384) == 128 and mt(other, 16384, 256) == 128
         assert F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, 64) == 3
     finally:
         F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, -1)
+
+
+def test_mx_auto_pack_rule(h):
+    """AUTO never packs bfloat16 / E4M3 operands (unpacked reads are as fast); the split forms
+    follow the reuse rule (an unpacked read would redo the split)."""
+    assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO) == 0
+    for dtype in (F.FIP_BF16, F.FIP_E4M3):
+        rc, p = F.fip_plan(h, dtype, 0, 16384, 16384, 1024, "N", "N")
+        assert rc == 0 and (p.pack_a, p.pack_b) == (0, 0) and p.workspace_bytes == 0
+    for dtype in (F.FIP_BF16X3, F.FIP_BF16X3_FAST):
+        rc, p = F.fip_plan(h, dtype, 0, 16384, 16384, 1024, "N", "N")
+        assert rc == 0 and p.pack_a == 1
 
 
 def _vb_arrays():
