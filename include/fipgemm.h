@@ -111,6 +111,9 @@ enum {
        (claims and publish flags of that call hold this value; stamps are
        unique within the process). */
     FIP_ATTR_EPOCH = 5,
+    /* Read only: the hipError_t of the last launch that failed on this handle
+       (a call returning FIP_ERR_LAUNCH), 0 if none. */
+    FIP_ATTR_LAST_HIP_ERROR = 12,
 };
 
 enum {

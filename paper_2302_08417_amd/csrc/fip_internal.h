@@ -55,6 +55,11 @@ struct LaunchDesc {
     hipStream_t stream;
 };
 
+// hipGetLastError also reports non-sticky errors left by any earlier runtime
+// call in the process (another library's query, say); each launcher clears
+// them first, so the status it returns after its launches is its own.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 // Enqueue the fused-pack tile kernel.  Returns a hipError_t.
 hipError_t launch_gemm(const LaunchDesc& d);
 // Enqueue the standalone pack of both operands into copy 0 (pack-then-compute).

@@ -77,12 +77,19 @@ struct fip_handle_s {
     int vb_split;     // FIP_ATTR_VB_SPLIT (-1: tuned or default)
     int mx_tile;      // FIP_ATTR_MX_TILE (-1: planner's choice, 128, 256)
     int split_k;      // FIP_ATTR_SPLIT_K (-1: planner's choice, 1: off, 2..64: forced)
+    int last_hip_error;  // FIP_ATTR_LAST_HIP_ERROR
     VbState* vb;
 };
 
 namespace {
 
 bool valid_handle(fip_handle_t h) { return h != nullptr && h->magic == kMagic; }
+// A failed launch: keep the HIP status for FIP_ATTR_LAST_HIP_ERROR.
+int launch_failed(fip_handle_t h, hipError_t e)
+{
+    h->last_hip_error = (int)e;
+    return FIP_ERR_LAUNCH;
+}
 bool valid_trans(char t)
 {
     return t == 'N' || t == 'n' || t == 'T' || t == 't' || t == 'C' || t == 'c';
@@ -446,8 +453,9 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         if ((alpha == T(0) || k == 0) && beta == T(1)) return 0;
         const KernelShape ks = kernel_shape(layout, m, n);
         if (alpha == T(0) || k == 0) {
-            if (fip::launch_scale(sizeof(T), ks.M, ks.N, C, ldc, (double)beta, h->stream) != hipSuccess)
-                return FIP_ERR_LAUNCH;
+            if (const hipError_t e = fip::launch_scale(sizeof(T), ks.M, ks.N, C, ldc, (double)beta,
+                                                       h->stream); e != hipSuccess)
+                return launch_failed(h, e);
             return 0;
         }
         Plan pl;
@@ -476,7 +484,7 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
             d.stats = 0;
         }
         d.stream = h->stream;
-        if (fip::launch_gemm(d) != hipSuccess) return FIP_ERR_LAUNCH;
+        if (const hipError_t e = fip::launch_gemm(d); e != hipSuccess) return launch_failed(h, e);
         h->last = pl.pub;
         h->has_last = 1;
         return 0;
@@ -547,8 +555,9 @@ int gemm_mx_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, in
         const KernelShape ks = kernel_shape(layout, m, n);
         const int c_bf16 = c_type == FIP_BF16;
         if (alpha == 0.f || k == 0) {
-            if (fip::launch_scale_mx(c_bf16, ks.M, ks.N, C, ldc, beta, h->stream) != hipSuccess)
-                return FIP_ERR_LAUNCH;
+            if (const hipError_t e = fip::launch_scale_mx(c_bf16, ks.M, ks.N, C, ldc, beta, h->stream);
+                e != hipSuccess)
+                return launch_failed(h, e);
             return 0;
         }
         Plan pl;
@@ -564,7 +573,7 @@ int gemm_mx_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, in
         d.a_scale = ks.swapped ? b_scale : a_scale;
         d.b_scale = ks.swapped ? a_scale : b_scale;
         if (pl.pub.workspace_bytes > 0 && pl.mode == fip::kModeFused) d.epoch = h->epoch = next_epoch();
-        if (fip::launch_gemm_mx(d) != hipSuccess) return FIP_ERR_LAUNCH;
+        if (const hipError_t e = fip::launch_gemm_mx(d); e != hipSuccess) return launch_failed(h, e);
         h->last = pl.pub;
         h->has_last = 1;
         return 0;
@@ -857,6 +866,7 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_STATS: *value = handle->stats; return 0;
     case FIP_ATTR_ORDER: *value = handle->order; return 0;
     case FIP_ATTR_EPOCH: *value = (int64_t)handle->epoch; return 0;
+    case FIP_ATTR_LAST_HIP_ERROR: *value = handle->last_hip_error; return 0;
     case FIP_ATTR_VB_SPLIT: *value = handle->vb_split; return 0;
     case FIP_ATTR_VB_GRID: *value = fip::vbatched_grid(); return 0;
     case FIP_ATTR_MX_TILE: *value = handle->mx_tile; return 0;
@@ -942,7 +952,7 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
             fip::MxLaunchDesc d;
             fill_mx_desc(handle, pl, mx_form_of(dtype), layout, k, A, lda, transA, B, ldb, transB,
                          &d);
-            if (fip::launch_pack_mx(d) != hipSuccess) return FIP_ERR_LAUNCH;
+            if (const hipError_t e = fip::launch_pack_mx(d); e != hipSuccess) return launch_failed(handle, e);
             handle->last = pl.pub;
             handle->has_last = 1;
             return 0;
@@ -956,7 +966,7 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
         fill_operands(pl, layout, A, lda, transA, B, ldb, transB, &d);
         fill_workspace(handle, pl, &d);
         d.stream = handle->stream;
-        if (fip::launch_pack(d) != hipSuccess) return FIP_ERR_LAUNCH;
+        if (const hipError_t e = fip::launch_pack(d); e != hipSuccess) return launch_failed(handle, e);
         handle->last = pl.pub;
         handle->has_last = 1;
         return 0;

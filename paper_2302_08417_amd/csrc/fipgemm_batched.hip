@@ -340,6 +340,7 @@ int64_t vb_launch_grid(const VbLaunchDesc& d)
 
 hipError_t launch_vbatched(const VbLaunchDesc& d)
 {
+    clear_stale_error();
     if (d.total < 1) return hipSuccess;
     const VbParams P = make_vb_params(d);
     vbatched_kernel<<<dim3((unsigned)vb_launch_grid(d)), dim3(VB_NTHR), 0, d.stream>>>(P);

@@ -537,16 +537,19 @@ hipError_t dispatch_pack(const LaunchDesc& d)
 
 hipError_t launch_gemm(const LaunchDesc& d)
 {
+    clear_stale_error();
     return d.elem == 8 ? dispatch_gemm<double>(d) : dispatch_gemm<float>(d);
 }
 
 hipError_t launch_pack(const LaunchDesc& d)
 {
+    clear_stale_error();
     return d.elem == 8 ? dispatch_pack<double>(d) : dispatch_pack<float>(d);
 }
 
 hipError_t launch_xcc_map(uint32_t* out, int64_t nblocks, hipStream_t stream)
 {
+    clear_stale_error();
     xcc_map_kernel<<<dim3((unsigned)nblocks), dim3(64), 0, stream>>>(out);
     return hipGetLastError();
 }
@@ -554,6 +557,7 @@ hipError_t launch_xcc_map(uint32_t* out, int64_t nblocks, hipStream_t stream)
 hipError_t launch_scale(int elem, int64_t M, int64_t N, void* C, int64_t ldc, double beta,
                         hipStream_t stream)
 {
+    clear_stale_error();
     const int64_t total = M * N;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 8192) blocks = 8192;

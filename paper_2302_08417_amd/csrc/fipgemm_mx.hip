@@ -1141,13 +1141,22 @@ hipError_t dispatch_mx(const MxLaunchDesc& d, bool pack)
 
 }  // namespace
 
-hipError_t launch_gemm_mx(const MxLaunchDesc& d) { return dispatch_mx(d, false); }
+hipError_t launch_gemm_mx(const MxLaunchDesc& d)
+{
+    clear_stale_error();
+    return dispatch_mx(d, false);
+}
 
-hipError_t launch_pack_mx(const MxLaunchDesc& d) { return dispatch_mx(d, true); }
+hipError_t launch_pack_mx(const MxLaunchDesc& d)
+{
+    clear_stale_error();
+    return dispatch_mx(d, true);
+}
 
 hipError_t launch_scale_mx(int c_bf16, int64_t M, int64_t N, void* C, int64_t ldc, float beta,
                            hipStream_t stream)
 {
+    clear_stale_error();
     scale_mx_kernel<<<dim3(grid_for(M * N)), dim3(256), 0, stream>>>(static_cast<char*>(C), c_bf16,
                                                                       M, N, ldc, beta);
     return hipGetLastError();
@@ -1157,6 +1166,7 @@ hipError_t launch_quantize_fp8(int layout_col, int64_t rows, int64_t cols, const
                                int64_t ldx, int axis, uint8_t* Q, int64_t ldq, float* scales,
                                hipStream_t stream)
 {
+    clear_stale_error();
     const int64_t lines = axis == 0 ? rows : cols;
     uint32_t* amax = reinterpret_cast<uint32_t*>(scales);
     fp8_zero_kernel<<<dim3(grid_for(lines)), dim3(256), 0, stream>>>(amax, lines);

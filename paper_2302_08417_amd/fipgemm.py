@@ -19,6 +19,13 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "fipgemm.h")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2302_08417_amd.build`")
 
+# The library and PyTorch must share one HIP runtime.  PyTorch ships its own
+# libamdhip64; loading it first makes the library's libamdhip64 dependency
+# resolve to that copy.  Loaded the other way round, the process ends up with
+# two runtimes, and the library's reports no device (hipErrorNoDevice) once
+# PyTorch's has opened the GPU.
+import torch  # noqa: E402,F401  (load order only)
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 FIP_COL_MAJOR, FIP_ROW_MAJOR = 0, 1
@@ -31,6 +38,7 @@ FIP_ATTR_VB_SPLIT = 8
 FIP_ATTR_VB_GRID = 9
 FIP_ATTR_MX_TILE = 10
 FIP_ATTR_SPLIT_K = 11
+FIP_ATTR_LAST_HIP_ERROR = 12
 FIP_VB_GRAPH = 1
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
@@ -99,9 +107,10 @@ def header_symbols():
 
 
 class FipError(RuntimeError):
-    def __init__(self, func, code):
-        super().__init__(f"{func} returned {code}")
-        self.func, self.code = func, code
+    def __init__(self, func, code, hip_error=None):
+        extra = f" (hipError_t {hip_error})" if hip_error else ""
+        super().__init__(f"{func} returned {code}{extra}")
+        self.func, self.code, self.hip_error = func, code, hip_error
 
 
 def _addr(x):
@@ -247,7 +256,12 @@ class Handle:
 
     def _check(self, name, rc):
         if rc != 0:
-            raise FipError(name, rc)
+            hip = None
+            if rc == FIP_ERR_LAUNCH:
+                grc, v = fip_get_attr(self.h, FIP_ATTR_LAST_HIP_ERROR)
+                if grc == 0:
+                    hip = int(v)
+            raise FipError(name, rc, hip)
 
     def set_attr(self, attr, value):
         self._check("fip_set_attr", fip_set_attr(self.h, attr, value))
