@@ -149,6 +149,7 @@ struct Stage {
     }
     // Byte step from one chunk to the next along k.
     __device__ __forceinline__ static int64_t chunk_step(int64_t ldb) { return (int64_t)G::KT * SB; }
+    __device__ __forceinline__ void finish() {}
 
     __device__ __forceinline__ void clear()
     {
@@ -297,7 +298,12 @@ struct Stage<FORM, false, MT> {
     static constexpr int NV = NP * VT;
     static constexpr int WPV = VE * EB / 4;               // packed words per vector and plane
     static_assert(VT >= 1 && NP >= 1 && (WPV == 2 || WPV == 4), "MN-major staging shape");
+    static constexpr bool SPLIT = FORM == kMxX3 || FORM == kMxX3Fast;
     uint32_t w[PL][NV][WPV];
+    // Split forms: unpacked binary32 words stay raw until finish(), so the
+    // loads of the next chunk remain in flight across the current MFMAs.
+    uint32_t raw[SPLIT ? NV : 1][4];
+    bool pending = false;
 
     __device__ __forceinline__ static int row_of(int v, int tid) { return 32 * (v / VT) + (tid >> 3); }
     __device__ __forceinline__ static int x_of(int v, int tid) { return VE * ((tid & 7) + 8 * (v % VT)); }
@@ -340,8 +346,27 @@ struct Stage<FORM, false, MT> {
         for (int v = 0; v < NV; ++v) {
             const u4 x = *reinterpret_cast<const u4a*>(src + (int64_t)(32 * (v / VT)) * ldb +
                                                        16 * 8 * (v % VT));
-            const uint32_t a[4] = {x[0], x[1], x[2], x[3]};
-            put_vec(v, a);
+            if constexpr (SPLIT) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) raw[v][u] = x[u];
+            } else {
+                const uint32_t a[4] = {x[0], x[1], x[2], x[3]};
+                put_vec(v, a);
+            }
+        }
+        if constexpr (SPLIT) pending = true;
+    }
+
+    // Split forms: turn raw binary32 words into the packed planes (before the
+    // chunk is stored); a no-op otherwise or when the chunk came packed.
+    __device__ __forceinline__ void finish()
+    {
+        if constexpr (SPLIT) {
+            if (pending) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) put_vec(v, raw[v]);
+                pending = false;
+            }
         }
     }
 
@@ -366,11 +391,13 @@ struct Stage<FORM, false, MT> {
             }
             put_vec(v, a);
         }
+        if constexpr (SPLIT) pending = false;
     }
 
     // Packed source (MN-major planes): element (x, p) of plane t at (p*MT + x)*EB.
     __device__ __forceinline__ void load_packed(const char* __restrict__ chunk, int tid)
     {
+        if constexpr (SPLIT) pending = false;
 #pragma unroll
         for (int t = 0; t < PL; ++t)
 #pragma unroll
@@ -788,6 +815,8 @@ gemm_mx_kernel(const MxParams P)
         }
     };
     auto put_chunks = [&](int buf, int c) {
+        ra.finish();
+        rb.finish();
         ra.store_lds(sA[buf], tid);
         rb.store_lds(sB[buf], tid);
         if (prodA) ra.store_pack(apanel + (int64_t)c * G::PACK_CHUNK, tid);
