@@ -14,6 +14,8 @@ its pack launch).
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu-baseline]
                     [--no-mx] [--no-autograd] [--no-batched]
 
+With the sweep come cold-cache timings (a 512 MB write before each timed call) beside the
+hot ones, and graph-replayed per-call times for tiny sizes.
 Further sections of the same JSON line: the mixed-precision forms (bfloat16, FP8 E4M3,
 3- and 2-term bfloat16 splits) at m = n = k in {1024, 4096, 16384} with their error
 against the binary64 oracle; the bfloat16 autograd linear layer (8192 x 4096 x 4096,
@@ -452,6 +454,73 @@ def cpu_baseline(n, target_s=12.0):
                       f"C[:, :{cols}] of the m=n=k={n} workload ({t:.1f} s)"}
 
 
+def cache_section(F, torch):
+    """FP64, fused vs pack-then-compute: "hot" per-call times (repeated calls) beside "cold" ones
+    (a 512 MB write before every call evicts the XCD L2s and the 256 MB Infinity Cache; only the
+    call is timed), and for tiny sizes the per-call time of 100 calls replayed from one captured
+    graph beside the eager launch."""
+    import statistics
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    cold = []
+    for m, n, k in [(256, 256, 256), (1024, 1024, 1024), (4096, 4096, 4096), (32, 4096, 4096)]:
+        g = Gemm(F, torch, n, "f64", seed=71 + n + k, m=m, k=k)
+        row = {"m": m, "n": n, "k": k}
+        for pol, name in ((F.FIP_PACK_AUTO, "fused"), (F.FIP_PACK_CONSUME_ONLY,
+                                                         "pack_then_compute")):
+            reps = 20 if m * n * k >= 4096 ** 3 else 50
+            row[f"{name}_hot_us"] = round(1e3 * g.time(pol, reps, 3), 2)
+            ts = []
+            for r in range(reps):
+                flush.fill_(r & 0xFF)
+                a, b = ev(), ev()
+                a.record()
+                g.call(pol)
+                b.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            row[f"{name}_cold_us"] = round(1e3 * statistics.median(ts), 2)
+        row["cold_fused_speedup_vs_pack_then_compute"] = round(
+            row["pack_then_compute_cold_us"] / row["fused_cold_us"], 3)
+        log(f"[cold] {row}")
+        cold.append(row)
+        g.release()
+    graph = []
+    for n in (16, 64, 256):
+        g = Gemm(F, torch, n, "f64", seed=91 + n)
+        eager_us = 1e3 * g.time(F.FIP_PACK_AUTO, 200, 10)
+        h = g.handle(F.FIP_PACK_AUTO)
+        c = g.case
+        gr = torch.cuda.CUDAGraph()
+        calls = 100
+        with torch.cuda.graph(gr):
+            h.bind_stream()
+            for _ in range(calls):
+                rc = g.fn(h.h, c.layout, c.m, c.n, c.k, c.alpha, g.A, c.lda, c.transA, g.B, c.ldb,
+                          c.transB, c.beta, g.C, c.ldc)
+                if rc:
+                    raise F.FipError(g.fn.__name__, rc)
+        h.bind_stream()
+        gr.replay()
+        torch.cuda.synchronize()
+        ts = []
+        for r in range(5):
+            a, b = ev(), ev()
+            a.record()
+            gr.replay()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) * 1e3 / calls)
+        row = {"n": n, "eager_us_per_call": round(eager_us, 2),
+               "graph_us_per_call": round(statistics.median(ts), 2)}
+        log(f"[graph] {row}")
+        graph.append(row)
+        g.release()
+    del flush
+    torch.cuda.empty_cache()
+    return {"cold": cold, "graph_replay": graph}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -563,6 +632,8 @@ def main():
             "min_fused_speedup": min(sp), "median_fused_speedup": sorted(sp)[len(sp) // 2]}
         log(f"[bench] sweep summary {result['sweep_summary']}")
 
+    if not args.no_sweep:
+        result["cache_and_graph"] = cache_section(F, torch)
     if not args.no_mx:
         result["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
     if not args.no_autograd:

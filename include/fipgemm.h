@@ -128,6 +128,11 @@ enum {
     FIP_PACK_CONSUME_ONLY = 3, /* read only packed panels written beforehand by
                                   fip_pack (the pack-then-compute baseline) */
 };
+/* Stream capture: while the handle's stream is being captured into a graph,
+   AUTO and ALL calls are planned as NONE (fip_plan reports it), so a captured
+   GEMM replays correctly however its inputs change between replays: a fused
+   pack's claims and flags carry an epoch chosen per call on the host, which a
+   replay would reuse.  Split k and CONSUME_ONLY need no epoch and are kept. */
 
 /*
  * The plan of one call, in the caller's terms (op(A) is m x k, op(B) k x n).

@@ -84,6 +84,11 @@ struct fip_handle_s {
 namespace {
 
 bool valid_handle(fip_handle_t h) { return h != nullptr && h->magic == kMagic; }
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+}
 // A failed launch: keep the HIP status for FIP_ATTR_LAST_HIP_ERROR.
 int launch_failed(fip_handle_t h, hipError_t e)
 {
@@ -258,6 +263,12 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     }
 
     int policy = standalone_pack ? FIP_PACK_CONSUME_ONLY : h->policy;
+    // Under stream capture a fused call runs unpacked: its claims and flags are
+    // stamped with an epoch chosen on the host per call, and every replay of a
+    // captured launch would carry the same one, so a replay would take the
+    // previous replay's flags for its own and read packs of old data.
+    if ((policy == FIP_PACK_AUTO || policy == FIP_PACK_ALL) && stream_capturing(h->stream))
+        policy = FIP_PACK_NONE;
     int copies = 0;
     if (policy == FIP_PACK_CONSUME_ONLY) {
         pl->mode = fip::kModeConsumePacked;

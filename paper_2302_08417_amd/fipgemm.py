@@ -303,9 +303,9 @@ class Handle:
         """Dispatch on C's dtype (float64 -> fip_dgemm, float32 -> fip_sgemm)."""
         import torch
         dt = FIP_F64 if C.dtype == torch.float64 else FIP_F32
+        self.bind_stream()   # first: the plan depends on whether the stream is capturing
         p = self.plan(dt, layout, m, n, k, transA, transB)
         self.ensure_workspace(p.workspace_bytes)
-        self.bind_stream()
         fn = fip_dgemm if dt == FIP_F64 else fip_sgemm
         rc = fn(self.h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc)
         self._check(fn.__name__, rc)
@@ -315,9 +315,9 @@ class Handle:
         """Mixed-precision form dtype (FIP_BF16 .. FIP_BF16X3_FAST); C binary32 or bfloat16."""
         import torch
         c_type = FIP_BF16 if C.dtype == torch.bfloat16 else FIP_F32
+        self.bind_stream()   # first: the plan depends on whether the stream is capturing
         p = self.plan(dtype, layout, m, n, k, transA, transB)
         self.ensure_workspace(p.workspace_bytes)
-        self.bind_stream()
         self._check("fip_gemm_mx", fip_gemm_mx(self.h, dtype, layout, m, n, k, alpha, A, lda,
                                                transA, B, ldb, transB, beta, C, ldc, c_type,
                                                a_scale, b_scale))
