@@ -83,7 +83,8 @@ enum {
        into the workspace's statistics block (a diagnostic; costs atomics). */
     FIP_ATTR_STATS = 4,
     /* Tile order inside an XCD's run: 0 = GROUP_M tiles of a column
-       consecutive, 1 = consecutive tiles in distinct columns.  Default 0. */
+       consecutive, 1 = consecutive tiles in distinct columns; -1 (default):
+       1 for the split forms (FIP_BF16X3, FIP_BF16X3_FAST), else 0. */
     FIP_ATTR_ORDER = 7,
     /* Batched calls: problems with max(m, n) <= value use 16 x 16 C tiles,
        the others 32 x 32.  -1 (default): the value fip_vbatched_tune chose for
