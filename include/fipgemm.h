@@ -98,15 +98,17 @@ enum {
        -1 (default): 256 for bfloat16 when the call has at least 256 tiles of
        256 x 256, else 128. */
     FIP_ATTR_MX_TILE = 10,
-    /* FP64/FP32 calls: split k into slices computed by separate workgroups;
-       each slice writes its partial product to the workspace and a second
-       kernel sums the slices in slice order and applies alpha and beta.
+    /* Split k into slices computed by separate workgroups; each slice
+       writes its partial product to the workspace and a second kernel sums
+       the slices in slice order and applies alpha and beta.  FP64/FP32 calls
+       and mixed-precision calls on the 128 tile (a 256 tile never splits).
        -1 (default): the planner splits when the tiles would occupy at most
-       half of the resident workgroups (slices of >= 16 k-steps, at most 32
-       slices); 1: never; 2..32: slices of ceil(ksteps / value) k-steps (fewer
-       slices if that leaves some empty).  The split depends on the shape and
-       this attribute only, so every pack policy gives bit-identical C for a
-       given split. */
+       half (FP64/FP32) or a quarter (mixed forms) of the resident workgroups,
+       with slices of >= 16 k-steps (FP64/FP32), >= 256 k (split forms) or
+       >= 1024 k (bfloat16, E4M3), at most 32 slices; 1: never; 2..32: slices of ceil(ksteps / value) k-steps
+       (fewer slices if that leaves some empty).  The split depends on the
+       shape and this attribute only, so every pack policy gives bit-identical
+       C for a given split. */
     FIP_ATTR_SPLIT_K = 11,
     /* Read only: the 64-bit epoch stamp of the most recent fused call
        (claims and publish flags of that call hold this value; stamps are
@@ -179,9 +181,10 @@ typedef struct {
     int64_t workspace_bytes;   /* bytes this call needs */
     int32_t split_k;           /* k-slices (1: k not split) */
     int32_t slice_ksteps;      /* k-steps per slice (the last one may have fewer) */
-    int64_t partial_offset;    /* split_k > 1: the slices' partial products, elem
+    int64_t partial_offset;    /* split_k > 1: the slices' partial products
                                   [split_k][kernel N][kernel M] (C's shape, column-major;
-                                  transposed for row-major calls); -1 otherwise */
+                                  transposed for row-major calls) in C's type, binary32
+                                  for the mixed forms (FP8 scales applied); -1 otherwise */
 } fip_plan_t;
 
 int fip_create(fip_handle_t* handle);

@@ -89,7 +89,7 @@ inline bool mx_has_big(int form) { return form == kMxBF16; }
 
 struct MxLaunchDesc {
     int form;              // MxForm
-    int mt;                // tile extent: 128, or 256 (bfloat16 / E4M3)
+    int mt;                // tile extent: 128, or 256 (bfloat16 only)
     int mode;              // Mode
     int pack_a, pack_b, no_publish, stats, order;
     int c_bf16;            // C stored as bfloat16 (else binary32)
@@ -105,6 +105,10 @@ struct MxLaunchDesc {
     uint64_t* aflag; uint64_t* bflag; uint64_t* aclaim; uint64_t* bclaim;
     unsigned long long* stats_ptr;
     uint64_t epoch;
+    // split k (128 tiles only): `split` slices of `slice_ksteps` k-steps each
+    // (split = 1: none); binary32 slice partials [split][N][M] (column-major)
+    int split, slice_ksteps;
+    void* part;
     hipStream_t stream;
 };
 

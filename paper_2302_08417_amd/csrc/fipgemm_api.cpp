@@ -20,6 +20,9 @@ namespace {
 constexpr uint32_t kMagic = 0xF1F6E77u;
 constexpr int64_t kMinSliceKsteps = 16;  // split k: at least this many k-steps per slice
 constexpr int kMaxSplit = 32;            // split k: at most this many slices
+// split k, mixed forms: at least this many k per slice (bfloat16 / E4M3, whose first
+// pass only copies, and the bfloat16 split forms of binary32)
+constexpr int64_t kMinSliceKCopy = 1024, kMinSliceKSplit = 256;
 
 // Epoch stamps of fused calls.  Claims and publish flags in a workspace are
 // compared for equality with the current call's stamp, so a stamp must never
@@ -183,7 +186,7 @@ struct Plan {
     int64_t tilesKM, tilesKN, nK;
     int64_t off_stats, off_aflag, off_bflag, off_aclaim, off_bclaim, off_apack, off_bpack;
     int64_t apack_copy_elems, bpack_copy_elems;
-    int split, slice_ksteps;        // k split (FP64/FP32 kernel only; 1 = none)
+    int split, slice_ksteps;        // k split (1 = none; not on the 256 tile)
     int order;                      // tile order in effect (FIP_ATTR_ORDER or the planner's)
     int64_t off_part;
 };
@@ -242,22 +245,32 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     pl->tilesKN = cdiv(pl->ks.N, NT);
     pl->nK = cdiv(k, KT);
 
-    // Split k (FP64/FP32): when the tiles leave most of the device idle (at
-    // most half the resident workgroups), k is cut into slices of at least
-    // kMinSliceKsteps k-steps, one workgroup per (tile, slice), up to the
-    // resident count; a second kernel sums the slices' partial products.
-    // The choice depends on the shape only (not on the pack policy), so every
-    // policy runs the same arithmetic.
+    // Split k: when the tiles leave most of the device idle, k is cut into
+    // slices, one workgroup per (tile, slice), up to the resident count; a
+    // second kernel sums the slices' partial products.  FP64/FP32: at most
+    // half the resident workgroups busy, slices of at least kMinSliceKsteps
+    // k-steps.  Mixed forms (128 tile only): at most a quarter busy (their
+    // MFMA time per slice is short against the partial planes' traffic).
+    // The split forms take slices of >= 256 k: their first pass splits every
+    // binary32 operand element, and `split` times as many CUs share that work
+    // (measured 2.7x at m = n = k = 1024).  bfloat16 and E4M3 only copy, so
+    // short slices bring them nothing (E4M3 at 1024 with 256-k slices was
+    // 30 % slower): >= 1024 k.  The choice depends on the shape only (not on
+    // the pack policy), so every policy runs the same arithmetic.
     pl->split = 1;
     pl->slice_ksteps = (int)pl->nK;
-    if (form < 0 && pl->nK > 1) {
+    if ((form < 0 || MT == fip::kMxTile) && pl->nK > 1) {
         const int64_t tiles = pl->tilesKM * pl->tilesKN;
+        const int64_t busy = form < 0 ? 2 : 4;
+        const bool splits = form == fip::kMxX3 || form == fip::kMxX3Fast;
+        const int64_t min_slice = form < 0 ? kMinSliceKsteps
+                                           : std::max<int64_t>(1, (splits ? kMinSliceKSplit : kMinSliceKCopy) / KT);
         int64_t sp = 1;
         if (h->split_k > 0) {
             sp = h->split_k;
-        } else if (h->split_k == -1 && tiles > 0 && 2 * tiles <= resident) {
+        } else if (h->split_k == -1 && tiles > 0 && busy * tiles <= resident) {
             sp = resident / tiles;
-            if (sp > pl->nK / kMinSliceKsteps) sp = pl->nK / kMinSliceKsteps;
+            if (sp > pl->nK / min_slice) sp = pl->nK / min_slice;
             if (sp > kMaxSplit) sp = kMaxSplit;
         }
         if (sp > pl->nK) sp = pl->nK;
@@ -329,7 +342,9 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     pl->bpack_copy_elems = pl->kpack_b ? pl->tilesKN * pl->nK * KT * NT : 0;
     pl->off_apack = off; off = align256(off + copies * pl->apack_copy_elems * pl->elem);
     pl->off_bpack = off; off = align256(off + copies * pl->bpack_copy_elems * pl->elem);
-    pl->off_part = off; off = align256(off + (sp > 1 ? sp * pl->ks.M * pl->ks.N * pl->elem : 0));
+    // slice partials: the output type's accumulator (binary32 for the mixed forms)
+    const int64_t part_elem = form >= 0 ? 4 : pl->elem;
+    pl->off_part = off; off = align256(off + (sp > 1 ? sp * pl->ks.M * pl->ks.N * part_elem : 0));
 
     fip_plan_t& p = pl->pub;
     p.dtype = dtype; p.layout = layout; p.m = m; p.n = n; p.k = k;
@@ -544,9 +559,12 @@ void fill_mx_desc(const fip_handle_s* h, const Plan& pl, int form, int layout, i
         d->bpack = ws + pl.off_bpack;
         d->apack_copy_bytes = pl.apack_copy_elems * pl.elem;
         d->bpack_copy_bytes = pl.bpack_copy_elems * pl.elem;
+        if (pl.split > 1) d->part = ws + pl.off_part;
     } else {
         d->stats = 0;
     }
+    d->split = pl.split;
+    d->slice_ksteps = pl.slice_ksteps;
     d->stream = h->stream;
 }
 

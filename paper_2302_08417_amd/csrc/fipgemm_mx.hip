@@ -523,6 +523,8 @@ struct MxParams {
     int mode, pack_a, pack_b, no_publish, do_stats, order;
     int a_vec, b_vec;                // unpacked vector loads allowed (dword alignment)
     int c_bf16;
+    int split, slice_ksteps;         // k slices (1: none) and k-steps per slice
+    float* part;                     // slice partials [split][N][M] when split > 1
 };
 
 // One MFMA k-substep on LDS buffers la (A-side rows) and lb (B-side rows).
@@ -715,10 +717,17 @@ gemm_mx_kernel(const MxParams P)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
+    // Split k: workgroup w computes k-slice w / tiles of tile w % tiles, i.e.
+    // chunks [q0, q1); slices of one tile are `tiles` workgroups apart.
+    const int NS = MT == 128 ? P.split : 1;  // the 256 tile never splits
+    const int ntiles = P.tilesM * P.tilesN;
+    const int slice = NS > 1 ? (int)(blockIdx.x / (unsigned)ntiles) : 0;
     int tm, tn;
-    tile_coords(blockIdx.x, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
+    tile_coords((int)blockIdx.x - slice * ntiles, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
     const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * MT;
     const int nK = P.nK;
+    const int q0 = slice * P.slice_ksteps;
+    const int q1 = q0 + P.slice_ksteps < nK ? q0 + P.slice_ksteps : nK;
     const int nKfull = (int)(P.K / KT);
     const uint64_t epoch = P.epoch;
 
@@ -743,8 +752,11 @@ gemm_mx_kernel(const MxParams P)
     char* bpanel = nullptr;
     if (useA || consume) apanel = P.apack + copy * P.apack_copy + (int64_t)tm * nK * G::PACK_CHUNK;
     if (useB || consume) bpanel = P.bpack + copy * P.bpack_copy + (int64_t)tn * nK * G::PACK_CHUNK;
-    uint64_t* adone = useA ? P.aflag + (int64_t)copy * P.tilesM + tm : nullptr;
-    uint64_t* bdone = useB ? P.bflag + (int64_t)copy * P.tilesN + tn : nullptr;
+    // one claim and one completion flag per (copy, panel, k-slice)
+    const int64_t aslot = ((int64_t)copy * P.tilesM + tm) * NS + slice;
+    const int64_t bslot = ((int64_t)copy * P.tilesN + tn) * NS + slice;
+    uint64_t* adone = useA ? P.aflag + aslot : nullptr;
+    uint64_t* bdone = useB ? P.bflag + bslot : nullptr;
     auto load_flag = [&](const uint64_t* f) -> uint64_t {
         return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
@@ -753,10 +765,10 @@ gemm_mx_kernel(const MxParams P)
     // broadcast because every thread stores its share of each packed chunk.
     if (tid == 0) {
         int role = 0;
-        if (useA && __hip_atomic_exchange(P.aclaim + copy * P.tilesM + tm, epoch, __ATOMIC_RELAXED,
+        if (useA && __hip_atomic_exchange(P.aclaim + aslot, epoch, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT) != epoch)
             role |= 1;
-        if (useB && __hip_atomic_exchange(P.bclaim + copy * P.tilesN + tn, epoch, __ATOMIC_RELAXED,
+        if (useB && __hip_atomic_exchange(P.bclaim + bslot, epoch, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT) != epoch)
             role |= 2;
         s_role = role;
@@ -823,9 +835,10 @@ gemm_mx_kernel(const MxParams P)
         if (prodB) rb.store_pack(bpanel + (int64_t)c * G::PACK_CHUNK, tid);
     };
 
-    load_chunks(0);
-    put_chunks(0, 0);
+    load_chunks(q0);
+    put_chunks(0, q0);
     if constexpr (MT == 256) {
+        // (no split k here: q0 = 0 and q1 = nK)
         // Software pipeline with one wave per SIMD: the fragments of k-block
         // s + 1 are read while the MFMAs of block s issue; the next chunk goes
         // from registers to the other LDS buffer after block NB - 2, and the
@@ -871,9 +884,9 @@ gemm_mx_kernel(const MxParams P)
         kstep(nK - 1, std::false_type{});
     } else {
         __syncthreads();
-        for (int q = 0; q < nK; ++q) {
-            const int cur = q & 1;
-            const bool more = q + 1 < nK;
+        for (int q = q0; q < q1; ++q) {
+            const int cur = (q - q0) & 1;
+            const bool more = q + 1 < q1;
             poll_issue(q);
             if (more) load_chunks(q + 1);
             MM::template step<AKC, BKC>(sA[cur], sB[cur], wm * WT, wn * WT, lane, acc);
@@ -906,6 +919,35 @@ gemm_mx_kernel(const MxParams P)
     const float alpha = P.alpha, beta = P.beta;
     const int64_t r0w = x0a + wm * WT, c0w = x0b + wn * WT;
     const bool c_in = x0a + MT <= P.M && x0b + MT <= P.N;
+    if (MT == 128 && NS > 1) {
+        // Split k: the slice's product, with the FP8 scales applied (exact),
+        // goes to its own column-major M x N binary32 plane; a second kernel
+        // sums the planes in slice order and applies alpha, beta and C.
+        float* pp = P.part + (int64_t)slice * P.M * P.N;
+        const bool vec = c_in && P.M % 4 == 0;
+        MM::pieces(acc, lane, [&](f4 v, int di, int dj) {
+            const int64_t i0 = r0w + di, j = c0w + dj;
+            float ib = 1.f;
+            if (FORM == kMxFP8 && P.b_scale != nullptr && j < P.N) ib = 1.f / P.b_scale[j];
+            u4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float t = v[r];
+                if (FORM == kMxFP8 && P.a_scale != nullptr && i0 + r < P.M)
+                    t = t * (1.f / P.a_scale[i0 + r]);
+                o[r] = __float_as_uint(t * ib);
+            }
+            float* cp = pp + j * P.M;
+            if (vec) {
+                *reinterpret_cast<u4a*>(cp + i0) = o;
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (i0 + r < P.M && j < P.N) cp[i0 + r] = __uint_as_float(o[r]);
+            }
+        });
+        return;
+    }
     MM::pieces(acc, lane, [&](f4 v, int di, int dj) {
         const int64_t i0 = r0w + di, j = c0w + dj;
         float ib = 1.f;
@@ -997,6 +1039,31 @@ __global__ void __launch_bounds__(256) scale_mx_kernel(char* C, int c_bf16, int6
         } else {
             float* p = reinterpret_cast<float*>(C) + i + j * ldc;
             *p = beta == 0.f ? 0.f : beta * *p;
+        }
+    }
+}
+
+// Second half of a split-k call: C = alpha * (sum of the slice planes, in
+// slice order 0, 1, ...) + beta * C with the tile kernel's epilogue rounding
+// (C not read when beta == 0).  One thread per C element, column by column.
+__global__ void __launch_bounds__(256) splitk_reduce_mx_kernel(const float* __restrict__ part,
+                                                               int S, int64_t M, int64_t N,
+                                                               char* C, int c_bf16, int64_t ldc,
+                                                               float alpha, float beta)
+{
+    const int64_t MN = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < MN;
+         idx += (int64_t)gridDim.x * 256) {
+        float v = part[idx];
+        for (int sl = 1; sl < S; ++sl) v = v + part[(int64_t)sl * MN + idx];
+        const int64_t i = idx % M, j = idx / M;
+        if (c_bf16) {
+            uint16_t* cp = reinterpret_cast<uint16_t*>(C) + i + j * ldc;
+            const float o = beta != 0.f ? axpby(alpha, v, beta, bf16_float(*cp)) : alpha * v;
+            *cp = (uint16_t)bf16_bits(o);
+        } else {
+            float* cp = reinterpret_cast<float*>(C) + i + j * ldc;
+            *cp = beta != 0.f ? axpby(alpha, v, beta, *cp) : alpha * v;
         }
     }
 }
@@ -1131,6 +1198,9 @@ MxParams make_mx_params(const MxLaunchDesc& d, int MT)
     P.a_vec = ((uintptr_t)d.A % 4 == 0) && ((d.a_ld * SB) % 4 == 0);
     P.b_vec = ((uintptr_t)d.B % 4 == 0) && ((d.b_ld * SB) % 4 == 0);
     P.c_bf16 = d.c_bf16;
+    P.split = d.split > 1 ? d.split : 1;
+    P.slice_ksteps = d.split > 1 ? d.slice_ksteps : P.nK;
+    P.part = static_cast<float*>(d.part);
     return P;
 }
 
@@ -1141,11 +1211,21 @@ hipError_t launch_form(const MxLaunchDesc& d, bool pack)
     const bool akc = d.a_kmajor, bkc = d.b_kmajor;
     const dim3 block(NTHR);
     if (!pack) {
-        const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN));
+        // split k runs on the 128 tile only, with every slice non-empty
+        if (P.split > 1 && (MT != 128 || P.part == nullptr || P.slice_ksteps < 1 ||
+                            (int64_t)(P.split - 1) * P.slice_ksteps >= P.nK))
+            return hipErrorInvalidValue;
+        const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN * P.split));
         if (!akc && !bkc) gemm_mx_kernel<FORM, MT, false, false><<<grid, block, 0, d.stream>>>(P);
         else if (!akc && bkc) gemm_mx_kernel<FORM, MT, false, true><<<grid, block, 0, d.stream>>>(P);
         else if (akc && !bkc) gemm_mx_kernel<FORM, MT, true, false><<<grid, block, 0, d.stream>>>(P);
         else gemm_mx_kernel<FORM, MT, true, true><<<grid, block, 0, d.stream>>>(P);
+        if (P.split > 1) {
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            splitk_reduce_mx_kernel<<<dim3(grid_for(d.M * d.N)), dim3(256), 0, d.stream>>>(
+                P.part, P.split, d.M, d.N, P.C, P.c_bf16, d.ldc, P.alpha, P.beta);
+        }
     } else {
         const dim3 grid((unsigned)(((int64_t)P.tilesM + P.tilesN) * P.nK));
         if (!akc && !bkc) pack_mx_kernel<FORM, MT, false, false><<<grid, block, 0, d.stream>>>(P);

@@ -304,6 +304,52 @@ def test_mx_auto_pack_rule(h):
         assert rc == 0 and p.pack_a == 1
 
 
+def test_split_choice(h):
+    """Split k: FP64/FP32 when the tiles fill at most half of the resident workgroups (>= 16
+    k-steps per slice); the mixed forms on the 128 tile when they fill at most a quarter
+    (>= 256 k per slice for the split forms, >= 1024 k for bfloat16 / E4M3); never on the
+    bfloat16 256 tile; at most 32 slices, none empty."""
+    def plan(dtype, m, n, k, split=-1, tile=-1):
+        assert F.fip_set_attr(h, F.FIP_ATTR_SPLIT_K, split) == 0
+        assert F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, tile) == 0
+        rc, p = F.fip_plan(h, dtype, 0, m, n, k, "N", "N")
+        assert rc == 0
+        return p
+    try:
+        # 64 tiles of 128 at k = 1024: the split forms (1 per CU: 256 resident) -> 4 slices
+        # of 8 k-steps; bf16 and E4M3 need 2048 k for two slices -> none
+        for dtype in (F.FIP_BF16X3, F.FIP_BF16X3_FAST):
+            p = plan(dtype, 1024, 1024, 1024)
+            assert (p.MT, p.split_k, p.slice_ksteps) == (128, 4, 8), dtype
+            assert p.partial_offset >= 0
+            assert p.workspace_bytes >= p.partial_offset + 4 * 1024 * 1024 * 4
+        for dtype in (F.FIP_BF16, F.FIP_E4M3):
+            assert plan(dtype, 1024, 1024, 1024).split_k == 1
+            # 4 tiles, k = 8192: 8 slices of 1024 k
+            p = plan(dtype, 256, 256, 8192)
+            assert (p.MT, p.split_k, p.slice_ksteps * p.KT) == (128, 8, 1024), dtype
+        # bf16 at 2048: 256 tiles of 128 fill half of the resident workgroups -> no split
+        assert plan(F.FIP_BF16, 2048, 2048, 2048).split_k == 1
+        # a 256 tile never splits, even when forced; forced on the 128 tile it does
+        assert plan(F.FIP_BF16, 4096, 4096, 4096, split=4).MT == 256
+        assert plan(F.FIP_BF16, 4096, 4096, 4096, split=4).split_k == 1
+        assert plan(F.FIP_BF16, 4096, 4096, 4096, split=4, tile=128).split_k == 4
+        # few tiles, very deep k: capped at 32 slices
+        p = plan(F.FIP_BF16X3, 256, 256, 16384)
+        assert (p.split_k, p.slice_ksteps) == (32, 16)
+        # k below two minimum slices: no split
+        assert plan(F.FIP_BF16X3, 256, 256, 448).split_k == 1
+        # FP64: 4 tiles with a deep k split; a full device does not
+        assert plan(F.FIP_F64, 128, 128, 8192).split_k > 1
+        assert plan(F.FIP_F64, 8192, 8192, 8192).split_k == 1
+        # AUTO with split but no packing (bf16): the workspace holds the partials only
+        p = plan(F.FIP_BF16, 256, 256, 8192)
+        assert (p.pack_a, p.pack_b) == (0, 0) and p.workspace_bytes > 0
+    finally:
+        F.fip_set_attr(h, F.FIP_ATTR_SPLIT_K, -1)
+        F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, -1)
+
+
 def _vb_arrays():
     import numpy as np
     m = np.array([5, 0, 300, 64], np.int32)

@@ -10,7 +10,7 @@ import oracle
 from paper_2302_08417_amd import synth
 from paper_2302_08417_amd.synth import COL, ROW
 
-from gemm_util import check_full, to_dev
+from gemm_util import c_mask, check_full, check_mx, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -206,3 +206,166 @@ def test_split_packed_chunks_bit_exact(F, dtype):
                     lo = (t_ * nk + q0) * chunk_bytes
                     hi = (t_ * nk + q1) * chunk_bytes
                     assert np.array_equal(buf[lo:hi], ref[lo:hi]), (which, cp, t_, sl)
+
+
+# ---- mixed-precision forms (128 x 128 tiles) -------------------------------------------------
+
+MX_FORMS = [synth.FORM_BF16, synth.FORM_E4M3, synth.FORM_BF16X3, synth.FORM_BF16X3_FAST]
+MX_IDS = ["bf16", "e4m3", "bf16x3", "bf16x3f"]
+
+
+def min_slice_k(form):
+    """The planner's minimum k per slice: the split forms share their first pass's split
+    work; bfloat16 and E4M3 only copy and split for deep k only."""
+    return 256 if form in (synth.FORM_BF16X3, synth.FORM_BF16X3_FAST) else 1024
+
+
+def deep_k(form):
+    """A k deep enough for several default slices on a few tiles."""
+    return 2000 if min_slice_k(form) == 256 else 4100
+
+
+def run_mx(F, c, policy=0, split=-1, h=None, no_publish=0, C0=None):
+    """One mixed-precision call on a fresh handle (or h) with the 128 tile; returns (C host
+    buffer, handle)."""
+    import torch
+    if h is None:
+        h = F.Handle(policy=policy)
+        h.set_attr(F.FIP_ATTR_SPLIT_K, split)
+        h.set_attr(F.FIP_ATTR_NO_PUBLISH, no_publish)
+    h.set_attr(F.FIP_ATTR_MX_TILE, 128)
+    A, B = to_dev(c.A), to_dev(c.B)
+    C = to_dev(c.C if C0 is None else C0)
+    if c.c_bf16:
+        C = C.view(torch.bfloat16)
+    sa = to_dev(c.a_scale) if c.a_scale is not None else None
+    sb = to_dev(c.b_scale) if c.b_scale is not None else None
+    if policy == F.FIP_PACK_CONSUME_ONLY:
+        h.pack(c.layout, c.m, c.n, c.k, A, c.lda, c.transA, B, c.ldb, c.transB, dtype=c.form)
+    h.gemm_mx(c.form, c.layout, c.m, c.n, c.k, c.alpha, A, c.lda, c.transA, B, c.ldb, c.transB,
+              c.beta, C, c.ldc, sa, sb)
+    torch.cuda.synchronize()
+    out = (C.view(torch.int16) if c.c_bf16 else C).cpu().numpy()
+    return (out.view(np.uint16) if c.c_bf16 else out), h
+
+
+@pytest.mark.parametrize("form", MX_FORMS, ids=MX_IDS)
+@pytest.mark.parametrize("layout,tA,tB,pad,c_bf16", [
+    (COL, "N", "N", 0, False),
+    (ROW, "T", "N", 5, False),
+    (COL, "T", "T", 3, True),
+])
+def test_mx_auto_split_matches_oracle(F, form, layout, tA, tB, pad, c_bf16):
+    """Few tiles, deep k: the planner splits k (slices of >= 256 k); FP8 scales are applied
+    per slice (exact powers of two) and alpha, beta, C by the reduction, for a binary32 or a
+    bfloat16 C."""
+    m, n, k = 300, 260, deep_k(form)
+    say("mx auto split", form, layout, tA, tB, pad, c_bf16)
+    c = synth.make_mx_case(form, layout, m, n, k, tA, tB, ld_pad=pad, alpha=1.5, beta=0.5,
+                           seed=form * 17 + layout * 3 + pad, c_bf16=c_bf16)
+    out, h = run_mx(F, c)
+    p = h.last_plan()
+    say("  split", p.split_k, "x", p.slice_ksteps, "k-steps of", p.KT)
+    assert p.MT == 128 and p.split_k > 1 and p.slice_ksteps * p.KT >= min_slice_k(form)
+    nerr, truth = check_mx(c, out)
+    say(f"  normalised error {nerr:.3e}; vs binary64 product of binary32 inputs {truth:.3e}")
+
+
+@pytest.mark.parametrize("form", MX_FORMS, ids=MX_IDS)
+def test_mx_split_modes_bitwise(F, form):
+    """At a given split every pack policy (and ALL without publishing) runs the same slices
+    in the same k order: C agrees bit for bit."""
+    say("mx split modes", form)
+    c = synth.make_mx_case(form, COL, 260, 200, deep_k(form) - 200, "N", "T", ld_pad=3,
+                           alpha=1.0, beta=0.5, seed=91 + form)
+    for split in (-1, 3):
+        ref, h = run_mx(F, c, F.FIP_PACK_NONE, split=split)
+        S = h.last_plan().split_k
+        assert S > 1
+        check_mx(c, ref)
+        for pol, nopub in [(F.FIP_PACK_AUTO, 0), (F.FIP_PACK_ALL, 0), (F.FIP_PACK_ALL, 1),
+                           (F.FIP_PACK_CONSUME_ONLY, 0)]:
+            say("  split", split, "policy", pol, "no publish", nopub)
+            out, h2 = run_mx(F, c, pol, split=split, no_publish=nopub)
+            assert h2.last_plan().split_k == S
+            assert same_bits(out, ref), (split, pol, nopub)
+
+
+@pytest.mark.parametrize("form", MX_FORMS, ids=MX_IDS)
+@pytest.mark.parametrize("split", [2, 5, 32])
+def test_mx_forced_split_values(F, form, split):
+    """Forced slice counts, k not a multiple of the k-step: within the bound, and the plan
+    reports the slices it ran (none empty)."""
+    say("mx forced", form, split)
+    c = synth.make_mx_case(form, ROW, 150, 90, 1100, "N", "N", alpha=-0.75, beta=1.25,
+                           seed=101 + split + form)
+    out, h = run_mx(F, c, split=split)
+    p = h.last_plan()
+    nk = -(-1100 // p.KT)
+    assert 1 <= p.split_k <= split and p.slice_ksteps == -(-nk // split)
+    assert (p.split_k - 1) * p.slice_ksteps < nk <= p.split_k * p.slice_ksteps
+    check_mx(c, out)
+
+
+@pytest.mark.parametrize("form", MX_FORMS, ids=MX_IDS)
+def test_mx_split_packed_chunks_bit_exact(F, form):
+    """PACK_POLICY=ALL with k split: every (panel, k-slice) is claimed on some XCD and
+    published, and the chunks of each claimed slice equal the oracle's pack byte for byte."""
+    say("mx split pack bits", form)
+    m, n, k = 300, 170, 1500
+    c = synth.make_mx_case(form, COL, m, n, k, "T", "N", ld_pad=4, seed=111 + form)
+    out, h = run_mx(F, c, F.FIP_PACK_ALL, split=4)
+    check_mx(c, out)
+    p = h.last_plan()
+    S, per, nk = p.split_k, p.slice_ksteps, p.ksteps
+    assert S == 4 and p.pack_a and p.pack_b
+    ws = h.workspace
+    epoch = np.uint64(h.get_attr(F.FIP_ATTR_EPOCH))
+
+    def u64(off, count):
+        return ws[off: off + 8 * count].cpu().numpy().view(np.uint64)
+
+    for which, ntiles, off_pack, copy_bytes, off_claim, off_flag, X, ld, t, mn, is_b in [
+            ("A", p.tiles_m, p.a_pack_offset, p.a_copy_bytes, p.a_claim_offset,
+             p.a_flag_offset, c.A, c.lda, "T", m, 0),
+            ("B", p.tiles_n, p.b_pack_offset, p.b_copy_bytes, p.b_claim_offset,
+             p.b_flag_offset, c.B, c.ldb, "N", n, 1)]:
+        ref = oracle.pack_mx(form, X, is_b, c.layout, t, mn, k, ld, p.MT)
+        assert ref.size == copy_bytes
+        chunk_bytes = copy_bytes // (ntiles * nk)
+        claims = u64(off_claim, F.COPIES * ntiles * S).reshape(F.COPIES, ntiles, S)
+        flags = u64(off_flag, F.COPIES * ntiles * S).reshape(F.COPIES, ntiles, S)
+        assert np.all((claims == epoch).any(axis=0)), f"{which}: a (panel, slice) never packed"
+        for cp in range(F.COPIES):
+            buf = ws[off_pack + cp * copy_bytes: off_pack + (cp + 1) * copy_bytes].cpu().numpy()
+            for t_ in range(ntiles):
+                for sl in range(S):
+                    if claims[cp, t_, sl] != epoch:
+                        continue
+                    assert flags[cp, t_, sl] == epoch, (which, cp, t_, sl)
+                    lo = (t_ * nk + sl * per) * chunk_bytes
+                    hi = (t_ * nk + min(nk, (sl + 1) * per)) * chunk_bytes
+                    assert np.array_equal(buf[lo:hi], ref[lo:hi]), (which, cp, t_, sl)
+
+
+@pytest.mark.parametrize("form", MX_FORMS, ids=MX_IDS)
+def test_mx_split_stale_workspace_and_special_cases(F, form):
+    """Partials of earlier calls (or garbage) never leak into C; beta = 0 does not read C
+    (NaN C stays out of the result)."""
+    import torch
+    say("mx split stale", form)
+    c = synth.make_mx_case(form, COL, 64, 300, deep_k(form) - 400, "N", "N", alpha=2.0,
+                           beta=0.0, seed=121 + form)
+    nanC = c.C.copy()
+    nanC[c_mask(c)] = np.nan
+    h = F.Handle()
+    ref, _ = run_mx(F, c, h=h, C0=nanC)
+    assert h.last_plan().split_k > 1
+    check_mx(c, ref)
+    for trial, fill in enumerate((0xFF, 0x00, None)):
+        if fill is not None:
+            h.workspace.fill_(fill)
+            torch.cuda.synchronize()
+        say("  trial", trial, "fill", fill)
+        out, _ = run_mx(F, c, h=h, C0=nanC)
+        assert same_bits(out, ref), trial
