@@ -287,6 +287,66 @@ def mx_section(F, torch, sizes):
     return out
 
 
+MX_DEEP_K = [(256, 256, 8192), (128, 512, 16384)]
+
+
+def mx_deep_k_section(F, torch):
+    """Mixed-precision forms on few tiles with a deep k (column-major NN, alpha = 1,
+    beta = 0): fused with the planner's k split, fused unsplit, pack-then-compute and no-pack
+    (both with the planner's split), in microseconds.  Operands: N(0, 1) binary32 (split
+    forms) or rounded to bfloat16; E4M3 codes drawn uniformly from the finite codes of
+    magnitude <= 120 with unit scales."""
+    out = []
+    for (m, n, k) in MX_DEEP_K:
+        for name, dt, peak, prods in MX_FORMS:
+            g = torch.Generator(device="cuda").manual_seed(m + n + k + dt)
+            if dt == F.FIP_E4M3:
+                A = torch.randint(0, 0x70, (m * k,), device="cuda", generator=g, dtype=torch.uint8)
+                B = torch.randint(0, 0x70, (k * n,), device="cuda", generator=g, dtype=torch.uint8)
+                A |= (torch.randint(0, 2, (m * k,), device="cuda", generator=g, dtype=torch.uint8) << 7)
+                B |= (torch.randint(0, 2, (k * n,), device="cuda", generator=g, dtype=torch.uint8) << 7)
+            else:
+                A = torch.randn(m * k, device="cuda", generator=g)
+                B = torch.randn(k * n, device="cuda", generator=g)
+                if dt == F.FIP_BF16:
+                    A, B = A.to(torch.bfloat16), B.to(torch.bfloat16)
+            C = torch.zeros(m * n, device="cuda")
+            legs = {"fused": (F.FIP_PACK_AUTO, -1), "fused_unsplit": (F.FIP_PACK_AUTO, 1),
+                    "pack_then_compute": (F.FIP_PACK_CONSUME_ONLY, -1),
+                    "no_pack": (F.FIP_PACK_NONE, -1)}
+            hs = {}
+            for key, (pol, split) in legs.items():
+                hs[key] = F.Handle(policy=pol)
+                hs[key].set_attr(F.FIP_ATTR_SPLIT_K, split)
+
+            def mk(key):
+                h, pol = hs[key], legs[key][0]
+
+                def call():
+                    if pol == F.FIP_PACK_CONSUME_ONLY:
+                        h.pack(0, m, n, k, A, m, "N", B, k, "N", dtype=dt)
+                    h.gemm_mx(dt, 0, m, n, k, 1.0, A, m, "N", B, k, "N", 0.0, C, m)
+                return call
+            calls = {key: mk(key) for key in legs}
+            for c in calls.values():
+                c()
+            torch.cuda.synchronize()
+            est = 2.0 * m * n * k * prods / (peak * 0.25e12)
+            med = _median_times(torch, calls, 5, max(1, min(50, int(0.01 / est))))
+            row = {"form": name, "m": m, "n": n, "k": k,
+                   "split_k": hs["fused"].last_plan().split_k}
+            for key in legs:
+                row[key + "_us"] = round(med[key] * 1e3, 2)
+            row["fused_speedup_vs_pack_then_compute"] = round(med["pack_then_compute"] / med["fused"], 3)
+            log(f"[mx deep k] {row}")
+            out.append(row)
+            for h in hs.values():
+                h.close()
+            del A, B, C
+            torch.cuda.empty_cache()
+    return out
+
+
 def autograd_section(F, torch):
     """bfloat16 linear layer, forward Y = X W^T and backward dX = dY W, dW = dY^T X, all
     through the fused-pack GEMM: X 8192 x 4096 ~ N(0,1), W 4096 x 4096 ~ N(0, 1/4096),
@@ -636,6 +696,7 @@ def main():
         result["cache_and_graph"] = cache_section(F, torch)
     if not args.no_mx:
         result["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
+        result["mixed_precision_deep_k"] = mx_deep_k_section(F, torch)
     if not args.no_autograd:
         result["autograd"] = autograd_section(F, torch)
     if not args.no_batched:
