@@ -125,6 +125,28 @@ __device__ __forceinline__ uint32_t bf16_bits(float v)
 }
 __device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
 
+typedef float mx_f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 mx_bf2 __attribute__((ext_vector_type(2)));
+// Two binary32 values as one word of two bfloat16 (lo in the low half), round
+// to nearest even: one packed hardware conversion.
+__device__ __forceinline__ uint32_t bf16x2_bits(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(mx_f2{lo, hi}, mx_bf2));
+}
+// The bfloat16 split of two binary32 values (elements e and e + 1 of a run):
+// word t holds term t of both, x0 = bf16(x), x1 = bf16(x - x0) and, with three
+// terms, x2 = bf16(x - x0 - x1); each difference is exact in binary32.
+template <int PL>
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t (&h)[3])
+{
+    h[0] = bf16x2_bits(a, b);
+    const float ra = a - __uint_as_float(h[0] << 16), rb = b - __uint_as_float(h[0] & 0xFFFF0000u);
+    h[1] = bf16x2_bits(ra, rb);
+    h[2] = 0u;
+    if constexpr (PL == 3)
+        h[2] = bf16x2_bits(ra - __uint_as_float(h[1] << 16), rb - __uint_as_float(h[1] & 0xFFFF0000u));
+}
+
 // Registers of one K-major operand chunk (operand contiguous along k) on their
 // way from HBM to LDS (and, for a producer, to the pack buffer): thread b holds
 // rows x0 .. x0+NR-1 (x0 = NR*(b/8)) and k-values p0 .. p0+VK-1 (p0 =
@@ -161,24 +183,26 @@ struct Stage {
                 for (int u = 0; u < WPR; ++u) w[t][j][u] = 0;
     }
 
-    // Place source element (row j, k i) of the micro-block; w must start cleared.
+    static constexpr bool SPLIT = FORM == kMxX3 || FORM == kMxX3Fast;
+    // Place source element (row j, k i) of the micro-block (bfloat16 / E4M3);
+    // w must start cleared.
     __device__ __forceinline__ void put(int j, int i, S v)
     {
+        static_assert(!SPLIT, "split forms place pairs");
         if constexpr (FORM == kMxBF16) {
             w[0][j][i >> 1] |= (uint32_t)v << (16 * (i & 1));
-        } else if constexpr (FORM == kMxFP8) {
-            w[0][j][i >> 2] |= (uint32_t)v << (8 * (i & 3));
         } else {
-            const uint32_t h0 = bf16_bits(v);
-            const float r1 = v - bf16_float(h0);
-            const uint32_t h1 = bf16_bits(r1);
-            w[0][j][i >> 1] |= h0 << (16 * (i & 1));
-            w[1][j][i >> 1] |= h1 << (16 * (i & 1));
-            if constexpr (PL == 3) {
-                const float r2 = r1 - bf16_float(h1);
-                w[2][j][i >> 1] |= bf16_bits(r2) << (16 * (i & 1));
-            }
+            w[0][j][i >> 2] |= (uint32_t)v << (8 * (i & 3));
         }
+    }
+    // Split forms: elements (row j, k i) and (row j, k i + 1), i even, make
+    // word i/2 of row j in every plane.
+    __device__ __forceinline__ void put_pair(int j, int i, float a, float b)
+    {
+        uint32_t h[3];
+        split_pair<PL>(a, b, h);
+#pragma unroll
+        for (int t = 0; t < PL; ++t) w[t][j][i >> 1] = h[t];
     }
 
     // Unpacked source, every element of the micro-block present and vector
@@ -196,11 +220,8 @@ struct Stage {
                     for (int u = 0; u < 4; ++u) w[0][j][u] = v[u];
                 } else {
 #pragma unroll
-                    for (int t = 0; t < PL; ++t)
-#pragma unroll
-                        for (int u = 0; u < WPR; ++u) w[t][j][u] = 0;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) put(j, i, __uint_as_float(v[i]));
+                    for (int i = 0; i < 4; i += 2)
+                        put_pair(j, i, __uint_as_float(v[i]), __uint_as_float(v[i + 1]));
                 }
             }
         }
@@ -212,17 +233,30 @@ struct Stage {
     __device__ __forceinline__ void load_edge(const S* __restrict__ X, int64_t ld, int64_t MN,
                                               int64_t K, int64_t xc, int64_t pc, int tid)
     {
-        clear();
         const int64_t x0 = xc + x0_of(tid), p0 = pc + p0_of(tid);
+        if constexpr (SPLIT) {
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
+            for (int j = 0; j < NR; ++j)
 #pragma unroll
-            for (int i = 0; i < VK; ++i) {
-                const int64_t x = x0 + j, p = p0 + i;
-                S v = S(0);
-                if (x < MN && p < K) v = X[x * ld + p];
-                put(j, i, v);
-            }
+                for (int i = 0; i < VK; i += 2) {
+                    const int64_t x = x0 + j, p = p0 + i;
+                    float a = 0.f, b = 0.f;
+                    if (x < MN && p < K) a = X[x * ld + p];
+                    if (x < MN && p + 1 < K) b = X[x * ld + p + 1];
+                    put_pair(j, i, a, b);
+                }
+        } else {
+            clear();
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+#pragma unroll
+                for (int i = 0; i < VK; ++i) {
+                    const int64_t x = x0 + j, p = p0 + i;
+                    S v = S(0);
+                    if (x < MN && p < K) v = X[x * ld + p];
+                    put(j, i, v);
+                }
+        }
     }
 
     // Packed source: the chunk's planes, K-major; this thread's rows are
@@ -323,17 +357,10 @@ struct Stage<FORM, false, MT> {
         } else {
 #pragma unroll
             for (int e = 0; e < VE; e += 2) {
-                uint32_t h[3][2];
+                uint32_t h[3];
+                split_pair<PL>(__uint_as_float(src[e]), __uint_as_float(src[e + 1]), h);
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const float x = __uint_as_float(src[e + q]);
-                    h[0][q] = bf16_bits(x);
-                    const float r1 = x - bf16_float(h[0][q]);
-                    h[1][q] = bf16_bits(r1);
-                    h[2][q] = bf16_bits(r1 - bf16_float(h[1][q]));
-                }
-#pragma unroll
-                for (int t = 0; t < PL; ++t) w[t][v][e >> 1] = h[t][0] | (h[t][1] << 16);
+                for (int t = 0; t < PL; ++t) w[t][v][e >> 1] = h[t];
             }
         }
     }
