@@ -159,6 +159,15 @@ struct Stage {
     static constexpr int NR = G::NR;
     typedef typename Form<FORM>::S S;
     static constexpr int PL = G::PL, WPR = G::WPR, VK = G::VK, EB = G::EB, SB = G::SB;
+    static constexpr bool SPLIT = FORM == kMxX3 || FORM == kMxX3Fast;
+    // Two-term split: unpacked binary32 words stay raw until finish(), so the
+    // loads of the next chunk remain in flight across the current MFMAs; the
+    // four raw words of row j wait in w[0][j] and w[1][j] (no extra
+    // registers), and the caller knows (uniformly) which chunks came in raw.
+    // The three-term split converts at load time: deferring it measured
+    // slower for that form's packed path (its kernel is the most
+    // register- and schedule-bound).
+    static constexpr bool DEFER = FORM == kMxX3Fast;
     uint32_t w[PL][NR][WPR];
 
     __device__ __forceinline__ static int x0_of(int tid) { return NR * (tid / G::KGROUPS); }
@@ -171,7 +180,20 @@ struct Stage {
     }
     // Byte step from one chunk to the next along k.
     __device__ __forceinline__ static int64_t chunk_step(int64_t ldb) { return (int64_t)G::KT * SB; }
-    __device__ __forceinline__ void finish() {}
+    // Deferred forms: turn the raw binary32 words that load_full left into
+    // the packed planes (only for a chunk that came through load_full).
+    __device__ __forceinline__ void finish()
+    {
+        if constexpr (DEFER) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const float a = __uint_as_float(w[0][j][0]), b = __uint_as_float(w[0][j][1]),
+                            c = __uint_as_float(w[1][j][0]), d = __uint_as_float(w[1][j][1]);
+                put_pair(j, 0, a, b);
+                put_pair(j, 2, c, d);
+            }
+        }
+    }
 
     __device__ __forceinline__ void clear()
     {
@@ -183,7 +205,6 @@ struct Stage {
                 for (int u = 0; u < WPR; ++u) w[t][j][u] = 0;
     }
 
-    static constexpr bool SPLIT = FORM == kMxX3 || FORM == kMxX3Fast;
     // Place source element (row j, k i) of the micro-block (bfloat16 / E4M3);
     // w must start cleared.
     __device__ __forceinline__ void put(int j, int i, S v)
@@ -218,10 +239,15 @@ struct Stage {
                 if constexpr (FORM == kMxBF16 || FORM == kMxFP8) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) w[0][j][u] = v[u];
+                } else if constexpr (DEFER) {
+                    static_assert(WPR == 2 && PL >= 2, "raw words fit planes 0 and 1");
+                    w[0][j][0] = v[0];
+                    w[0][j][1] = v[1];
+                    w[1][j][0] = v[2];
+                    w[1][j][1] = v[3];
                 } else {
-#pragma unroll
-                    for (int i = 0; i < 4; i += 2)
-                        put_pair(j, i, __uint_as_float(v[i]), __uint_as_float(v[i + 1]));
+                    put_pair(j, 0, __uint_as_float(v[0]), __uint_as_float(v[1]));
+                    put_pair(j, 2, __uint_as_float(v[2]), __uint_as_float(v[3]));
                 }
             }
         }
@@ -333,11 +359,12 @@ struct Stage<FORM, false, MT> {
     static constexpr int WPV = VE * EB / 4;               // packed words per vector and plane
     static_assert(VT >= 1 && NP >= 1 && (WPV == 2 || WPV == 4), "MN-major staging shape");
     static constexpr bool SPLIT = FORM == kMxX3 || FORM == kMxX3Fast;
+    static constexpr bool DEFER = SPLIT;
     uint32_t w[PL][NV][WPV];
     // Split forms: unpacked binary32 words stay raw until finish(), so the
-    // loads of the next chunk remain in flight across the current MFMAs.
-    uint32_t raw[SPLIT ? NV : 1][4];
-    bool pending = false;
+    // loads of the next chunk remain in flight across the current MFMAs.  The
+    // four raw words of vector v wait in w[0][v] and w[1][v] (no extra
+    // registers).  The caller knows (uniformly) which chunks came in raw.
 
     __device__ __forceinline__ static int row_of(int v, int tid) { return 32 * (v / VT) + (tid >> 3); }
     __device__ __forceinline__ static int x_of(int v, int tid) { return VE * ((tid & 7) + 8 * (v % VT)); }
@@ -374,25 +401,27 @@ struct Stage<FORM, false, MT> {
             const u4 x = *reinterpret_cast<const u4a*>(src + (int64_t)(32 * (v / VT)) * ldb +
                                                        16 * 8 * (v % VT));
             if constexpr (SPLIT) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) raw[v][u] = x[u];
+                static_assert(WPV == 2 && PL >= 2, "raw words fit planes 0 and 1");
+                w[0][v][0] = x[0];
+                w[0][v][1] = x[1];
+                w[1][v][0] = x[2];
+                w[1][v][1] = x[3];
             } else {
                 const uint32_t a[4] = {x[0], x[1], x[2], x[3]};
                 put_vec(v, a);
             }
         }
-        if constexpr (SPLIT) pending = true;
     }
 
-    // Split forms: turn raw binary32 words into the packed planes (before the
-    // chunk is stored); a no-op otherwise or when the chunk came packed.
+    // Split forms: turn the raw binary32 words that load_full left into the
+    // packed planes (only for a chunk that came through load_full).
     __device__ __forceinline__ void finish()
     {
         if constexpr (SPLIT) {
-            if (pending) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) put_vec(v, raw[v]);
-                pending = false;
+            for (int v = 0; v < NV; ++v) {
+                const uint32_t a[4] = {w[0][v][0], w[0][v][1], w[1][v][0], w[1][v][1]};
+                put_vec(v, a);
             }
         }
     }
@@ -418,13 +447,11 @@ struct Stage<FORM, false, MT> {
             }
             put_vec(v, a);
         }
-        if constexpr (SPLIT) pending = false;
     }
 
     // Packed source (MN-major planes): element (x, p) of plane t at (p*MT + x)*EB.
     __device__ __forceinline__ void load_packed(const char* __restrict__ chunk, int tid)
     {
-        if constexpr (SPLIT) pending = false;
 #pragma unroll
         for (int t = 0; t < PL; ++t)
 #pragma unroll
@@ -816,19 +843,27 @@ gemm_mx_kernel(const MxParams P)
     unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_polls = 0;
     StA ra;
     StB rb;
+    auto count_chunk = [&]() {
+        if (P.do_stats && tid == 0) {
+            n_prod += (int)prodA + (int)prodB;
+            n_pk += (int)(wantA && apk) + (int)(wantB && bpk) + (consume ? 2 : 0);
+            n_unpk += (int)(wantA && !apk) + (int)(wantB && !bpk);
+        }
+    };
+    // Split forms: a chunk read by load_full sits in registers as raw binary32
+    // until put_chunks converts it; a_raw / b_raw say so (workgroup-uniform).
+    bool a_raw = false, b_raw = false;
     auto load_chunks = [&](int c) {
         const bool kin = c < nKfull;
+        a_raw = StA::DEFER && !apk && a_in && kin;
+        b_raw = StB::DEFER && !bpk && b_in && kin;
         if (apk) ra.load_packed(apanel + (int64_t)c * G::PACK_CHUNK, tid);
         else if (a_in && kin) ra.load_full(a_src + (int64_t)c * a_step, a_ldb);
         else ra.load_edge(reinterpret_cast<const S*>(P.A), P.a_ld, P.M, P.K, x0a, (int64_t)c * KT, tid);
         if (bpk) rb.load_packed(bpanel + (int64_t)c * G::PACK_CHUNK, tid);
         else if (b_in && kin) rb.load_full(b_src + (int64_t)c * b_step, b_ldb);
         else rb.load_edge(reinterpret_cast<const S*>(P.B), P.b_ld, P.N, P.K, x0b, (int64_t)c * KT, tid);
-        if (P.do_stats && tid == 0) {
-            n_prod += (int)prodA + (int)prodB;
-            n_pk += (int)(wantA && apk) + (int)(wantB && bpk) + (consume ? 2 : 0);
-            n_unpk += (int)(wantA && !apk) + (int)(wantB && !bpk);
-        }
+        count_chunk();
     };
 
     typedef Mma<FORM, MT> MM;
@@ -853,13 +888,35 @@ gemm_mx_kernel(const MxParams P)
             if (P.do_stats && tid == 0) ++n_polls;
         }
     };
+    // Each operand takes one of two complete paths (convert then store, or
+    // store), so no register value flows out of a conditional conversion.
     auto put_chunks = [&](int buf, int c) {
-        ra.finish();
-        rb.finish();
-        ra.store_lds(sA[buf], tid);
-        rb.store_lds(sB[buf], tid);
-        if (prodA) ra.store_pack(apanel + (int64_t)c * G::PACK_CHUNK, tid);
-        if (prodB) rb.store_pack(bpanel + (int64_t)c * G::PACK_CHUNK, tid);
+        // three-term split: one path (measured faster for this form)
+        if constexpr (FORM == kMxX3) {
+            if (a_raw) ra.finish();
+            if (b_raw) rb.finish();
+            ra.store_lds(sA[buf], tid);
+            rb.store_lds(sB[buf], tid);
+            if (prodA) ra.store_pack(apanel + (int64_t)c * G::PACK_CHUNK, tid);
+            if (prodB) rb.store_pack(bpanel + (int64_t)c * G::PACK_CHUNK, tid);
+            return;
+        }
+        if (a_raw) {
+            ra.finish();
+            ra.store_lds(sA[buf], tid);
+            if (prodA) ra.store_pack(apanel + (int64_t)c * G::PACK_CHUNK, tid);
+        } else {
+            ra.store_lds(sA[buf], tid);
+            if (prodA) ra.store_pack(apanel + (int64_t)c * G::PACK_CHUNK, tid);
+        }
+        if (b_raw) {
+            rb.finish();
+            rb.store_lds(sB[buf], tid);
+            if (prodB) rb.store_pack(bpanel + (int64_t)c * G::PACK_CHUNK, tid);
+        } else {
+            rb.store_lds(sB[buf], tid);
+            if (prodB) rb.store_pack(bpanel + (int64_t)c * G::PACK_CHUNK, tid);
+        }
     };
 
     load_chunks(q0);
@@ -910,17 +967,42 @@ gemm_mx_kernel(const MxParams P)
         for (int q = 0; q + 1 < nK; ++q) kstep(q, std::true_type{});
         kstep(nK - 1, std::false_type{});
     } else {
-        __syncthreads();
-        for (int q = q0; q < q1; ++q) {
-            const int cur = (q - q0) & 1;
-            const bool more = q + 1 < q1;
-            poll_issue(q);
-            if (more) load_chunks(q + 1);
-            MM::template step<AKC, BKC>(sA[cur], sB[cur], wm * WT, wn * WT, lane, acc);
-            if (more) put_chunks(cur ^ 1, q + 1);
-            poll_finish();
+        // A tile that reads both operands packed from its first chunk on (the
+        // pack-then-compute baseline, or a later pass that finds both panels
+        // published) has nothing to convert, store or poll: it runs a copy of
+        // the loop compiled for that case alone, so the general loop's
+        // conversion code does not shape its schedule.
+        auto loop = [&](auto all_packed_c) {
+            constexpr bool ALL_PACKED = decltype(all_packed_c)::value;
             __syncthreads();
-        }
+            for (int q = q0; q < q1; ++q) {
+                const int cur = (q - q0) & 1;
+                const bool more = q + 1 < q1;
+                if constexpr (ALL_PACKED) {
+                    if (more) {
+                        ra.load_packed(apanel + (int64_t)(q + 1) * G::PACK_CHUNK, tid);
+                        rb.load_packed(bpanel + (int64_t)(q + 1) * G::PACK_CHUNK, tid);
+                        count_chunk();
+                    }
+                    MM::template step<AKC, BKC>(sA[cur], sB[cur], wm * WT, wn * WT, lane, acc);
+                    if (more) {
+                        ra.store_lds(sA[cur ^ 1], tid);
+                        rb.store_lds(sB[cur ^ 1], tid);
+                    }
+                } else {
+                    poll_issue(q);
+                    if (more) load_chunks(q + 1);
+                    MM::template step<AKC, BKC>(sA[cur], sB[cur], wm * WT, wn * WT, lane, acc);
+                    if (more) put_chunks(cur ^ 1, q + 1);
+                    poll_finish();
+                }
+                __syncthreads();
+            }
+        };
+        // apk and bpk imply that this workgroup produces neither panel; the
+        // three-term split keeps the one loop (measured faster for that form)
+        if (FORM != kMxX3 && apk && bpk) loop(std::true_type{});
+        else loop(std::false_type{});
     }
 
     if (producer) {
