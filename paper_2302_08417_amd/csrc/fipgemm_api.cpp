@@ -309,7 +309,14 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
             // the launch order and packs an operand when most of its panels are
             // read again in a later round; with a single round nobody could
             // reuse a pack.
-            const bool later_passes = pl->tilesKM * pl->tilesKN * pl->split > resident;
+            // The split forms need more than 4 rounds: each XCD produces its own
+            // copy of every panel it reads, a producer costs about three packed
+            // tiles, and with few rounds that is not repaid (2-term split at
+            // 4096^3, 4 rounds: 932 us packed, 773 unpacked; 8192^3, 16 rounds:
+            // 6.5 ms packed, 7.4 unpacked).
+            const bool split_form = form == fip::kMxX3 || form == fip::kMxX3Fast;
+            const bool later_passes =
+                pl->tilesKM * pl->tilesKN * pl->split > (split_form ? 4 : 1) * resident;
             double fa = 0.0, fb = 0.0;
             if (later_passes)
                 later_round_reuse(pl->tilesKM, pl->tilesKN, pl->order, resident / fip::kCopies,

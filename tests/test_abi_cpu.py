@@ -294,13 +294,20 @@ def test_mx_tile_choice(h):
 
 def test_mx_auto_pack_rule(h):
     """AUTO never packs bfloat16 / E4M3 operands (unpacked reads are as fast); the split forms
-    follow the reuse rule (an unpacked read would redo the split)."""
+    follow the reuse rule (an unpacked read would redo the split) once a launch runs more than
+    4 rounds of workgroups."""
     assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO) == 0
     for dtype in (F.FIP_BF16, F.FIP_E4M3):
         rc, p = F.fip_plan(h, dtype, 0, 16384, 16384, 1024, "N", "N")
         assert rc == 0 and (p.pack_a, p.pack_b) == (0, 0) and p.workspace_bytes == 0
     for dtype in (F.FIP_BF16X3, F.FIP_BF16X3_FAST):
         rc, p = F.fip_plan(h, dtype, 0, 16384, 16384, 1024, "N", "N")
+        assert rc == 0 and p.pack_a == 1
+        # 4096^2: 1024 tiles = 4 rounds of 256 resident workgroups: not enough to repay
+        # the per-XCD producer copies; 8192^2 (16 rounds) packs
+        rc, p = F.fip_plan(h, dtype, 0, 4096, 4096, 4096, "N", "N")
+        assert rc == 0 and (p.pack_a, p.pack_b) == (0, 0)
+        rc, p = F.fip_plan(h, dtype, 0, 8192, 8192, 8192, "N", "N")
         assert rc == 0 and p.pack_a == 1
 
 
