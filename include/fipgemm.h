@@ -123,9 +123,12 @@ enum {
     FIP_PACK_AUTO = 0,         /* paper Sec. 3.3 reuse table, applied when the
                                   launch has more tiles than fit on the device
                                   at once (only then can a later pass reuse a
-                                  pack without waiting for it); bfloat16 and
-                                  E4M3 operands are never packed under AUTO
-                                  (their unpacked reads are as fast) */
+                                  pack without waiting for it), more than 4
+                                  such rounds for the bfloat16 split forms of
+                                  binary32 (their per-XCD producer copies are
+                                  not repaid in fewer); bfloat16 and E4M3
+                                  operands are never packed under AUTO (their
+                                  unpacked reads are as fast) */
     FIP_PACK_ALL = 1,          /* pack both operands whatever the shape */
     FIP_PACK_NONE = 2,         /* never pack (the unpacked "SUP" path, Sec. 2.3) */
     FIP_PACK_CONSUME_ONLY = 3, /* read only packed panels written beforehand by
