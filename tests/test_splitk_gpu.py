@@ -1,8 +1,11 @@
-"""GPU parity of the split-k path (FP64 / FP32): k cut into slices computed by separate
-workgroups, their partial products summed in slice order by a second kernel.
+"""GPU parity of the split-k path (FP64 / FP32, and the mixed-precision forms on the 128 x 128
+tile): k cut into slices computed by separate workgroups, their partial products summed in
+slice order by a second kernel.
 
-Checked against the oracle within 4 k u max D, and for bit-identical results across pack
-policies, tile classes (at one split), repeated calls and stale workspaces."""
+Checked against the oracle within 4 k u max D (the mixed forms: check_mx's bound on the
+values the stored operands stand for), and for bit-identical results across pack policies,
+tile classes (at one split), repeated calls and stale workspaces; packed chunks of every
+claimed (panel, k-slice) byte-exact against the oracle's pack."""
 import numpy as np
 import pytest
 
