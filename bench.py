@@ -277,6 +277,24 @@ def mx_section(F, torch, sizes):
                 row[key + "_tflops"] = round(fl / (med[pol] * 1e-3) / 1e12, 1)
             row["mfma_peak_tflops"] = peak
             row["fused_pct_mfma_peak"] = round(100 * row["fused_tflops"] * prods / peak, 2)
+            if dt == F.FIP_E4M3:
+                # fip_quantize_fp8 of the binary32 operands (per row of op(A), per column of
+                # op(B); four launches each), timed on its own
+                hq = hs[F.FIP_PACK_AUTO]
+                Qa = torch.empty(n * n, dtype=torch.uint8, device="cuda")
+                Qb = torch.empty_like(Qa)
+                qsa = torch.empty(n, device="cuda")
+                qsb = torch.empty(n, device="cuda")
+
+                def quant():
+                    hq.quantize_fp8(0, n, n, A32, n, 0, Qa, n, qsa)
+                    hq.quantize_fp8(0, n, n, B32, n, 1, Qb, n, qsb)
+                quant()
+                torch.cuda.synchronize()
+                tq = _median_times(torch, {"q": quant}, 5, 5)["q"]
+                row["quantize_both_us"] = round(tq * 1e3, 2)
+                row["quantize_gbs"] = round(2 * n * n * (4 + 4 + 1) / (tq * 1e-3) / 1e9, 1)
+                del Qa, Qb
             row["err_vs_fp64_oracle_rel_to_max_absAB"] = float(f"{err:.3e}")
             log(f"[mx] {row}")
             out.append(row)
@@ -473,6 +491,28 @@ def skinny_section(F, torch, dtypes):
     return out
 
 
+LDIM_SIZES = [16, 32, 64, 128, 256, 512, 1024, 2000]
+
+
+def ldim_section(F, torch):
+    """The paper's second sweep (Sec. 4): m = n = k <= 2000 with every leading dimension 2000,
+    column-major NN, binary64 and binary32; fused vs pack-then-compute vs unpacked."""
+    from paper_2302_08417_amd import synth
+    out = []
+    for sdt in ("f64", "f32"):
+        for s in LDIM_SIZES:
+            g = Gemm(F, torch, s, sdt, seed=synth.BASE_SEED + 29 * s, ld_pad=2000 - s)
+            row = {"dtype": sdt, "m": s, "n": s, "k": s, "ld": 2000}
+            _time_row(F, torch, g, row, rounds=5, batch_s=0.003)
+            row["fused_pct_peak"] = round(100 * row["fused_gflops"] / (PEAK_TFLOPS[sdt] * 1e3), 2)
+            log(f"[ldim2000] {row}")
+            out.append(row)
+            g.release()
+            del g
+        torch.cuda.empty_cache()
+    return out
+
+
 def plain_dgemm_section(F, torch):
     """C := A B + C, m = n = k = 256, column-major NN, alpha = beta = 1 (FP64)."""
     from paper_2302_08417_amd import synth
@@ -486,8 +526,9 @@ def plain_dgemm_section(F, torch):
     return row
 
 
-def cpu_baseline(n, target_s=12.0):
-    """The oracle, as it stands, on a column sample of the headline workload."""
+def cpu_oracle_rate(n, target_s):
+    """GFLOP/s of the oracle, as it stands, on a column sample of the m = n = k = n binary64
+    workload grown until it takes about target_s; returns (GFLOP/s, columns, seconds, threads)."""
     import numpy as np
     import oracle
     from paper_2302_08417_amd import synth
@@ -502,16 +543,31 @@ def cpu_baseline(n, target_s=12.0):
         oracle.gemm(0, n, cols, n, c.alpha, A, c.lda, "N", B, c.ldb, "N", c.beta, C, c.ldc)
         return time.perf_counter() - t
 
-    cols = 4
+    cols = 1
     t = run(cols)
     while t < 0.5 * target_s and cols < n:  # grow the sample until it takes about target_s
         cols = int(max(cols + 1, min(n, cols * target_s / max(t, 1e-3))))
         t = run(cols)
-    gf = 2.0 * n * cols * n / t / 1e9
-    return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"binary64 oracle (triple loop, ascending-k sums, plus the |A||B| bound) on "
-                      f"C[:, :{cols}] of the m=n=k={n} workload ({t:.1f} s)"}
+    return 2.0 * n * cols * n / t / 1e9, cols, t, oracle.num_threads()
+
+
+def cpu_baseline(n, target_s=10.0, one_thread_s=6.0):
+    """The oracle timed on the host: all the threads OpenMP gives it, and one thread (in a child
+    process started with OMP_NUM_THREADS=1, so the setting cannot leak into this one)."""
+    import subprocess
+    gf, cols, t, threads = cpu_oracle_rate(n, target_s)
+    res = {"value": round(gf, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"binary64 oracle (triple loop, ascending-k sums, plus the |A||B| bound) on "
+                     f"C[:, :{cols}] of the m=n=k={n} workload ({t:.1f} s)",
+           "host_cpus": len(os.sched_getaffinity(0))}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    p = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", str(n),
+                        str(one_thread_s)], env=env, capture_output=True, text=True, timeout=300)
+    if p.returncode == 0 and p.stdout.strip():
+        leg = json.loads(p.stdout.strip().splitlines()[-1])
+        res["one_thread"] = {"value": leg["gflops"], "cores": leg["threads"],
+                             "sample": f"C[:, :{leg['cols']}] ({leg['seconds']:.1f} s)"}
+    return res
 
 
 def cache_section(F, torch):
@@ -581,6 +637,42 @@ def cache_section(F, torch):
     return {"cold": cold, "graph_replay": graph}
 
 
+SUMMARY_MAX_BYTES = 2000
+
+
+def compact_summary(result, full):
+    """Short per-section summaries for the final stdout line (the full rows go to the results
+    file and to stderr)."""
+    s = {}
+    if "sweep" in full:
+        rows = full["sweep"] + full["skinny"] + full.get("ldim2000", [])
+        sp = [r["fused_speedup_vs_pack_then_compute"] for r in rows]
+        s["sweep_summary"] = {
+            "rows": len(rows),
+            "rows_fused_faster_than_pack_then_compute": sum(x > 1.0 for x in sp),
+            "min_fused_speedup": min(sp), "median_fused_speedup": sorted(sp)[len(sp) // 2],
+            "fused_pct_peak_nn_col": {
+                f"{r['dtype']}_{r['m']}": r["fused_pct_peak"] for r in full["sweep"]
+                if r["m"] >= 4096 and r["layout"] == "col" and r["trans"] == "NN"
+                and r["ld_pad"] == 0}}
+    if "mixed_precision" in full:
+        big = max(r["m"] for r in full["mixed_precision"])
+        s["mixed_precision"] = {
+            r["form"]: {"n": big, "pct_peak": r["fused_pct_mfma_peak"],
+                        "vs_ptc": round(r["pack_then_compute_us"] / r["fused_us"], 3)}
+            for r in full["mixed_precision"] if r["m"] == big}
+    if "autograd" in full:
+        s["autograd"] = {k: full["autograd"][k] for k in ("ms_per_step", "pct_bf16_mfma_peak")}
+    if "batched" in full:
+        s["batched"] = {k: full["batched"][k] for k in ("eager_us", "graph_us",
+                                                         "pct_hbm_peak_graph")}
+    for key, val in s.items():
+        trial = dict(result, **{key: val})
+        if len(json.dumps(trial)) <= SUMMARY_MAX_BYTES:
+            result = trial
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -597,6 +689,12 @@ def main():
     ap.add_argument("--mx-sizes", default="1024,4096,16384")
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--results", default=os.path.join("gpurun_out", "bench_full.json"),
+                    help="file that receives every section's rows (the stdout line carries\n"
+                         "only their summaries); empty string: do not write it")
+    ap.add_argument("--cpu-leg", nargs=2, default=None, metavar=("N", "SECONDS"),
+                    help="no GPU work: time the oracle on a column sample of the N^3 workload\n"
+                         "for about SECONDS and print one JSON line (used for the one-thread leg)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), to "
                          "calibrate HBM byte counters against a kernel of known traffic")
@@ -609,6 +707,11 @@ def main():
 
     if args.traffic_summary:
         write_traffic_summary(args, *args.traffic_summary)
+        return
+    if args.cpu_leg:
+        gf, cols, t, threads = cpu_oracle_rate(int(args.cpu_leg[0]), float(args.cpu_leg[1]))
+        print(json.dumps({"gflops": round(gf, 3), "cols": cols, "seconds": round(t, 2),
+                          "threads": threads}), flush=True)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -679,32 +782,31 @@ def main():
         },
     }
 
+    full = {}
     if not args.no_sweep:
-        result["plain_dgemm_256"] = plain_dgemm_section(F, torch)
+        full["plain_dgemm_256"] = plain_dgemm_section(F, torch)
         sizes = [int(x) for x in args.sweep_sizes.split(",")] if args.sweep_sizes else SWEEP_SIZES
-        result["sweep"] = sweep_section(F, torch, sizes, args.sweep_dtypes.split(","))
-        result["skinny"] = skinny_section(F, torch, args.sweep_dtypes.split(","))
-        rows = result["sweep"] + result["skinny"]
-        sp = [r["fused_speedup_vs_pack_then_compute"] for r in rows]
-        result["sweep_summary"] = {
-            "rows": len(rows),
-            "rows_fused_faster_than_pack_then_compute": sum(x > 1.0 for x in sp),
-            "min_fused_speedup": min(sp), "median_fused_speedup": sorted(sp)[len(sp) // 2]}
-        log(f"[bench] sweep summary {result['sweep_summary']}")
-
-    if not args.no_sweep:
-        result["cache_and_graph"] = cache_section(F, torch)
+        full["sweep"] = sweep_section(F, torch, sizes, args.sweep_dtypes.split(","))
+        full["skinny"] = skinny_section(F, torch, args.sweep_dtypes.split(","))
+        full["ldim2000"] = ldim_section(F, torch)
+        full["cache_and_graph"] = cache_section(F, torch)
     if not args.no_mx:
-        result["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
-        result["mixed_precision_deep_k"] = mx_deep_k_section(F, torch)
+        full["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
+        full["mixed_precision_deep_k"] = mx_deep_k_section(F, torch)
     if not args.no_autograd:
-        result["autograd"] = autograd_section(F, torch)
+        full["autograd"] = autograd_section(F, torch)
     if not args.no_batched:
-        result["batched"] = batched_section(F, torch)
+        full["batched"] = batched_section(F, torch)
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(n if dt == "f64" else n)
+        result["cpu_baseline"] = cpu_baseline(n)
+    if args.results:
+        os.makedirs(os.path.dirname(os.path.abspath(args.results)), exist_ok=True)
+        with open(args.results, "w") as f:
+            json.dump(dict(result, sections=full), f, indent=1)
+        log(f"[bench] every section's rows: {args.results}")
+    result = compact_summary(result, full)
     print(json.dumps(result), flush=True)
 
 

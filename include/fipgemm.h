@@ -117,6 +117,11 @@ enum {
     /* Read only: the hipError_t of the last launch that failed on this handle
        (a call returning FIP_ERR_LAUNCH), 0 if none. */
     FIP_ATTR_LAST_HIP_ERROR = 12,
+    /* Read only, batched calls: 1 + the largest index of a problem that the
+       batched calls since the last read skipped because a device leading
+       dimension was too small or a matrix spans 2 GiB or more (0: none).
+       Reading it waits for the handle's stream and resets it to 0. */
+    FIP_ATTR_VB_STATUS = 13,
 };
 
 enum {
@@ -312,8 +317,11 @@ int fip_quantize_fp8(fip_handle_t handle, int layout, int64_t rows, int64_t cols
  *     them; a batch with the same shapes reuses the plan uploaded by the
  *     previous call).
  *   A, B, C: DEVICE arrays of count device pointers; lda, ldb, ldc: DEVICE
- *     arrays of count leading dimensions (not validated: they never reach the
- *     host).  All matrices in `layout`, C distinct from A and B.
+ *     arrays of count leading dimensions.  They never reach the host, so the
+ *     kernel checks them: a problem whose leading dimension is below the
+ *     extent it strides over (as in fip_sgemm), or one of whose matrices spans
+ *     2 GiB or more, is skipped (its C is not written) and reported through
+ *     FIP_ATTR_VB_STATUS.  All matrices in `layout`, C distinct from A and B.
  *   flags: 0, or FIP_VB_GRAPH: run the batch as a HIP graph, instantiated on
  *     the first call and replayed while the call repeats with the same shapes,
  *     pointer arrays, alpha, beta, workspace and stream.

@@ -22,13 +22,29 @@ from . import fipgemm as F
 
 ROW = F.FIP_ROW_MAJOR
 _local = threading.local()
+_policy = F.FIP_PACK_AUTO
+
+
+def set_pack_policy(policy):
+    """Packing policy (FIP_PACK_*) of the library handles this module uses (default AUTO)."""
+    global _policy
+    _policy = policy
+    for h in getattr(_local, "handles", {}).values():
+        h.set_attr(F.FIP_ATTR_PACK_POLICY, policy)
 
 
 def _handle():
-    h = getattr(_local, "handle", None)
+    """The calling thread's library handle for the current torch stream.  A handle owns one
+    workspace (pack panels, flags, split partials), so calls on different streams must not
+    share one: each (device, stream) gets its own."""
+    s = torch.cuda.current_stream()
+    handles = getattr(_local, "handles", None)
+    if handles is None:
+        handles = _local.handles = {}
+    key = (s.device.index, s.cuda_stream)
+    h = handles.get(key)
     if h is None:
-        h = F.Handle(policy=F.FIP_PACK_AUTO)
-        _local.handle = h
+        h = handles[key] = F.Handle(policy=_policy)
     return h
 
 

@@ -36,6 +36,25 @@ __device__ __forceinline__ void wait_all_memory()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// The publish protocol of a packed panel (paper Sec. 3.5: the one synchronisation).
+// Producer: every thread waits for its pack stores (wait_all_memory), the
+// workgroup meets at a barrier, then one thread stores the epoch into the
+// panel's flag with release semantics at agent scope.  Consumer: a relaxed
+// agent-scope flag load; the first time a wave sees the epoch it issues one
+// acquire fence at agent scope before its first load of the packed copy.
+// Producer and consumers of a copy run on one XCD, but the HIP memory model
+// has no XCD scope, so both sides use agent scope (an L2 write-back on
+// publish, an L1 invalidate on acquire: once per panel and once per wave).
+__device__ __forceinline__ void publish_flag(uint64_t* flag, uint64_t epoch)
+{
+    __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t peek_flag(const uint64_t* flag)
+{
+    return __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void acquire_packed() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Workgroup -> tile (also replayed on the host by the planner to see which
 // panels a later round reads).  Workgroups are dispatched round-robin over the 8 XCDs,
 // so w % 8 is (normally) the XCD.  Each XCD gets one contiguous run of a

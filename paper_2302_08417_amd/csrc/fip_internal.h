@@ -137,6 +137,7 @@ struct VbItem {
     uint16_t tm, tn;
 };
 struct VbLaunchDesc {
+    unsigned long long* status;    // device: 1 + largest index of a skipped problem (0: none)
     const VbProblem* probs;        // device
     const VbItem* items;           // device: XCD x's items at [xcd_off[x], xcd_off[x+1])
     int64_t total;                 // number of items

@@ -654,7 +654,8 @@ uint64_t vb_signature(int layout, int64_t count, const int32_t* m, const int32_t
 
 int64_t vb_tiles(int64_t M, int64_t N, int mt) { return cdiv(M, mt) * cdiv(N, mt); }
 
-// Workspace bytes: a 256-byte reserved header, the problem table, and the
+// Workspace bytes: a 256-byte header (its first 8 bytes: the skipped-problem
+// status word, see FIP_ATTR_VB_STATUS), the problem table, and the
 // item list of the smallest tile class for every problem (the most items any
 // split yields).
 int64_t vb_workspace_bytes(int layout, int64_t count, const int32_t* m, const int32_t* n,
@@ -756,6 +757,9 @@ int vb_upload(fip_handle_s* h, int layout, int64_t count, const int32_t* m, cons
     v.xcd_off[fip::kCopies] = (int64_t)v.items.size();
     if (hipStreamSynchronize(h->stream) != hipSuccess) return FIP_ERR_LAUNCH;
     char* ws = static_cast<char*>(h->ws);
+    const unsigned long long zero = 0;   // the header's skipped-problem status word
+    if (hipMemcpy(ws, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
+        return FIP_ERR_LAUNCH;
     if (count > 0 &&
         hipMemcpy(ws + off_probs, v.probs.data(), count * sizeof(fip::VbProblem),
                   hipMemcpyHostToDevice) != hipSuccess)
@@ -781,6 +785,7 @@ fip::VbLaunchDesc vb_desc(const fip_handle_s* h, float alpha, const float* const
     const VbState& v = *h->vb;
     char* ws = static_cast<char*>(h->ws);
     fip::VbLaunchDesc d{};
+    d.status = reinterpret_cast<unsigned long long*>(ws);
     d.probs = reinterpret_cast<const fip::VbProblem*>(ws + v.off_probs);
     d.items = reinterpret_cast<const fip::VbItem*>(ws + v.off_items);
     d.total = v.total;
@@ -913,6 +918,19 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_VB_GRID: *value = fip::vbatched_grid(); return 0;
     case FIP_ATTR_MX_TILE: *value = handle->mx_tile; return 0;
     case FIP_ATTR_SPLIT_K: *value = handle->split_k; return 0;
+    case FIP_ATTR_VB_STATUS: {
+        *value = 0;
+        VbState* v = handle->vb;
+        if (v == nullptr || v->ws == nullptr || v->ws != handle->ws) return 0;
+        unsigned long long st = 0;
+        const unsigned long long zero = 0;
+        if (hipStreamSynchronize(handle->stream) != hipSuccess ||
+            hipMemcpy(&st, v->ws, sizeof st, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(v->ws, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
+            return FIP_ERR_LAUNCH;
+        *value = (int64_t)st;
+        return 0;
+    }
     default: return 2;
     }
 }

@@ -29,6 +29,7 @@ namespace {
 constexpr int VB_NTHR = 64;    // one wave per workgroup: a wave owns whole tiles
 
 struct VbParams {
+    unsigned long long* status;    // 1 + the largest index of a problem that was skipped
     const VbProblem* probs;
     const VbItem* items;
     int64_t total;
@@ -43,19 +44,36 @@ struct VbParams {
 // A matrix viewed as a buffer resource: loads at byte offsets at or beyond
 // `bytes` return zeros without touching memory, so fringe lanes need no
 // branch (a branch per lane would also make the compiler wait for every
-// outstanding load before the MFMAs).  Offsets are 32-bit: each operand's
-// storage must stay below 2 GiB.
+// outstanding load before the MFMAs).  Offsets are 32-bit: a problem whose
+// storage reaches 2 GiB is not run (vb_valid).
 struct Mat {
     __amdgpu_buffer_rsrc_t r;
     uint32_t bytes;
 };
 constexpr uint32_t kOob = 0x80000000u;   // an offset past any operand
 
+// Bytes spanned by an MN x K operand (kc: K-major, X[x*ld + p]; else X[x + p*ld]).
+__device__ __forceinline__ int64_t mat_span(int64_t ld, int64_t MN, int64_t K, bool kc)
+{
+    if (MN <= 0 || K <= 0) return 0;
+    return (kc ? (MN - 1) * ld + K : (K - 1) * ld + MN) * (int64_t)sizeof(float);
+}
+// A problem the kernel can run: every leading dimension at least the extent it strides over,
+// and every matrix it reads or writes below kMaxSpan bytes (32-bit buffer offsets).
+constexpr int64_t kMaxSpan = 0x7FFFFFF0;
+__device__ __forceinline__ bool vb_valid(int64_t lda, int64_t ldb, int64_t ldc, int M, int N,
+                                         int K, bool akc, bool bkc)
+{
+    if (ldc < (M > 1 ? M : 1) || mat_span(ldc, M, N, false) > kMaxSpan) return false;
+    if (K == 0) return true;   // A and B are not read
+    const int64_t need_a = akc ? K : M, need_b = bkc ? K : N;
+    return lda >= (need_a > 1 ? need_a : 1) && ldb >= (need_b > 1 ? need_b : 1) &&
+           mat_span(lda, M, K, akc) <= kMaxSpan && mat_span(ldb, N, K, bkc) <= kMaxSpan;
+}
+
 __device__ __forceinline__ Mat make_mat(const float* X, int64_t ld, int64_t MN, int64_t K, bool kc)
 {
-    int64_t n = 0;
-    if (MN > 0 && K > 0) n = (kc ? (MN - 1) * ld + K : (K - 1) * ld + MN) * (int64_t)sizeof(float);
-    if (n > (int64_t)0x7FFFFFF0) n = 0x7FFFFFF0;
+    const int64_t n = mat_span(ld, MN, K, kc);   // <= kMaxSpan (vb_valid)
     Mat m;
     m.bytes = (uint32_t)n;
     m.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X), (short)0, (int)n, 0x00020000);
@@ -64,7 +82,7 @@ __device__ __forceinline__ Mat make_mat(const float* X, int64_t ld, int64_t MN, 
 
 // One operand's fragment rows for a wave: for each 16-row block a, lane
 // (r, q) reads row x = x0 + 16a + r at k = 16j + 4q + t (t = 0..3) of k-block
-// j.  Byte offsets are 32-bit (operands below 2 GiB), set up once per tile and
+// j.  Byte offsets are 32-bit (operands below 2 GiB, vb_valid), set up once per tile and
 // advanced by a constant per k-block; lanes whose row or k lies outside the
 // operand read at kOob and get zeros from the buffer unit, so the loads need
 // no branch (a branch per lane would also make the compiler wait for every
@@ -282,12 +300,17 @@ __global__ void __launch_bounds__(VB_NTHR, FIP_VB_WAVES_PER_EU) vbatched_kernel(
         const int64_t ldb = sw ? P.lda[it.prob] : P.ldb[it.prob];
         const int kmaj = (pr.flags & kVbAKmajor ? 1 : 0) | (pr.flags & kVbBKmajor ? 2 : 0);
         const int K = P.no_ab ? 0 : pr.K;
-        if (pr.cls == 1)
-            vb_dispatch<32>(kmaj, A, lda, B, ldb, P.C[it.prob], P.ldc[it.prob], pr.M, pr.N, K,
-                            it.tm, it.tn, P.alpha, P.beta);
+        const int64_t ldc = P.ldc[it.prob];
+        if (!vb_valid(lda, ldb, ldc, pr.M, pr.N, K, kmaj & 1, kmaj & 2)) {
+            // leading dimensions come from device arrays the host never sees: a problem
+            // that would read or write outside its matrices is skipped and reported
+            if ((threadIdx.x & 63) == 0) atomicMax(P.status, (unsigned long long)it.prob + 1);
+        } else if (pr.cls == 1)
+            vb_dispatch<32>(kmaj, A, lda, B, ldb, P.C[it.prob], ldc, pr.M, pr.N, K, it.tm,
+                            it.tn, P.alpha, P.beta);
         else
-            vb_dispatch<16>(kmaj, A, lda, B, ldb, P.C[it.prob], P.ldc[it.prob], pr.M, pr.N, K,
-                            it.tm, it.tn, P.alpha, P.beta);
+            vb_dispatch<16>(kmaj, A, lda, B, ldb, P.C[it.prob], ldc, pr.M, pr.N, K, it.tm,
+                            it.tn, P.alpha, P.beta);
         if (next >= end) break;
         item = next;
         it = it_n;
@@ -299,6 +322,7 @@ __global__ void __launch_bounds__(VB_NTHR, FIP_VB_WAVES_PER_EU) vbatched_kernel(
 VbParams make_vb_params(const VbLaunchDesc& d)
 {
     VbParams P{};
+    P.status = d.status;
     P.probs = d.probs; P.items = d.items; P.total = d.total;
     for (int i = 0; i <= kCopies; ++i) P.xcd_off[i] = d.xcd_off[i];
     P.A = d.A; P.lda = d.lda; P.B = d.B; P.ldb = d.ldb; P.C = d.C; P.ldc = d.ldc;

@@ -121,9 +121,6 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     const int64_t bslot = ((int64_t)copy * P.tilesN + tn) * S + slice;
     uint64_t* adone = useA ? P.aflag + aslot : nullptr;
     uint64_t* bdone = useB ? P.bflag + bslot : nullptr;
-    auto load_flag = [&](const uint64_t* f) -> uint64_t {
-        return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    };
 
     // First touch claims a panel (Sec. 3.2: the first pass packs it).  The role
     // must be workgroup-uniform because every thread stores its share of each
@@ -151,9 +148,10 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     constexpr int REPOLL = 16;
     bool apk = consume, bpk = consume;
     {
-        const uint64_t fa = wantA ? load_flag(adone) : 0, fb = wantB ? load_flag(bdone) : 0;
+        const uint64_t fa = wantA ? peek_flag(adone) : 0, fb = wantB ? peek_flag(bdone) : 0;
         apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
         bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+        if ((wantA && apk) || (wantB && bpk)) acquire_packed();
     }
 
     unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_polls = 0;
@@ -216,8 +214,8 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         const bool poll = ((wantA && !apk) || (wantB && !bpk)) && q % REPOLL == REPOLL - 1;
         uint64_t fa = 0, fb = 0;
         if (poll) {
-            if (wantA && !apk) fa = load_flag(adone);
-            if (wantB && !bpk) fb = load_flag(bdone);
+            if (wantA && !apk) fa = peek_flag(adone);
+            if (wantB && !bpk) fb = peek_flag(bdone);
         }
         if (more) load_chunks(q + 1);
         // MFMAs on chunk q.  Fragment element (row x, k-row kr) of either
@@ -243,22 +241,24 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
             if (prodB) rb.store_pack(bpanel + (int64_t)(q + 1) * KT * NT, tid);
         }
         if (poll) {  // takes effect from chunk q+2 on
-            apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
-            bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+            const bool na = !apk && wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0;
+            const bool nb = !bpk && wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0;
+            if (na || nb) acquire_packed();
+            apk = apk || na;
+            bpk = bpk || nb;
             if (P.do_stats && tid == 0) ++n_polls;
         }
         __syncthreads();
     }
 
     // The producer publishes its panel once every pack store of it has
-    // completed (the XCD's L2 has acknowledged them; consumers of this copy
-    // run on the same XCD and read through that L2).
+    // completed (see publish_flag).
     if (producer) {
         wait_all_memory();
         __syncthreads();
         if (tid == 0 && !P.no_publish) {
-            if (prodA) __hip_atomic_store(adone, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (prodB) __hip_atomic_store(bdone, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prodA) publish_flag(adone, epoch);
+            if (prodB) publish_flag(bdone, epoch);
         }
     }
 

@@ -811,9 +811,6 @@ gemm_mx_kernel(const MxParams P)
     const int64_t bslot = ((int64_t)copy * P.tilesN + tn) * NS + slice;
     uint64_t* adone = useA ? P.aflag + aslot : nullptr;
     uint64_t* bdone = useB ? P.bflag + bslot : nullptr;
-    auto load_flag = [&](const uint64_t* f) -> uint64_t {
-        return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    };
 
     // First touch claims the panel (Sec. 3.2); thread 0 claims, the role is
     // broadcast because every thread stores its share of each packed chunk.
@@ -835,9 +832,10 @@ gemm_mx_kernel(const MxParams P)
     constexpr int REPOLL = 8;
     bool apk = consume, bpk = consume;
     {
-        const uint64_t fa = wantA ? load_flag(adone) : 0, fb = wantB ? load_flag(bdone) : 0;
+        const uint64_t fa = wantA ? peek_flag(adone) : 0, fb = wantB ? peek_flag(bdone) : 0;
         apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(fa == epoch)) != 0);
         bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(fb == epoch)) != 0);
+        if ((wantA && apk) || (wantB && bpk)) acquire_packed();
     }
 
     unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_polls = 0;
@@ -877,14 +875,17 @@ gemm_mx_kernel(const MxParams P)
     auto poll_issue = [&](int q) {
         polling = ((wantA && !apk) || (wantB && !bpk)) && q % REPOLL == REPOLL - 1;
         if (polling) {
-            pfa = wantA && !apk ? load_flag(adone) : 0;
-            pfb = wantB && !bpk ? load_flag(bdone) : 0;
+            pfa = wantA && !apk ? peek_flag(adone) : 0;
+            pfb = wantB && !bpk ? peek_flag(bdone) : 0;
         }
     };
     auto poll_finish = [&]() {
         if (polling) {
-            apk = apk || (wantA && __builtin_amdgcn_readfirstlane((int)(pfa == epoch)) != 0);
-            bpk = bpk || (wantB && __builtin_amdgcn_readfirstlane((int)(pfb == epoch)) != 0);
+            const bool na = !apk && wantA && __builtin_amdgcn_readfirstlane((int)(pfa == epoch)) != 0;
+            const bool nb = !bpk && wantB && __builtin_amdgcn_readfirstlane((int)(pfb == epoch)) != 0;
+            if (na || nb) acquire_packed();
+            apk = apk || na;
+            bpk = bpk || nb;
             if (P.do_stats && tid == 0) ++n_polls;
         }
     };
@@ -1009,8 +1010,8 @@ gemm_mx_kernel(const MxParams P)
         wait_all_memory();
         __syncthreads();
         if (tid == 0 && !P.no_publish) {
-            if (prodA) __hip_atomic_store(adone, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (prodB) __hip_atomic_store(bdone, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prodA) publish_flag(adone, epoch);
+            if (prodB) publish_flag(bdone, epoch);
         }
     }
     if (P.do_stats && tid == 0) {

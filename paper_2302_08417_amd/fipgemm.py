@@ -39,6 +39,7 @@ FIP_ATTR_VB_GRID = 9
 FIP_ATTR_MX_TILE = 10
 FIP_ATTR_SPLIT_K = 11
 FIP_ATTR_LAST_HIP_ERROR = 12
+FIP_ATTR_VB_STATUS = 13
 FIP_VB_GRAPH = 1
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
@@ -283,14 +284,21 @@ class Handle:
 
     def bind_stream(self):
         import torch
-        self._check("fip_set_stream", fip_set_stream(self.h, torch.cuda.current_stream().cuda_stream))
+        s = torch.cuda.current_stream()
+        self._check("fip_set_stream", fip_set_stream(self.h, s.cuda_stream))
+        self.stream = s
 
     def ensure_workspace(self, nbytes):
-        """Make sure a workspace of at least nbytes is attached (grows, never shrinks)."""
+        """Make sure a workspace of at least nbytes is attached (grows, never shrinks).  A
+        replaced workspace is marked as used by the stream the handle last ran on, so the
+        caching allocator does not hand its memory out while queued kernels may still use it."""
         import torch
         if nbytes <= 0:
             return
         if self.workspace is None or self.workspace.numel() < nbytes:
+            old, s = self.workspace, getattr(self, "stream", None)
+            if old is not None and s is not None:
+                old.record_stream(s)
             self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
             self._check("fip_set_workspace",
                         fip_set_workspace(self.h, self.workspace.data_ptr(), self.workspace.numel()))

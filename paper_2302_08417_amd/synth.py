@@ -288,8 +288,8 @@ def mx_device_operands(form, n, seed=BASE_SEED, device="cuda"):
     """Large square mixed-precision operands drawn directly on the GPU (torch's seeded
     generator; same value recipe as make_mx_case: U[-1, 1] with rows of A and columns of B
     scaled by 2^u, u ~ U[-8, 8]), column-major, no transpose, ld = n.  Returns
-    (A, B, a_scale, b_scale, A32, B32) as torch tensors; A32/B32 are the binary32 values
-    (None for the E4M3 form, whose codes are drawn from scaled values)."""
+    (A, B, a_scale, b_scale, A32, B32) as torch tensors; A32/B32 are the binary32 values the
+    stored operands were made from (for E4M3, the codes are those values times the scales)."""
     import torch
     g = torch.Generator(device=device).manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
     u_row = torch.rand(n, device=device, generator=g) * 16 - 8

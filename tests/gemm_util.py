@@ -173,4 +173,102 @@ def check_mx(c, Cgpu, tol_factor=4.0):
     bound = tol_factor * kk * U32 * dmax + (U_BF16 * float(np.abs(ref).max()) if c.c_bf16 else 0)
     assert err <= bound, f"max err {err:.3e} > bound {bound:.3e} (dmax {dmax:.3e})"
     truth = mx_fp64_truth(c)[mask]
-    return err / (kk * U32 * dmax), float(np.abs(got - truth).max()) / dmax
+    terr = float(np.abs(got - truth).max())
+    assert terr <= mx_truth_bound(c, kk, dmax, float(np.abs(ref).max())), \
+        f"error vs the binary64 product of the binary32 values {terr:.3e}"
+    return err / (kk * U32 * dmax), terr / dmax
+
+
+# Error of a split form against the binary64 product of the binary32 values it was made from.
+# bfloat16 keeps 8 significant bits (unit roundoff 2^-8), and a term x_t is the rounding of
+# x - x_0 - ... - x_(t-1), so |x_1| <= 2^-8 |x| (1 + 2^-8) and |x_2| <= 2^-16 |x| (1 + 2^-7).
+# Every kept product x_i y_j of two bfloat16 values is exact in binary32.
+#   3-term split: x0 + x1 + x2 = x exactly; the dropped x1 y2 + x2 y1 + x2 y2 are at most
+#                 (2 * 2^-24 + 2^-32)(1 + 2^-6) |x||y| <= 2^-22 |x||y|;
+#   2-term split: the dropped x0 y2 + x2 y0 + x1 y1 + x1 y2 + x2 y1 + x2 y2 are at most
+#                 (3 * 2^-16 + 2 * 2^-24 + 2^-32)(1 + 2^-6) |x||y| <= 2^-14 |x||y|.
+# Summed over k these are bounded by that factor times D; the binary32 accumulation adds the
+# usual 4 k 2^-24 max D.
+SPLIT_DROP = {4: 2.0 ** -22, 5: 2.0 ** -14}
+
+
+def mx_truth_bound(c, kk, dmax, refmax):
+    if c.form not in SPLIT_DROP:
+        return float("inf")
+    bf = U_BF16 * refmax if c.c_bf16 else 0.0
+    return (4 * kk * U32 + SPLIT_DROP[c.form]) * dmax + bf
+
+
+def mx_reference_sampled(c, rows, cols):
+    """Oracle values at sampled entries, via a full reference on a row/column subset."""
+    sub_r = np.unique(rows)
+    sub_c = np.unique(cols)
+    opA = synth.op_view(c.A, c.layout, c.transA, c.m, c.k, c.lda)[sub_r, :]
+    opB = synth.op_view(c.B, c.layout, c.transB, c.k, c.n, c.ldb)[:, sub_c]
+    A32 = synth.op_view(c.A32, c.layout, c.transA, c.m, c.k, c.lda)[sub_r, :]
+    B32 = synth.op_view(c.B32, c.layout, c.transB, c.k, c.n, c.ldb)[:, sub_c]
+    C0 = synth.op_view(c.C, c.layout, "N", c.m, c.n, c.ldc)[np.ix_(sub_r, sub_c)]
+    mm, nn = sub_r.size, sub_c.size
+    sub = synth.MxCase(c.form, synth.COL, mm, nn, c.k, "N", "N", mm, c.k, mm, c.alpha, c.beta,
+                       np.asfortranarray(opA).reshape(-1, order="F").copy(),
+                       np.asfortranarray(opB).reshape(-1, order="F").copy(),
+                       np.asfortranarray(C0).reshape(-1, order="F").copy(), c.c_bf16,
+                       None if c.a_scale is None else c.a_scale[sub_r],
+                       None if c.b_scale is None else c.b_scale[sub_c],
+                       np.asfortranarray(A32).reshape(-1, order="F").copy(),
+                       np.asfortranarray(B32).reshape(-1, order="F").copy())
+    Cref, D = mx_reference(sub)
+    truth = mx_fp64_truth(sub)
+    ri = np.searchsorted(sub_r, rows)
+    ci = np.searchsorted(sub_c, cols)
+    pick = lambda X: X.reshape(nn, mm).T[ri, ci]  # noqa: E731
+    return pick(Cref), pick(D), pick(truth)
+
+
+def mx_freivalds(c, x):
+    """(y, bound): y = C_ref x for the product the stored operands stand for (the kept term
+    products for the split forms), bound = the |.| version on the binary32 values."""
+    C0 = mx_c0(c)
+    if c.form in (2, 3):
+        A = mx_effective(c.form, c.A, c.layout, c.transA, c.m, c.k, c.lda, c.a_scale, True)
+        B = mx_effective(c.form, c.B, c.layout, c.transB, c.k, c.n, c.ldb, c.b_scale, False)
+        return oracle.freivalds(c.layout, c.m, c.n, c.k, c.alpha, A, c.lda, c.transA, B, c.ldb,
+                                c.transB, c.beta, C0, c.ldc, x)
+    pa, pb = oracle.split3(c.A), oracle.split3(c.B)
+    ta = [oracle.bf16_decode(pa[t]) for t in range(3)]
+    tb = [oracle.bf16_decode(pb[t]) for t in range(3)]
+    if c.form == 4:
+        pairs = [(ta[0], tb[0] + tb[1] + tb[2]), (ta[1], tb[0] + tb[1]), (ta[2], tb[0])]
+    else:
+        pairs = [(ta[0], tb[0] + tb[1]), (ta[1], tb[0])]
+    y = None
+    for idx, (a, b) in enumerate(pairs):
+        r, _ = oracle.freivalds(c.layout, c.m, c.n, c.k, c.alpha, a, c.lda, c.transA, b, c.ldb,
+                                c.transB, c.beta if idx == 0 else 0.0, C0, c.ldc, x)
+        y = r if y is None else y + r
+    _, bnd = oracle.freivalds(c.layout, c.m, c.n, c.k, c.alpha, c.A32, c.lda, c.transA, c.B32,
+                              c.ldb, c.transB, c.beta, C0, c.ldc, x)
+    return y, bnd
+
+
+def check_mx_sampled(c, Cgpu, count=512, seed=11, tol_factor=4.0):
+    """Large mixed-precision results: the oracle on sampled entries (corners and fringes
+    included) and a Freivalds probe of every row.  Returns (normalised sampled error, sampled
+    error against the binary64 product of the binary32 values relative to max D)."""
+    assert not c.c_bf16
+    rows, cols = synth.sample_entries(c.m, c.n, count, seed)
+    ref, d, truth = mx_reference_sampled(c, rows, cols)
+    Cv = synth.op_view(Cgpu, c.layout, "N", c.m, c.n, c.ldc)
+    got = Cv[rows, cols].astype(np.float64)
+    kk = max(c.k, 1)
+    dmax = float(d.max())
+    err = float(np.abs(got - ref).max())
+    assert err <= tol_factor * kk * U32 * dmax, f"sampled err {err:.3e}"
+    terr = float(np.abs(got - truth).max())
+    assert terr <= mx_truth_bound(c, kk, dmax, float(np.abs(ref).max())), terr
+    x = synth.rng(seed + 1).choice([-1.0, 1.0], size=c.n)
+    y, bnd = mx_freivalds(c, x)
+    cx = Cv.astype(np.float64) @ x
+    slack = 2.0 * (c.n + c.k + 4) * 2.0 ** -53
+    assert np.all(np.abs(cx - y) <= (tol_factor * kk * U32 + slack) * bnd + 1e-300), "Freivalds"
+    return err / (kk * U32 * dmax), terr / dmax

@@ -91,6 +91,10 @@ def test_attributes(h):
     assert F.fip_get_attr(h, F.FIP_ATTR_PACK_POLICY) == (0, F.FIP_PACK_NONE)
     assert F.fip_set_workspace(h, 0x1001, 10) == 2  # misaligned
     assert F.fip_set_workspace(h, None, 10) == 2
+    # read-only status of batched calls: 0 before any batch ran (no HIP call made), and not
+    # settable
+    assert F.fip_get_attr(h, F.FIP_ATTR_VB_STATUS) == (0, 0)
+    assert F.fip_set_attr(h, F.FIP_ATTR_VB_STATUS, 0) == 2
 
 
 def plan(h, m, n, k, layout=0, dtype=F.FIP_F64, policy=F.FIP_PACK_AUTO, tile=-1, t="NN"):

@@ -134,3 +134,47 @@ def test_bf16_linear_full_size_sampled(AG):
         bound = 4 * kk * u * float(D.max()) + 2.0 ** -8 * float(np.abs(ref).max())
         say(f"{name}: sampled err {err:.3e} bound {bound:.3e}")
         assert err <= bound, name
+
+
+def test_two_streams_do_not_share_a_workspace(AG):
+    """fip_linear on two streams at once, packing forced, in binary32: each stream's calls use
+    their own handle and workspace, so the results match the oracle on both (a shared
+    workspace would let one stream's pack panels and flags overwrite the other's)."""
+    import torch
+    from paper_2302_08417_amd import fipgemm as F
+    say("two streams, packing forced")
+    AG.set_pack_policy(F.FIP_PACK_ALL)
+    try:
+        g = torch.Generator(device="cpu").manual_seed(13)
+        shapes = [(1024, 768, 512), (896, 1024, 640)]   # (batch, out, in): several tile rounds
+        Xs = [torch.randn(b, i, generator=g) for b, o, i in shapes]
+        Ws = [torch.randn(o, i, generator=g) for b, o, i in shapes]
+        dYs = [torch.randn(b, o, generator=g) for b, o, i in shapes]
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        torch.cuda.synchronize()
+        outs = [None, None]
+        for rep in range(3):
+            dev = []
+            for s, X, W, dY in zip(streams, Xs, Ws, dYs):
+                with torch.cuda.stream(s):
+                    x = X.cuda().requires_grad_()
+                    w = W.cuda().requires_grad_()
+                    y = AG.fip_linear(x, w)
+                    y.backward(dY.cuda())
+                    dev.append((y, x, w))
+            torch.cuda.synchronize()
+            outs = [(y.detach().cpu(), x.grad.cpu(), w.grad.cpu()) for y, x, w in dev]
+            for (Y, dX, dW), X, W, dY in zip(outs, Xs, Ws, dYs):
+                for got, a, b, ta, tb in ((Y, X, W, "N", "T"), (dX, dY, W, "N", "N"),
+                                          (dW, dY, X, "T", "N")):
+                    m, n = got.shape
+                    k = a.shape[0] if ta == "T" else a.shape[1]
+                    A64 = a.double().numpy().reshape(-1)
+                    B64 = b.double().numpy().reshape(-1)
+                    ref, D = oracle.gemm(1, m, n, k, 1.0, A64, a.shape[1], ta, B64, b.shape[1],
+                                         tb, 0.0, np.zeros(m * n), n)
+                    err = np.abs(got.double().numpy().reshape(-1) - ref).max()
+                    assert err <= 4 * k * 2.0 ** -24 * D.max(), (rep, m, n, k, err)
+        assert len(AG._local.handles) >= 2
+    finally:
+        AG.set_pack_policy(F.FIP_PACK_AUTO)

@@ -186,3 +186,36 @@ def test_batched_full_workload_sampled(F):
         got = host[db.c_off[i]: db.c_off[i] + b.C[i].size]
         worst = max(worst, check_problem(b, int(i), got))
     say(f"worst normalised error {worst:.3e}")
+
+
+def test_batched_invalid_device_leading_dims_are_skipped_and_reported(F):
+    """Leading dimensions live in device arrays the host never reads: a problem whose ld is
+    below the extent it strides over is not run (its C keeps its bits), the others are
+    computed, and FIP_ATTR_VB_STATUS reports 1 + the largest skipped index, then resets."""
+    from paper_2302_08417_amd.batched import DeviceBatch
+    import torch
+    say("invalid device leading dimensions")
+    b = synth.make_batch(60, COL, lo=2, hi=80, seed=71)
+    db = DeviceBatch(b)
+    h = F.Handle()
+    bad = {7: "lda", 23: "ldb", 41: "ldc"}
+    for i, which in bad.items():
+        arr = getattr(db, which)
+        arr[i] = 0 if which == "ldc" else 1
+    # make sure the shrunk leading dimensions really are too small for their problems
+    for i, which in bad.items():
+        m, n, k = int(b.m[i]), int(b.n[i]), int(b.k[i])
+        need = {"lda": k if chr(b.transA[i]) in "Tt" else m,
+                "ldb": n if chr(b.transB[i]) in "Tt" else k, "ldc": m}[which]
+        assert need > 1 or which == "ldc", (i, which, need)
+    db.run(h)
+    torch.cuda.synchronize()
+    assert h.get_attr(F.FIP_ATTR_VB_STATUS) == 42
+    assert h.get_attr(F.FIP_ATTR_VB_STATUS) == 0
+    host = db.C_host()
+    for i in range(b.count):
+        got = host[db.c_off[i]: db.c_off[i] + b.C[i].size]
+        if i in bad:
+            assert got.tobytes() == b.C[i].tobytes(), i
+        else:
+            check_problem(b, i, got)

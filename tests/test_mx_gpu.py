@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gemm_util import c_mask, check_mx, mx_reference, to_dev
+from gemm_util import c_mask, check_mx, mx_reference_sampled, to_dev
 from paper_2302_08417_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -116,35 +116,9 @@ def test_mx_modes_bitwise(F, form, layout, tA, tB):
     assert total_packed > 0
     # and the common result is right: sampled check against the oracle
     rows, cols = synth.sample_entries(m, n, 512, 3)
-    Cref, D = mx_reference_sampled(c, rows, cols)
+    Cref, D, _ = mx_reference_sampled(c, rows, cols)
     got = synth.op_view(ref, c.layout, "N", m, n, c.ldc)[rows, cols].astype(np.float64)
     assert np.abs(got - Cref).max() <= 4 * k * 2.0 ** -24 * D.max()
-
-
-def mx_reference_sampled(c, rows, cols):
-    """Oracle values at sampled entries, via a full reference on a row/column subset."""
-    sub_r = np.unique(rows)
-    sub_c = np.unique(cols)
-    opA = synth.op_view(c.A, c.layout, c.transA, c.m, c.k, c.lda)[sub_r, :]
-    opB = synth.op_view(c.B, c.layout, c.transB, c.k, c.n, c.ldb)[:, sub_c]
-    A32 = synth.op_view(c.A32, c.layout, c.transA, c.m, c.k, c.lda)[sub_r, :]
-    B32 = synth.op_view(c.B32, c.layout, c.transB, c.k, c.n, c.ldb)[:, sub_c]
-    C0 = synth.op_view(c.C, c.layout, "N", c.m, c.n, c.ldc)[np.ix_(sub_r, sub_c)]
-    mm, nn = sub_r.size, sub_c.size
-    sub = synth.MxCase(c.form, COL, mm, nn, c.k, "N", "N", mm, c.k, mm, c.alpha, c.beta,
-                       np.asfortranarray(opA).reshape(-1, order="F").copy(),
-                       np.asfortranarray(opB).reshape(-1, order="F").copy(),
-                       np.asfortranarray(C0).reshape(-1, order="F").copy(), c.c_bf16,
-                       None if c.a_scale is None else c.a_scale[sub_r],
-                       None if c.b_scale is None else c.b_scale[sub_c],
-                       np.asfortranarray(A32).reshape(-1, order="F").copy(),
-                       np.asfortranarray(B32).reshape(-1, order="F").copy())
-    Cref, D = mx_reference(sub)
-    ri = np.searchsorted(sub_r, rows)
-    ci = np.searchsorted(sub_c, cols)
-    return Cref.reshape(nn, mm).T[ri, ci], D.reshape(nn, mm).T[ri, ci]
-
-
 
 
 @pytest.mark.parametrize("form,tile", BIG, ids=["bf16-256"])

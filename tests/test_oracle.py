@@ -247,6 +247,26 @@ def test_freivalds_exact_on_integers(layout):
                                   + 3 * (np.abs(iC) @ np.abs(ix))).astype(np.float64))
 
 
+@pytest.mark.parametrize("layout", [COL, ROW])
+def test_freivalds_finds_a_planted_error(layout):
+    """A result that is right except for one entry: the probe flags exactly that entry's row,
+    for an error as small as a few times the tolerance, and flags nothing on the right
+    result."""
+    c = synth.make_case(layout, 40, 35, 50, "T", "N", ld_pad=7, seed=37)
+    Cref, _ = run_oracle(c)
+    x = synth.rng(9).choice([-1.0, 1.0], size=c.n)
+    y, bound = oracle.freivalds(c.layout, c.m, c.n, c.k, c.alpha, c.A, c.lda, c.transA, c.B,
+                                c.ldb, c.transB, c.beta, c.C, c.ldc, x)
+    tol = 4 * c.k * 2.0 ** -53 * bound + 2.0 * (c.n + c.k + 4) * 2.0 ** -53 * bound
+    good = cview(Cref, c) @ x
+    assert np.all(np.abs(good - y) <= tol)
+    for (i, j), rel in [((0, 0), 1e-6), ((17, 34), 1e-9), ((39, 20), 50.0)]:
+        bad = cview(Cref, c).copy()
+        bad[i, j] += rel * bound[i]
+        flagged = np.abs(bad @ x - y) > tol
+        assert flagged[i] and flagged.sum() == 1, (i, j, rel)
+
+
 def test_materialize_matches_numpy_views():
     for layout, t, pad in itertools.product([COL, ROW], TRANS, [0, 7]):
         c = synth.make_case(layout, 6, 5, 4, t, t, ld_pad=pad, seed=1)
@@ -282,11 +302,12 @@ def test_orientation_rule_matches_numpy_strides():
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_pack_block_structure_bruteforce(dtype):
-    """Every (mn, k) <= 6, (MNT, KT) in {1..4}^2, both operands, all layouts/trans:
+    """Every (mn, k) <= 9, (MNT, KT) in {1..4}^2 (so every (MT, NT, KT) in {1..4}^3 over the
+    two operands), both operands, all layouts/trans:
     reshaping the packed buffer to (tiles, ksteps, KT, MNT) for operands stored along MN,
     or (tiles, ksteps, MNT, KT) for operands stored along k, must expose op(X) tile by
     tile with zero fill outside op(X)."""
-    for mn, k, MNT, KT in itertools.product(range(0, 7), range(0, 7), range(1, 5), range(1, 5)):
+    for mn, k, MNT, KT in itertools.product(range(0, 10), range(0, 10), range(1, 5), range(1, 5)):
         for layout, t, is_b in itertools.product([COL, ROW], ["N", "T"], [0, 1]):
             rows, cols = (k, mn) if is_b else (mn, k)
             buf, ld, vals = _encoded_case(layout, t, rows, cols, 3, dtype)
