@@ -240,6 +240,28 @@ int fip_dgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, 
               const double* A, int64_t lda, char transA, const double* B, int64_t ldb,
               char transB, double beta, double* C, int64_t ldc);
 
+/*
+ * fip_dgemm for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, semantics, argument checks and return codes as
+ * fip_dgemm; the caller still owns A, B and C.  Instead of the handle's
+ * workspace, the call uses a scratch array that the library owns: 64 MiB of
+ * device memory per GPU (one copy on every GPU the library runs on, held until
+ * the process ends).  It calls no hipMalloc, hipFree or other allocating
+ * routine.  The plan is the one fip_plan reports under the handle's
+ * attributes, except that a plan whose workspace would not fit in the array
+ * runs without packing (the same kernel and k order, so the same C bit for
+ * bit); if the split-k partial products alone need more than 64 MiB the call
+ * returns FIP_ERR_WORKSPACE before launching anything.  Nothing in the array
+ * needs clearing between calls (claims and flags carry per-call stamps), and
+ * FIP_ATTR_STATS is ignored.  Every call on one GPU shares that GPU's array:
+ * calls that may overlap in time on one GPU (two streams, two threads, two
+ * handles) race on it and must be ordered by the caller.
+ */
+int fip_dgemm_noalloc(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double* A, int64_t lda, char transA, const double* B,
+                      int64_t ldb, char transB, double beta, double* C, int64_t ldc);
+
 /* The same in binary32 (FP32 MFMA, FP32 accumulation). */
 int fip_sgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, float alpha,
               const float* A, int64_t lda, char transA, const float* B, int64_t ldb,

@@ -152,6 +152,13 @@ hipError_t launch_vbatched(const VbLaunchDesc& d);
 hipError_t build_vbatched_graph(const VbLaunchDesc& d, hipGraphExec_t* exec);
 int vbatched_grid();   // resident workgroups of the batched kernel on the device
 
+// Scratch array of fip_dgemm_noalloc (fipgemm_scratch.hip): kScratchBytes of
+// device memory per GPU, owned by the library for the life of the process.
+constexpr int64_t kScratchBytes = (int64_t)64 << 20;
+// Device address of the current device's copy of the array (looked up once per
+// device, with that device current).
+hipError_t scratch_buffer(void** ptr);
+
 // Enqueue the XCC-id diagnostic (one 64-thread workgroup per entry).
 hipError_t launch_xcc_map(uint32_t* out, int64_t nblocks, hipStream_t stream);
 

@@ -208,7 +208,7 @@ int mx_form_of(int dtype)
 bool valid_dtype(int dtype) { return dtype == FIP_F64 || dtype == FIP_F32 || mx_form_of(dtype) >= 0; }
 
 void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
-               char tA, char tB, bool standalone_pack, Plan* pl)
+               char tA, char tB, bool standalone_pack, Plan* pl, int policy_override = -1)
 {
     memset(pl, 0, sizeof(*pl));
     const int form = mx_form_of(dtype);
@@ -281,7 +281,8 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
         }
     }
 
-    int policy = standalone_pack ? FIP_PACK_CONSUME_ONLY : h->policy;
+    int policy = standalone_pack ? FIP_PACK_CONSUME_ONLY
+                 : policy_override >= 0 ? policy_override : h->policy;
     // Under stream capture a fused call runs unpacked: its claims and flags are
     // stamped with an epoch chosen on the host per call, and every replay of a
     // captured launch would carry the same one, so a replay would take the
@@ -456,9 +457,9 @@ void fill_operands(const Plan& pl, int layout, const void* A, int64_t lda, char 
     }
 }
 
-void fill_workspace(const fip_handle_s* h, const Plan& pl, fip::LaunchDesc* d)
+void fill_workspace(void* base, const Plan& pl, fip::LaunchDesc* d)
 {
-    char* ws = static_cast<char*>(h->ws);
+    char* ws = static_cast<char*>(base);
     d->stats_ptr = reinterpret_cast<unsigned long long*>(ws + pl.off_stats);
     d->aflag = reinterpret_cast<uint64_t*>(ws + pl.off_aflag);
     d->bflag = reinterpret_cast<uint64_t*>(ws + pl.off_bflag);
@@ -478,10 +479,12 @@ int prepare_workspace(fip_handle_s* h, const Plan& pl)
     return 0;
 }
 
+// noalloc: run on the library's scratch array (fip_dgemm_noalloc) instead of
+// the handle's workspace.
 template <typename T>
 int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64_t k, T alpha,
               const T* A, int64_t lda, char tA, const T* B, int64_t ldb, char tB, T beta, T* C,
-              int64_t ldc)
+              int64_t ldc, bool noalloc = false)
 {
     try {
         if (!valid_handle(h)) return FIP_ERR_HANDLE;
@@ -499,8 +502,22 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         }
         Plan pl;
         make_plan(h, dtype, layout, m, n, k, tA, tB, false, &pl);
-        const int ws = prepare_workspace(h, pl);
-        if (ws) return ws;
+        void* ws_base = h->ws;
+        if (noalloc) {
+            // The scratch array replaces the workspace.  A plan whose packed
+            // panels would not fit runs unpacked (the same kernel and k order,
+            // so the same C bit for bit); one whose split-k partials alone
+            // exceed the array is rejected before anything is launched.
+            if (pl.pub.workspace_bytes > fip::kScratchBytes && pl.mode == fip::kModeFused)
+                make_plan(h, dtype, layout, m, n, k, tA, tB, false, &pl, FIP_PACK_NONE);
+            if (pl.pub.workspace_bytes > fip::kScratchBytes) return FIP_ERR_WORKSPACE;
+            if (pl.pub.workspace_bytes > 0) {
+                if (const hipError_t e = fip::scratch_buffer(&ws_base); e != hipSuccess)
+                    return launch_failed(h, e);
+            }
+        } else if (const int ws = prepare_workspace(h, pl); ws) {
+            return ws;
+        }
         fip::LaunchDesc d;
         memset(&d, 0, sizeof(d));
         d.elem = sizeof(T);
@@ -508,7 +525,7 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.mode = pl.mode;
         d.pack_a = pl.kpack_a; d.pack_b = pl.kpack_b;
         d.no_publish = h->no_publish;
-        d.stats = h->stats;
+        d.stats = noalloc ? 0 : h->stats;   // the scratch array's counters are never cleared
         d.order = pl.order;
         d.M = ks.M; d.N = ks.N; d.K = k;
         fill_operands(pl, layout, A, lda, tA, B, ldb, tB, &d);
@@ -517,7 +534,7 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.split = pl.split;
         d.slice_ksteps = pl.slice_ksteps;
         if (pl.pub.workspace_bytes > 0) {
-            fill_workspace(h, pl, &d);
+            fill_workspace(ws_base, pl, &d);
             if (pl.mode == fip::kModeFused) d.epoch = h->epoch = next_epoch();
         } else {
             d.stats = 0;
@@ -981,6 +998,14 @@ int fip_dgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, 
                              transB, beta, C, ldc);
 }
 
+int fip_dgemm_noalloc(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double* A, int64_t lda, char transA, const double* B,
+                      int64_t ldb, char transB, double beta, double* C, int64_t ldc)
+{
+    return gemm_impl<double>(handle, FIP_F64, layout, m, n, k, alpha, A, lda, transA, B, ldb,
+                             transB, beta, C, ldc, true);
+}
+
 int fip_sgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, float alpha,
               const float* A, int64_t lda, char transA, const float* B, int64_t ldb, char transB,
               float beta, float* C, int64_t ldc)
@@ -1024,7 +1049,7 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
         d.mode = pl.mode;
         d.M = pl.ks.M; d.N = pl.ks.N; d.K = k;
         fill_operands(pl, layout, A, lda, transA, B, ldb, transB, &d);
-        fill_workspace(handle, pl, &d);
+        fill_workspace(handle->ws, pl, &d);
         d.stream = handle->stream;
         if (const hipError_t e = fip::launch_pack(d); e != hipSuccess) return launch_failed(handle, e);
         handle->last = pl.pub;

@@ -43,6 +43,7 @@ FIP_ATTR_VB_STATUS = 13
 FIP_VB_GRAPH = 1
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
+SCRATCH_BYTES = 64 << 20   # fip_dgemm_noalloc's scratch array per GPU
 
 
 class fip_plan_t(ctypes.Structure):
@@ -81,6 +82,8 @@ _SIGS = {
     "fip_last_plan": [_vp, ctypes.POINTER(fip_plan_t)],
     "fip_dgemm": [_vp, _i32, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _ch, _vp, _i64, _ch,
                   ctypes.c_double, _vp, _i64],
+    "fip_dgemm_noalloc": [_vp, _i32, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _ch, _vp, _i64,
+                          _ch, ctypes.c_double, _vp, _i64],
     "fip_sgemm": [_vp, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64, _ch,
                   ctypes.c_float, _vp, _i64],
     "fip_pack": [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _ch, _vp, _i64, _ch],
@@ -171,6 +174,11 @@ def fip_last_plan(h):
 def fip_dgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
     return _lib.fip_dgemm(h, layout, m, n, k, alpha, _addr(A), lda, _trans(transA), _addr(B), ldb,
                           _trans(transB), beta, _addr(C), ldc)
+
+
+def fip_dgemm_noalloc(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+    return _lib.fip_dgemm_noalloc(h, layout, m, n, k, alpha, _addr(A), lda, _trans(transA),
+                                  _addr(B), ldb, _trans(transB), beta, _addr(C), ldc)
 
 
 def fip_sgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
