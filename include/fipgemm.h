@@ -125,15 +125,19 @@ enum {
 };
 
 enum {
-    FIP_PACK_AUTO = 0,         /* paper Sec. 3.3 reuse table, applied when the
-                                  launch has more tiles than fit on the device
-                                  at once (only then can a later pass reuse a
-                                  pack without waiting for it), more than 4
-                                  such rounds for the bfloat16 split forms of
-                                  binary32 (their per-XCD producer copies are
-                                  not repaid in fewer); bfloat16 and E4M3
-                                  operands are never packed under AUTO (their
-                                  unpacked reads are as fast) */
+    FIP_PACK_AUTO = 0,         /* paper Sec. 3.3 reuse table and stride
+                                  conditions: a panel is packed only if a later
+                                  round of workgroups re-reads it (the launch
+                                  has more tiles than fit on the device at
+                                  once, more than 4 such rounds for the bfloat16
+                                  split forms of binary32, and at least 4
+                                  k-steps) and its unpacked read is slower than a
+                                  packed one: every reused panel of the split
+                                  forms (an unpacked read redoes the split), and
+                                  for the other forms only the fringe panel of an
+                                  operand whose extent is not a multiple of the
+                                  tile (interior chunks read coalesced either
+                                  way; see fip_plan_t.a_pack_first) */
     FIP_PACK_ALL = 1,          /* pack both operands whatever the shape */
     FIP_PACK_NONE = 2,         /* never pack (the unpacked "SUP" path, Sec. 2.3) */
     FIP_PACK_CONSUME_ONLY = 3, /* read only packed panels written beforehand by
@@ -149,7 +153,8 @@ enum {
  * The plan of one call, in the caller's terms (op(A) is m x k, op(B) k x n).
  * Packed layout (the contract): the pack of op(A) is ceil(m/MT)*ceil(k/KT)
  * contiguous blocks of KT*MT elements; block (t, q) (tile row t, k-step q) is
- * block number t*ceil(k/KT) + q.  Inside a block the tile keeps the
+ * block number t*ceil(k/KT) + q (a copy that starts at tile row
+ * a_pack_first holds block number (t - a_pack_first)*ceil(k/KT) + q).  Inside a block the tile keeps the
  * orientation op(A) has in storage: if A's storage runs along m (column-major
  * 'N', row-major 'T'), element (i, p) sits at (p % KT)*MT + (i % MT), each
  * k-slice contiguous; otherwise (column-major 'T', row-major 'N') at
@@ -193,6 +198,10 @@ typedef struct {
                                   [split_k][kernel N][kernel M] (C's shape, column-major;
                                   transposed for row-major calls) in C's type, binary32
                                   for the mixed forms (FP8 scales applied); -1 otherwise */
+    int32_t a_pack_first;      /* pack_a: the first tile row whose panel is packed (AUTO may
+                                  pack only the fringe panel); a copy holds the panels
+                                  from it on, panel t at block (t - a_pack_first) */
+    int32_t b_pack_first;      /* the same for op(B)'s tile columns */
 } fip_plan_t;
 
 int fip_create(fip_handle_t* handle);

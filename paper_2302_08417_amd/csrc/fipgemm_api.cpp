@@ -23,6 +23,10 @@ constexpr int kMaxSplit = 32;            // split k: at most this many slices
 // split k, mixed forms: at least this many k per slice (bfloat16 / E4M3, whose first
 // pass only copies, and the bfloat16 split forms of binary32)
 constexpr int64_t kMinSliceKCopy = 1024, kMinSliceKSplit = 256;
+// AUTO packs nothing when a panel has fewer k-steps than this: a k-loop that
+// short is over before a later pass could read the pack, and its reads are
+// all first touches (each chunk is read once per tile either way).
+constexpr int64_t kMinPackKsteps = 4;
 
 // Epoch stamps of fused calls.  Claims and publish flags in a workspace are
 // compared for equality with the current call's stamp, so a stamp must never
@@ -183,6 +187,7 @@ struct Plan {
     int elem;
     int mode;
     int kpack_a, kpack_b;           // packing in kernel terms
+    int kfrom_a, kfrom_b;           // first packed tile row / column (kernel terms)
     int64_t tilesKM, tilesKN, nK;
     int64_t off_stats, off_aflag, off_bflag, off_aclaim, off_bclaim, off_apack, off_bpack;
     int64_t apack_copy_elems, bpack_copy_elems;
@@ -317,25 +322,46 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
             // 6.5 ms packed, 7.4 unpacked).
             const bool split_form = form == fip::kMxX3 || form == fip::kMxX3Fast;
             const bool later_passes =
-                pl->tilesKM * pl->tilesKN * pl->split > (split_form ? 4 : 1) * resident;
+                pl->tilesKM * pl->tilesKN * pl->split > (split_form ? 4 : 1) * resident &&
+                pl->nK >= kMinPackKsteps;
             double fa = 0.0, fb = 0.0;
             if (later_passes)
                 later_round_reuse(pl->tilesKM, pl->tilesKN, pl->order, resident / fip::kCopies,
                                   pl->split, &fa, &fb);
-            pl->kpack_a = pl->tilesKN > 1 && fa >= 0.5;
-            pl->kpack_b = pl->tilesKM > 1 && fb >= 0.5;
-            // bfloat16 / E4M3: the pack is a plain copy in the operand's own
-            // orientation, and the kernel reads either orientation from the
-            // caller's buffer at full speed (MN-major through the transposing
-            // LDS reads); measured, packed re-reads were slower than unpacked
-            // ones, so (Sec. 3.3: skip the pack when the strides allow fast
-            // unpacked access) AUTO does not pack them.  The split forms pack:
-            // an unpacked read redoes the split.
-            if (form == fip::kMxBF16 || form == fip::kMxFP8) pl->kpack_a = pl->kpack_b = 0;
+            const bool reuse_a = pl->tilesKN > 1 && fa >= 0.5;
+            const bool reuse_b = pl->tilesKM > 1 && fb >= 0.5;
+            // Sec. 3.3's stride conditions, read for this GPU: a reused
+            // panel is packed only where its unpacked read is slower than a
+            // packed one would be.
+            //  - The split forms: an unpacked read redoes the binary32 split,
+            //    a packed one reads the terms: every reused panel is packed.
+            //  - Otherwise the unpacked read of an interior chunk is as
+            //    coalesced as the packed one, whatever the transposes: each
+            //    of its rows (the k-rows of an MN-major operand, the MN-rows of
+            //    a K-major one) is one contiguous run of at least a 128-byte
+            //    line (MT or NT times the element size is 256 bytes or more;
+            //    KT times it is 128 bytes in every form), and a panel's runs
+            //    span as many lines as the packed copy, plus at most one per
+            //    row that the next k-step reads from the XCD's L2.  So only a
+            //    fringe panel (the operand's M or N extent not a multiple of
+            //    the tile) is packed: its unpacked chunks take the masked,
+            //    zero-filling loads, its packed chunks are zero padded and
+            //    read with the same unmasked loads as any other.
+            if (split_form) {
+                pl->kpack_a = reuse_a;
+                pl->kpack_b = reuse_b;
+            } else {
+                pl->kpack_a = reuse_a && pl->ks.M % MT != 0;
+                pl->kpack_b = reuse_b && pl->ks.N % NT != 0;
+                pl->kfrom_a = (int)pl->tilesKM - 1;
+                pl->kfrom_b = (int)pl->tilesKN - 1;
+            }
         }
         if (pl->kpack_a || pl->kpack_b) copies = fip::kCopies;
     }
     if (k == 0 || m == 0 || n == 0) { pl->kpack_a = pl->kpack_b = 0; copies = 0; }
+    if (!pl->kpack_a) pl->kfrom_a = 0;
+    if (!pl->kpack_b) pl->kfrom_b = 0;
 
     if (k == 0 || m == 0 || n == 0) { pl->split = 1; pl->slice_ksteps = (int)pl->nK; }
     const bool fz = pl->mode == fip::kModeFused;
@@ -346,8 +372,8 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     pl->off_bflag = off; off = align256(off + (pl->kpack_b && fz ? copies * pl->tilesKN * sp * 8 : 0));
     pl->off_aclaim = off; off = align256(off + (pl->kpack_a && fz ? copies * pl->tilesKM * sp * 8 : 0));
     pl->off_bclaim = off; off = align256(off + (pl->kpack_b && fz ? copies * pl->tilesKN * sp * 8 : 0));
-    pl->apack_copy_elems = pl->kpack_a ? pl->tilesKM * pl->nK * KT * MT : 0;
-    pl->bpack_copy_elems = pl->kpack_b ? pl->tilesKN * pl->nK * KT * NT : 0;
+    pl->apack_copy_elems = pl->kpack_a ? (pl->tilesKM - pl->kfrom_a) * pl->nK * KT * MT : 0;
+    pl->bpack_copy_elems = pl->kpack_b ? (pl->tilesKN - pl->kfrom_b) * pl->nK * KT * NT : 0;
     pl->off_apack = off; off = align256(off + copies * pl->apack_copy_elems * pl->elem);
     pl->off_bpack = off; off = align256(off + copies * pl->bpack_copy_elems * pl->elem);
     // slice partials: the output type's accumulator (binary32 for the mixed forms)
@@ -374,6 +400,7 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     if (!pl->ks.swapped) {
         p.tiles_m = (int32_t)pl->tilesKM; p.tiles_n = (int32_t)pl->tilesKN;
         p.pack_a = pl->kpack_a; p.pack_b = pl->kpack_b;
+        p.a_pack_first = pl->kfrom_a; p.b_pack_first = pl->kfrom_b;
         p.a_pack_offset = pl->off_apack; p.a_copy_bytes = pl->apack_copy_elems * pl->elem;
         p.b_pack_offset = pl->off_bpack; p.b_copy_bytes = pl->bpack_copy_elems * pl->elem;
         p.a_flag_offset = fl ? pl->off_aflag : -1; p.b_flag_offset = fl ? pl->off_bflag : -1;
@@ -381,6 +408,7 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     } else {
         p.tiles_m = (int32_t)pl->tilesKN; p.tiles_n = (int32_t)pl->tilesKM;
         p.pack_a = pl->kpack_b; p.pack_b = pl->kpack_a;
+        p.a_pack_first = pl->kfrom_b; p.b_pack_first = pl->kfrom_a;
         p.a_pack_offset = pl->off_bpack; p.a_copy_bytes = pl->bpack_copy_elems * pl->elem;
         p.b_pack_offset = pl->off_apack; p.b_copy_bytes = pl->apack_copy_elems * pl->elem;
         p.a_flag_offset = fl ? pl->off_bflag : -1; p.b_flag_offset = fl ? pl->off_aflag : -1;
@@ -524,6 +552,7 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.tile_class = pl.pub.tile_class;
         d.mode = pl.mode;
         d.pack_a = pl.kpack_a; d.pack_b = pl.kpack_b;
+        d.a_pack_from = pl.kfrom_a; d.b_pack_from = pl.kfrom_b;
         d.no_publish = h->no_publish;
         d.stats = noalloc ? 0 : h->stats;   // the scratch array's counters are never cleared
         d.order = pl.order;
@@ -560,6 +589,7 @@ void fill_mx_desc(const fip_handle_s* h, const Plan& pl, int form, int layout, i
     d->mt = pl.pub.MT;
     d->mode = pl.mode;
     d->pack_a = pl.kpack_a; d->pack_b = pl.kpack_b;
+    d->a_pack_from = pl.kfrom_a; d->b_pack_from = pl.kfrom_b;
     d->no_publish = h->no_publish;
     d->stats = h->stats;
     d->order = pl.order;

@@ -45,6 +45,7 @@ struct Params {
     uint64_t epoch;
     int tilesM, tilesN, nK, group_m;
     int mode, pack_a, pack_b, no_publish, do_stats;
+    int a_pack_from, b_pack_from;  // first tile row / column whose panel is packed
     int a_vec, b_vec, c_vec;
     int a_fast, b_fast;  // interior chunks may use the 32-bit-offset vector loader
     int order;       // tile order inside an XCD's run: 0 grouped, 1 column-distinct rounds
@@ -109,12 +110,16 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         if (x < (unsigned)kCopies) copy = (int)x;
         else fused = false;  // unknown XCD id: this workgroup stays unpacked
     }
-    const bool useA = fused && P.pack_a, useB = fused && P.pack_b;
+    const bool useA = fused && P.pack_a && tm >= P.a_pack_from;
+    const bool useB = fused && P.pack_b && tn >= P.b_pack_from;
 
     T* apanel = nullptr;
     T* bpanel = nullptr;
-    if (useA || consume) apanel = P.apack + (int64_t)copy * P.apack_copy + (int64_t)tm * nK * KT * MT;
-    if (useB || consume) bpanel = P.bpack + (int64_t)copy * P.bpack_copy + (int64_t)tn * nK * KT * NT;
+    // a copy holds the packed panels from a_pack_from / b_pack_from on
+    if (useA || consume)
+        apanel = P.apack + (int64_t)copy * P.apack_copy + (int64_t)(tm - P.a_pack_from) * nK * KT * MT;
+    if (useB || consume)
+        bpanel = P.bpack + (int64_t)copy * P.bpack_copy + (int64_t)(tn - P.b_pack_from) * nK * KT * NT;
     // One completion flag and one claim per (copy, panel, k-slice): a slice's
     // chunks of a panel are packed by the first workgroup of that slice.
     const int64_t aslot = ((int64_t)copy * P.tilesM + tm) * S + slice;
@@ -451,6 +456,7 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.nK = (int)((d.K + KT - 1) / KT);
     P.group_m = kGroupM;
     P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
+    P.a_pack_from = d.a_pack_from; P.b_pack_from = d.b_pack_from;
     P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
     const int64_t a_far = d.a_kmajor ? d.a_smn : d.a_sk;  // the leading dimension
     const int64_t b_far = d.b_kmajor ? d.b_smn : d.b_sk;

@@ -575,6 +575,7 @@ struct MxParams {
     uint64_t epoch;
     int tilesM, tilesN, nK, group_m;
     int mode, pack_a, pack_b, no_publish, do_stats, order;
+    int a_pack_from, b_pack_from;  // first tile row / column whose panel is packed
     int a_vec, b_vec;                // unpacked vector loads allowed (dword alignment)
     int c_bf16;
     int split, slice_ksteps;         // k slices (1: none) and k-steps per slice
@@ -801,11 +802,15 @@ gemm_mx_kernel(const MxParams P)
         if (x < (unsigned)kCopies) copy = (int)x;
         else fused = false;
     }
-    const bool useA = fused && P.pack_a, useB = fused && P.pack_b;
+    const bool useA = fused && P.pack_a && tm >= P.a_pack_from;
+    const bool useB = fused && P.pack_b && tn >= P.b_pack_from;
     char* apanel = nullptr;
     char* bpanel = nullptr;
-    if (useA || consume) apanel = P.apack + copy * P.apack_copy + (int64_t)tm * nK * G::PACK_CHUNK;
-    if (useB || consume) bpanel = P.bpack + copy * P.bpack_copy + (int64_t)tn * nK * G::PACK_CHUNK;
+    // a copy holds the packed panels from a_pack_from / b_pack_from on
+    if (useA || consume)
+        apanel = P.apack + copy * P.apack_copy + (int64_t)(tm - P.a_pack_from) * nK * G::PACK_CHUNK;
+    if (useB || consume)
+        bpanel = P.bpack + copy * P.bpack_copy + (int64_t)(tn - P.b_pack_from) * nK * G::PACK_CHUNK;
     // one claim and one completion flag per (copy, panel, k-slice)
     const int64_t aslot = ((int64_t)copy * P.tilesM + tm) * NS + slice;
     const int64_t bslot = ((int64_t)copy * P.tilesN + tn) * NS + slice;
@@ -1300,6 +1305,7 @@ MxParams make_mx_params(const MxLaunchDesc& d, int MT)
     P.nK = (int)((d.K + KT - 1) / KT);
     P.group_m = kGroupM;
     P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
+    P.a_pack_from = d.a_pack_from; P.b_pack_from = d.b_pack_from;
     P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
     P.order = d.order;
     // vector loads of the unpacked operand need every 4-byte group of a

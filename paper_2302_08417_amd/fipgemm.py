@@ -64,6 +64,7 @@ class fip_plan_t(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64),
         ("split_k", ctypes.c_int32), ("slice_ksteps", ctypes.c_int32),
         ("partial_offset", ctypes.c_int64),
+        ("a_pack_first", ctypes.c_int32), ("b_pack_first", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -141,9 +141,12 @@ def _expected_pack(tilesM, tilesN, resident, order=0):
 
 
 def test_pack_table_of_the_paper(h):
-    """Sec. 3.3: n <= n_R -> do not pack A; m <= m_R -> do not pack B (tile = MT x NT); and
-    on the GPU a pack only pays when a later round of workgroups on the same XCD reads the
-    panel again (a single round, or a panel used by one round only, is not packed)."""
+    """Sec. 3.3: n <= n_R -> do not pack A; m <= m_R -> do not pack B (tile = MT x NT); on the
+    GPU a pack only pays when a later round of workgroups on the same XCD reads the panel again
+    (a single round, or a panel used by one round only, is not packed), and, by the stride
+    conditions, only where the unpacked read is slower than a packed one: a fringe panel.  An
+    operand whose extent is a multiple of the tile is never packed under AUTO (its chunks read
+    coalesced either way); one with a fringe packs only that last panel."""
     for tile, T, slots in [(0, 128, 512), (1, 64, 1024), (2, 32, 1536)]:
         for m, n in [(T, T), (T, (2 * slots + 1) * T), ((2 * slots + 1) * T, T),
                      (T, (slots + 1) * T), (40 * T, 40 * T), (64 * T, 64 * T),
@@ -151,24 +154,42 @@ def test_pack_table_of_the_paper(h):
             for layout in (0, 1):
                 for order in (0, 1):
                     assert F.fip_set_attr(h, F.FIP_ATTR_ORDER, order) == 0
-                    p = plan(h, m, n, 64, layout=layout, tile=tile)
                     # kernel terms: row-major storage swaps the operands
                     tM, tN = (m // T, n // T) if layout == 0 else (n // T, m // T)
                     ea, eb = _expected_pack(tM, tN, slots, order)
                     if layout == 1:
                         ea, eb = eb, ea
-                    assert (p.pack_a, p.pack_b) == (ea, eb), (tile, m, n, layout, order)
+                    # exact multiples of the tile: nothing is packed
+                    p = plan(h, m, n, 64, layout=layout, tile=tile)
+                    assert (p.pack_a, p.pack_b) == (0, 0), (tile, m, n, layout, order)
                     assert p.MT == T and p.NT == T
+                    assert p.workspace_bytes == 0 and p.copies == 0
+                    # a fringe in both extents (same tile counts): the reused fringe panels
+                    p = plan(h, m - 3, n - 5, 64, layout=layout, tile=tile)
+                    assert (p.pack_a, p.pack_b) == (ea, eb), (tile, m, n, layout, order)
+                    if p.pack_a:
+                        assert p.a_pack_first == p.tiles_m - 1
+                        assert p.a_copy_bytes == p.ksteps * p.KT * p.MT * 8
+                    if p.pack_b:
+                        assert p.b_pack_first == p.tiles_n - 1
+                        assert p.b_copy_bytes == p.ksteps * p.KT * p.NT * 8
                     if not p.pack_a and not p.pack_b:
                         assert p.workspace_bytes == 0 and p.copies == 0
     assert F.fip_set_attr(h, F.FIP_ATTR_ORDER, 0) == 0
     # the shapes the rule is about: one tile row reused by many later rounds packs A only
-    p = plan(h, 128, (2 * 512 + 1) * 128 * 8, 64, tile=0)
+    p = plan(h, 100, (2 * 512 + 1) * 128 * 8 - 1, 64, tile=0)
+    assert (p.pack_a, p.pack_b, p.a_pack_first) == (1, 0, 0)
+    p = plan(h, 64 * 128 - 1, 64 * 128 - 1, 64, tile=0)  # one band per XCD: B columns never recur
     assert (p.pack_a, p.pack_b) == (1, 0)
-    p = plan(h, 64 * 128, 64 * 128, 64, tile=0)     # one band per XCD: B columns never recur
-    assert (p.pack_a, p.pack_b) == (1, 0)
-    p = plan(h, 128 * 128, 128 * 128, 64, tile=0)   # several bands per XCD: both recur
+    p = plan(h, 128 * 128 - 1, 128 * 128 - 1, 64, tile=0)   # several bands per XCD: both recur
     assert (p.pack_a, p.pack_b) == (1, 1)
+    assert (p.a_pack_first, p.b_pack_first) == (127, 127)
+    # a k-loop of fewer than 4 k-steps is never packed (FP64 k-step 16)
+    assert plan(h, 128 * 128 - 1, 128 * 128 - 1, 48, tile=0).workspace_bytes == 0
+    assert plan(h, 128 * 128 - 1, 128 * 128 - 1, 49, tile=0).pack_a == 1
+    # every policy but AUTO keeps whole-operand packs
+    q = plan(h, 128 * 128 - 1, 128 * 128 - 1, 64, tile=0, policy=F.FIP_PACK_ALL)
+    assert (q.pack_a, q.pack_b, q.a_pack_first, q.b_pack_first) == (1, 1, 0, 0)
 
 
 def test_single_round_launches_do_not_pack(h):
