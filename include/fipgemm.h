@@ -122,6 +122,12 @@ enum {
        dimension was too small or a matrix spans 2 GiB or more (0: none).
        Reading it waits for the handle's stream and resets it to 0. */
     FIP_ATTR_VB_STATUS = 13,
+    /* Pack copies of a fused call: 1 (one copy shared by all XCDs: a panel
+       is packed once on the device, and the publish protocol's agent-scope
+       release and acquire make it visible across XCDs) or 8 (one per XCD,
+       indexed by the hardware XCC id: every XCD packs its own copy of each
+       panel it reads); -1 (default): 1. */
+    FIP_ATTR_COPIES = 14,
 };
 
 enum {
@@ -162,10 +168,11 @@ enum {
  * the same with (MT, i) replaced by (NT, j): its storage runs along n for
  * column-major 'T' and row-major 'N'.  Entries outside the matrix are +0.0.
  * Element bits are copied unchanged; alpha is not folded in.
- * The fused path keeps one copy per XCD (copies = 8), indexed by the
- * hardware XCC id of the workgroup that packs it; copy c of op(A)'s pack
- * starts at workspace + a_pack_offset + c * a_copy_bytes.  The standalone
- * pack (fip_pack) and CONSUME_ONLY use copy 0.
+ * The fused path keeps one copy shared by all XCDs (copies = 1) or, with
+ * FIP_ATTR_COPIES = 8, one per XCD (copies = 8), indexed by the hardware XCC
+ * id of the workgroup that packs it; copy c of op(A)'s pack starts at
+ * workspace + a_pack_offset + c * a_copy_bytes.  The standalone pack
+ * (fip_pack) and CONSUME_ONLY use copy 0.
  * Mixed-precision forms (dtype FIP_BF16 .. FIP_BF16X3_FAST): MT = NT = 128
  * (256 for bfloat16, see FIP_ATTR_MX_TILE), KT = 64 (bfloat16), 128 (E4M3) or
  * 32 (split forms); blocks keep the operand's storage orientation as above
@@ -388,6 +395,15 @@ int fip_vbatched_tune(fip_handle_t handle, int layout, int64_t count, const int3
                       float alpha, const float* const* A, const int64_t* lda,
                       const float* const* B, const int64_t* ldb, float beta, float* const* C,
                       const int64_t* ldc, int* split_out);
+
+/*
+ * Diagnostic (host only, no HIP call): the tile that workgroup w of a launch
+ * over tiles_m x tiles_n C tiles computes, for tile order 0 or 1 (see
+ * FIP_ATTR_ORDER): tm[w], tn[w] for w = 0 .. tiles_m*tiles_n - 1 (host
+ * arrays).  The tile kernels use this same map.
+ * Positions: tiles_m 1, tiles_n 2, order 3, tm 4, tn 5.
+ */
+int fip_tile_map(int64_t tiles_m, int64_t tiles_n, int order, int32_t* tm, int32_t* tn);
 
 /*
  * Diagnostic: launch nblocks one-wave workgroups; workgroup b writes the

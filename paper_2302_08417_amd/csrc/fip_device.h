@@ -63,9 +63,15 @@ __device__ __forceinline__ void acquire_packed() { __builtin_amdgcn_fence(__ATOM
 // of the panels an XCD packs private to it.
 //   order 0: inside a band, the GROUP_M tiles of one column are consecutive;
 //   order 1: inside a band, consecutive tiles take distinct columns (round r,
-//            slot s -> column s, row (s + r) mod GROUP_M), so the first round of
-//            workgroups touches every column panel of the band once and later
-//            rounds find them all packed.
+//            slot s -> column (s + rot) mod tilesN, row (s + r) mod GROUP_M), so
+//            the first round of workgroups touches every column panel of the
+//            band once and later rounds find them all packed.  rot staggers the
+//            bands' sweeps by the XCD whose run starts the band (band start *
+//            8 / tiles, times tilesN / 8): the XCDs start on different bands, so
+//            with one pack copy shared by all XCDs the workgroups running at
+//            once spread over the column panels instead of all XCDs reading the
+//            same unpublished ones.  A band keeps one rotation, so the map stays
+//            one-to-one.
 __host__ __device__ inline void tile_coords(int w, int tilesM, int tilesN, int group_m, int order,
                                             int& tm, int& tn)
 {
@@ -83,7 +89,9 @@ __host__ __device__ inline void tile_coords(int w, int tilesM, int tilesN, int g
         tn = rem / gsize;
     } else {
         const int round = rem / tilesN, slot = rem - round * tilesN;
-        tn = slot;
+        const int64_t starter = ((int64_t)g * per_group * 8) / T;   // 0..7
+        const int rot = (int)((starter * tilesN) >> 3);
+        tn = slot + rot < tilesN ? slot + rot : slot + rot - tilesN;
         tm = first_m + (slot + round) % gsize;
     }
 }

@@ -36,6 +36,7 @@ struct LaunchDesc {
     int mode;              // Mode
     int pack_a, pack_b;    // fused mode: operand packed on first touch
     int a_pack_from, b_pack_from;  // ... from this tile row / column on (0: every panel)
+    int shared_copy;       // 1: one pack copy shared by all XCDs, else one per XCD
     int no_publish, stats;
     int order;             // tile order inside an XCD's run (0 grouped, 1 rounds)
     int64_t M, N, K;
@@ -94,6 +95,7 @@ struct MxLaunchDesc {
     int mode;              // Mode
     int pack_a, pack_b, no_publish, stats, order;
     int a_pack_from, b_pack_from;  // first packed tile row / column (0: every panel)
+    int shared_copy;               // 1: one pack copy for all XCDs
     int c_bf16;            // C stored as bfloat16 (else binary32)
     int64_t M, N, K;       // kernel terms (C column-major M x N)
     const void* A; int64_t a_ld; int a_kmajor;   // element (x, p): K-major X[x*ld + p],

@@ -84,6 +84,7 @@ struct fip_handle_s {
     int vb_split;     // FIP_ATTR_VB_SPLIT (-1: tuned or default)
     int mx_tile;      // FIP_ATTR_MX_TILE (-1: planner's choice, 128, 256)
     int split_k;      // FIP_ATTR_SPLIT_K (-1: planner's choice, 1: off, 2..64: forced)
+    int copies;       // FIP_ATTR_COPIES (-1: planner's choice, 1 or 8)
     int last_hip_error;  // FIP_ATTR_LAST_HIP_ERROR
     VbState* vb;
 };
@@ -188,6 +189,7 @@ struct Plan {
     int mode;
     int kpack_a, kpack_b;           // packing in kernel terms
     int kfrom_a, kfrom_b;           // first packed tile row / column (kernel terms)
+    int shared_copy;                // one pack copy for all XCDs
     int64_t tilesKM, tilesKN, nK;
     int64_t off_stats, off_aflag, off_bflag, off_aclaim, off_bclaim, off_apack, off_bpack;
     int64_t apack_copy_elems, bpack_copy_elems;
@@ -321,8 +323,14 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
             // 4096^3, 4 rounds: 932 us packed, 773 unpacked; 8192^3, 16 rounds:
             // 6.5 ms packed, 7.4 unpacked).
             const bool split_form = form == fip::kMxX3 || form == fip::kMxX3Fast;
+            // One pack copy shared by all XCDs unless the attribute asks for one
+            // per XCD.  Per-XCD copies make every XCD produce its own copy of
+            // each panel it reads; for the split forms a producer costs about
+            // three packed tiles, which fewer than 5 rounds do not repay.
+            pl->shared_copy = h->copies != fip::kCopies;
             const bool later_passes =
-                pl->tilesKM * pl->tilesKN * pl->split > (split_form ? 4 : 1) * resident &&
+                pl->tilesKM * pl->tilesKN * pl->split >
+                    (split_form && !pl->shared_copy ? 4 : 1) * resident &&
                 pl->nK >= kMinPackKsteps;
             double fa = 0.0, fb = 0.0;
             if (later_passes)
@@ -357,7 +365,9 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
                 pl->kfrom_b = (int)pl->tilesKN - 1;
             }
         }
-        if (pl->kpack_a || pl->kpack_b) copies = fip::kCopies;
+        if (policy == FIP_PACK_ALL) pl->shared_copy = h->copies != fip::kCopies;
+        if (pl->kpack_a || pl->kpack_b) copies = pl->shared_copy ? 1 : fip::kCopies;
+        else pl->shared_copy = 0;
     }
     if (k == 0 || m == 0 || n == 0) { pl->kpack_a = pl->kpack_b = 0; copies = 0; }
     if (!pl->kpack_a) pl->kfrom_a = 0;
@@ -553,6 +563,7 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.mode = pl.mode;
         d.pack_a = pl.kpack_a; d.pack_b = pl.kpack_b;
         d.a_pack_from = pl.kfrom_a; d.b_pack_from = pl.kfrom_b;
+        d.shared_copy = pl.shared_copy;
         d.no_publish = h->no_publish;
         d.stats = noalloc ? 0 : h->stats;   // the scratch array's counters are never cleared
         d.order = pl.order;
@@ -590,6 +601,7 @@ void fill_mx_desc(const fip_handle_s* h, const Plan& pl, int form, int layout, i
     d->mode = pl.mode;
     d->pack_a = pl.kpack_a; d->pack_b = pl.kpack_b;
     d->a_pack_from = pl.kfrom_a; d->b_pack_from = pl.kfrom_b;
+    d->shared_copy = pl.shared_copy;
     d->no_publish = h->no_publish;
     d->stats = h->stats;
     d->order = pl.order;
@@ -887,6 +899,7 @@ int fip_create(fip_handle_t* handle)
     h->vb_split = -1;
     h->mx_tile = -1;
     h->split_k = -1;
+    h->copies = -1;
     h->vb = nullptr;
     *handle = h;
     return 0;
@@ -944,6 +957,10 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
         if (value != -1 && (value < 1 || value > kMaxSplit)) return 3;
         handle->split_k = (int)value;
         return 0;
+    case FIP_ATTR_COPIES:
+        if (value != -1 && value != 1 && value != fip::kCopies) return 3;
+        handle->copies = (int)value;
+        return 0;
     default:
         return 2;
     }
@@ -965,6 +982,7 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_VB_GRID: *value = fip::vbatched_grid(); return 0;
     case FIP_ATTR_MX_TILE: *value = handle->mx_tile; return 0;
     case FIP_ATTR_SPLIT_K: *value = handle->split_k; return 0;
+    case FIP_ATTR_COPIES: *value = handle->copies; return 0;
     case FIP_ATTR_VB_STATUS: {
         *value = 0;
         VbState* v = handle->vb;
@@ -1237,6 +1255,23 @@ int fip_vbatched_tune(fip_handle_t handle, int layout, int64_t count, const int3
     } catch (...) {
         return FIP_ERR_LAUNCH;
     }
+}
+
+int fip_tile_map(int64_t tiles_m, int64_t tiles_n, int order, int32_t* tm, int32_t* tn)
+{
+    if (tiles_m < 0 || tiles_m * tiles_n > ((int64_t)1 << 30)) return 1;
+    if (tiles_n < 0) return 2;
+    if (order != 0 && order != 1) return 3;
+    const int64_t T = tiles_m * tiles_n;
+    if (T > 0 && tm == nullptr) return 4;
+    if (T > 0 && tn == nullptr) return 5;
+    for (int64_t w = 0; w < T; ++w) {
+        int a, b;
+        fip::tile_coords((int)w, (int)tiles_m, (int)tiles_n, fip::kGroupM, order, a, b);
+        tm[w] = a;
+        tn[w] = b;
+    }
+    return 0;
 }
 
 int fip_xcc_map(fip_handle_t handle, uint32_t* d_out, int64_t nblocks)

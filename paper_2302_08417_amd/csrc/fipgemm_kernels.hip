@@ -46,6 +46,7 @@ struct Params {
     int tilesM, tilesN, nK, group_m;
     int mode, pack_a, pack_b, no_publish, do_stats;
     int a_pack_from, b_pack_from;  // first tile row / column whose panel is packed
+    int shared_copy;  // 1: one pack copy for all XCDs (copy 0), else one per XCD
     int a_vec, b_vec, c_vec;
     int a_fast, b_fast;  // interior chunks may use the 32-bit-offset vector loader
     int order;       // tile order inside an XCD's run: 0 grouped, 1 column-distinct rounds
@@ -107,7 +108,8 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     int copy = 0;
     if (fused) {
         const unsigned x = xcc_id();
-        if (x < (unsigned)kCopies) copy = (int)x;
+        if (P.shared_copy) copy = 0;
+        else if (x < (unsigned)kCopies) copy = (int)x;
         else fused = false;  // unknown XCD id: this workgroup stays unpacked
     }
     const bool useA = fused && P.pack_a && tm >= P.a_pack_from;
@@ -457,6 +459,7 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.group_m = kGroupM;
     P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
     P.a_pack_from = d.a_pack_from; P.b_pack_from = d.b_pack_from;
+    P.shared_copy = d.shared_copy;
     P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
     const int64_t a_far = d.a_kmajor ? d.a_smn : d.a_sk;  // the leading dimension
     const int64_t b_far = d.b_kmajor ? d.b_smn : d.b_sk;

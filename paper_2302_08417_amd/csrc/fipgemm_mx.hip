@@ -576,6 +576,7 @@ struct MxParams {
     int tilesM, tilesN, nK, group_m;
     int mode, pack_a, pack_b, no_publish, do_stats, order;
     int a_pack_from, b_pack_from;  // first tile row / column whose panel is packed
+    int shared_copy;  // 1: one pack copy for all XCDs (copy 0), else one per XCD
     int a_vec, b_vec;                // unpacked vector loads allowed (dword alignment)
     int c_bf16;
     int split, slice_ksteps;         // k slices (1: none) and k-steps per slice
@@ -799,7 +800,8 @@ gemm_mx_kernel(const MxParams P)
     int copy = 0;
     if (fused) {
         const unsigned x = xcc_id();
-        if (x < (unsigned)kCopies) copy = (int)x;
+        if (P.shared_copy) copy = 0;
+        else if (x < (unsigned)kCopies) copy = (int)x;
         else fused = false;
     }
     const bool useA = fused && P.pack_a && tm >= P.a_pack_from;
@@ -1306,6 +1308,7 @@ MxParams make_mx_params(const MxLaunchDesc& d, int MT)
     P.group_m = kGroupM;
     P.mode = d.mode; P.pack_a = d.pack_a; P.pack_b = d.pack_b;
     P.a_pack_from = d.a_pack_from; P.b_pack_from = d.b_pack_from;
+    P.shared_copy = d.shared_copy;
     P.no_publish = d.no_publish; P.do_stats = d.stats && d.stats_ptr != nullptr;
     P.order = d.order;
     // vector loads of the unpacked operand need every 4-byte group of a

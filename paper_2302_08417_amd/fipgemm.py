@@ -40,6 +40,7 @@ FIP_ATTR_MX_TILE = 10
 FIP_ATTR_SPLIT_K = 11
 FIP_ATTR_LAST_HIP_ERROR = 12
 FIP_ATTR_VB_STATUS = 13
+FIP_ATTR_COPIES = 14
 FIP_VB_GRAPH = 1
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
@@ -89,6 +90,7 @@ _SIGS = {
                   ctypes.c_float, _vp, _i64],
     "fip_pack": [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _ch, _vp, _i64, _ch],
     "fip_xcc_map": [_vp, _vp, _i64],
+    "fip_tile_map": [_i64, _i64, _i32, _vp, _vp],
     "fip_gemm_mx": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64,
                     _ch, ctypes.c_float, _vp, _i64, _i32, _vp, _vp],
     "fip_quantize_fp8": [_vp, _i32, _i64, _i64, _vp, _i64, _i32, _vp, _i64, _vp],
@@ -190,6 +192,16 @@ def fip_sgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C
 def fip_pack(h, dtype, layout, m, n, k, A, lda, transA, B, ldb, transB):
     return _lib.fip_pack(h, dtype, layout, m, n, k, _addr(A), lda, _trans(transA), _addr(B), ldb,
                          _trans(transB))
+
+
+def fip_tile_map(tiles_m, tiles_n, order):
+    """(rc, tm, tn): the workgroup -> tile map of a launch (host NumPy int32 arrays)."""
+    import numpy as np
+    T = max(tiles_m * tiles_n, 0)
+    tm = np.zeros(max(T, 1), dtype=np.int32)
+    tn = np.zeros(max(T, 1), dtype=np.int32)
+    rc = _lib.fip_tile_map(tiles_m, tiles_n, order, tm.ctypes.data, tn.ctypes.data)
+    return rc, tm[:T], tn[:T]
 
 
 def fip_xcc_map(h, out, nblocks):

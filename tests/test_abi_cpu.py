@@ -119,7 +119,8 @@ def _tile_of(w, tilesM, tilesN, order, group=8):
     if order == 0:
         return first + rem % gsize, rem // gsize
     rnd, slot = divmod(rem, tilesN)
-    return first + (slot + rnd) % gsize, slot
+    rot = ((g * group * tilesN * 8) // T) * tilesN >> 3
+    return first + (slot + rnd) % gsize, (slot + rot) % tilesN
 
 
 def _expected_pack(tilesM, tilesN, resident, order=0):
@@ -204,14 +205,22 @@ def test_single_round_launches_do_not_pack(h):
 def test_plan_layout_and_sizes(h):
     p = plan(h, 300, 200, 77, policy=F.FIP_PACK_ALL, tile=2)
     assert (p.tiles_m, p.tiles_n, p.ksteps, p.KT) == (10, 7, 5, 16)
-    assert p.copies == 8
+    assert p.copies == 1   # one copy shared by all XCDs by default
     assert p.a_copy_bytes == 10 * 5 * 16 * 32 * 8
     assert p.b_copy_bytes == 7 * 5 * 16 * 32 * 8
     offs = sorted([p.a_pack_offset, p.b_pack_offset, p.a_flag_offset, p.b_flag_offset,
                    p.a_claim_offset, p.b_claim_offset])
     assert all(o % 256 == 0 for o in offs)
-    assert p.a_pack_offset + 8 * p.a_copy_bytes <= p.workspace_bytes
-    assert p.b_pack_offset + 8 * p.b_copy_bytes <= p.workspace_bytes
+    assert p.a_pack_offset + p.a_copy_bytes <= p.workspace_bytes
+    assert p.b_pack_offset + p.b_copy_bytes <= p.workspace_bytes
+    # one copy per XCD on request
+    assert F.fip_set_attr(h, F.FIP_ATTR_COPIES, 8) == 0
+    p8 = plan(h, 300, 200, 77, policy=F.FIP_PACK_ALL, tile=2)
+    assert F.fip_set_attr(h, F.FIP_ATTR_COPIES, -1) == 0
+    assert p8.copies == 8 and p8.a_copy_bytes == p.a_copy_bytes
+    assert p8.a_pack_offset + 8 * p8.a_copy_bytes <= p8.workspace_bytes
+    assert p8.b_pack_offset + 8 * p8.b_copy_bytes <= p8.workspace_bytes
+    assert F.fip_set_attr(h, F.FIP_ATTR_COPIES, 2) == 3
     # row-major: the kernel swaps operand sides; the plan still speaks of op(A), op(B)
     q = plan(h, 300, 200, 77, layout=1, policy=F.FIP_PACK_ALL, tile=2)
     assert (q.tiles_m, q.tiles_n) == (10, 7)
@@ -293,7 +302,7 @@ def test_mx_plans(h, dtype, KT, planes, eb):
     # row-major: op(A) is the kernel's B side; sizes are reported in the caller's terms
     assert p.a_copy_bytes == 3 * nk * KT * 128 * planes * eb
     assert p.b_copy_bytes == 2 * nk * KT * 128 * planes * eb
-    assert p.copies == 8 and p.workspace_bytes >= 8 * (p.a_copy_bytes + p.b_copy_bytes)
+    assert p.copies == 1 and p.workspace_bytes >= p.a_copy_bytes + p.b_copy_bytes
     assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO) == 0
     rc, p = F.fip_plan(h, dtype, 0, 300, 200, 333, "N", "N")
     assert rc == 0 and p.workspace_bytes == 0      # one round of tiles: nothing to reuse
@@ -328,12 +337,17 @@ def test_mx_auto_pack_rule(h):
     for dtype in (F.FIP_BF16X3, F.FIP_BF16X3_FAST):
         rc, p = F.fip_plan(h, dtype, 0, 16384, 16384, 1024, "N", "N")
         assert rc == 0 and p.pack_a == 1
-        # 4096^2: 1024 tiles = 4 rounds of 256 resident workgroups: not enough to repay
-        # the per-XCD producer copies; 8192^2 (16 rounds) packs
+        # 4096^2: 1024 tiles = 4 rounds of 256 resident workgroups: with one copy shared by
+        # all XCDs that packs; with per-XCD copies it is not enough to repay every XCD's
+        # producers; 8192^2 (16 rounds) packs either way
+        rc, p = F.fip_plan(h, dtype, 0, 4096, 4096, 4096, "N", "N")
+        assert rc == 0 and p.pack_a == 1 and p.copies == 1
+        assert F.fip_set_attr(h, F.FIP_ATTR_COPIES, 8) == 0
         rc, p = F.fip_plan(h, dtype, 0, 4096, 4096, 4096, "N", "N")
         assert rc == 0 and (p.pack_a, p.pack_b) == (0, 0)
         rc, p = F.fip_plan(h, dtype, 0, 8192, 8192, 8192, "N", "N")
-        assert rc == 0 and p.pack_a == 1
+        assert rc == 0 and p.pack_a == 1 and p.copies == 8
+        assert F.fip_set_attr(h, F.FIP_ATTR_COPIES, -1) == 0
 
 
 def test_split_choice(h):
@@ -423,3 +437,21 @@ def test_vbatched_workspace_and_positions(h):
     assert F.fip_set_attr(h, F.FIP_ATTR_VB_SPLIT, 96) == 0
     assert F.fip_get_attr(h, F.FIP_ATTR_VB_SPLIT) == (0, 96)
     assert F.fip_set_attr(h, F.FIP_ATTR_VB_SPLIT, -2) == 3
+
+
+def test_tile_map_is_one_to_one_and_matches_replica():
+    """Every tile of a launch is computed by exactly one workgroup, in both tile orders and for
+    shapes whose bands straddle the XCDs' runs; the map equals the replica the planner tests
+    use."""
+    import numpy as np
+    shapes = [(1, 1), (3, 5), (8, 8), (9, 7), (32, 32), (64, 64), (128, 128), (17, 200),
+              (200, 17), (256, 64), (64, 256), (13, 1), (1, 13), (40, 33)]
+    for tM, tN in shapes:
+        for order in (0, 1):
+            rc, tm, tn = F.fip_tile_map(tM, tN, order)
+            assert rc == 0
+            ids = tm.astype(np.int64) * tN + tn
+            assert np.array_equal(np.sort(ids), np.arange(tM * tN)), (tM, tN, order)
+            for w in range(0, tM * tN, max(1, tM * tN // 97)):
+                assert (tm[w], tn[w]) == _tile_of(w, tM, tN, order), (tM, tN, order, w)
+    assert F.fip_tile_map(4, 4, 2)[0] == 3

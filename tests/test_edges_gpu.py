@@ -194,15 +194,15 @@ def _check_claimed_packs(F, h, c, items, pack_fn):
     for which, ntiles, off_pack, copy_bytes, off_claim, off_flag, args in items(p):
         ref = pack_fn(*args).view(np.uint8)
         assert ref.size == copy_bytes
-        claims = ws[off_claim: off_claim + 8 * F.COPIES * ntiles].cpu().numpy().view(np.uint64)
-        flags = ws[off_flag: off_flag + 8 * F.COPIES * ntiles].cpu().numpy().view(np.uint64)
-        claims = claims.reshape(F.COPIES, ntiles)
-        flags = flags.reshape(F.COPIES, ntiles)
-        packs = ws[off_pack: off_pack + F.COPIES * copy_bytes].cpu().numpy().reshape(F.COPIES, -1)
+        claims = ws[off_claim: off_claim + 8 * p.copies * ntiles].cpu().numpy().view(np.uint64)
+        flags = ws[off_flag: off_flag + 8 * p.copies * ntiles].cpu().numpy().view(np.uint64)
+        claims = claims.reshape(p.copies, ntiles)
+        flags = flags.reshape(p.copies, ntiles)
+        packs = ws[off_pack: off_pack + p.copies * copy_bytes].cpu().numpy().reshape(p.copies, -1)
         panel = copy_bytes // ntiles
         checked = 0
         for t in range(ntiles):
-            owners = [cp for cp in range(F.COPIES) if claims[cp, t] == epoch]
+            owners = [cp for cp in range(p.copies) if claims[cp, t] == epoch]
             assert owners, f"{which} panel {t} packed by nobody"
             for cp in owners:
                 assert flags[cp, t] == epoch

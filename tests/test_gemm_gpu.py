@@ -156,9 +156,10 @@ def test_special_cases(F, dtype):
     assert np.array_equal(C.cpu().numpy(), c.C, equal_nan=True)
 
 
-def _run_policy(F, c, policy, no_publish=0, ws=None, order=0, tile=-1, split=-1):
+def _run_policy(F, c, policy, no_publish=0, ws=None, order=0, tile=-1, split=-1, copies=-1):
     import torch
     h = handle(F, policy=policy, tile=tile)
+    h.set_attr(F.FIP_ATTR_COPIES, copies)
     h.set_attr(F.FIP_ATTR_NO_PUBLISH, no_publish)
     h.set_attr(F.FIP_ATTR_ORDER, order)
     h.set_attr(F.FIP_ATTR_SPLIT_K, split)
@@ -196,7 +197,8 @@ def test_modes_bitwise_identical(F, dtype, layout, tA, tB):
 
 @pytest.mark.parametrize("dtype,shape,tile", [(F64, (2048, 2048, 256), 2), (F32, (2048, 2048, 333), 2),
                                               (F64, (4096, 4096, 64), 0)])
-def test_fused_repeated_calls_bitwise(F, dtype, shape, tile):
+@pytest.mark.parametrize("copies", [1, 8], ids=["shared", "per-xcd"])
+def test_fused_repeated_calls_bitwise(F, dtype, shape, tile, copies):
     """Repeated fused calls on launches with several rounds of tiles (so later tiles do read
     packed panels) must equal the unpacked path bit for bit every time; the workspace is
     poisoned before each call.  Tile classes change the blocking only, so at the same k split
@@ -212,12 +214,13 @@ def test_fused_repeated_calls_bitwise(F, dtype, shape, tile):
     A, B = to_dev(c.A), to_dev(c.B)
     h = handle(F, policy=F.FIP_PACK_ALL, tile=tile)
     h.set_attr(F.FIP_ATTR_STATS, 1)
+    h.set_attr(F.FIP_ATTR_COPIES, copies)
     dt = F.FIP_F64 if dtype == F64 else F.FIP_F32
     p = h.plan(dt, COL, m, n, k, "N", "N")
     h.ensure_workspace(p.workspace_bytes)
     total_packed_reads = 0
     for trial in range(4):
-        say("repeat", dtype.__name__, shape, trial)
+        say("repeat", dtype.__name__, shape, copies, trial)
         h.workspace.fill_(0xFF)
         h.workspace[:64].zero_()
         C = to_dev(c.C)
@@ -236,11 +239,11 @@ def test_fused_repeated_calls_bitwise(F, dtype, shape, tile):
 @pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
 def test_graph_capture_replays_with_new_inputs(F, dtype):
     """A GEMM captured into a graph on a shape that packs when run eagerly (many rounds of 32 x
-    32 tiles) replays correctly while its inputs change between replays: under capture the
+    32 tiles, a fringe panel) replays correctly while its inputs change between replays: under capture the
     call is planned unpacked.  Eager work and synchronisations sit between the replays, and
     every replay is checked against the oracle for that replay's inputs."""
     import torch
-    m, n, k = 2048, 2048, 256
+    m, n, k = 2045, 2043, 256   # ragged: AUTO packs the fringe panel when run eagerly
     cases = [synth.make_case(COL, m, n, k, "N", "T", alpha=1.5, beta=0.5, dtype=dtype,
                              seed=300 + i) for i in range(4)]
     c0 = cases[0]
@@ -285,18 +288,20 @@ def _ws_u64(ws, off, count):
 @pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
 @pytest.mark.parametrize("layout,tA,tB,pad", [(COL, "N", "N", 0), (COL, "T", "N", 7),
                                               (ROW, "N", "T", 7), (ROW, "T", "T", 0)])
-def test_packed_buffers_bit_exact(F, dtype, layout, tA, tB, pad):
+@pytest.mark.parametrize("copies", [1, 8], ids=["shared", "per-xcd"])
+def test_packed_buffers_bit_exact(F, dtype, layout, tA, tB, pad, copies):
     """Every panel a producer claimed must equal the oracle's reference pack byte for byte,
-    and every panel must have been packed by some XCD (PACK_POLICY=ALL)."""
-    say("pack bits", dtype.__name__, layout, tA, tB, pad)
+    and every panel must have been packed (PACK_POLICY=ALL), with one copy shared by all XCDs
+    or one per XCD."""
+    say("pack bits", dtype.__name__, layout, tA, tB, pad, copies)
     m, n, k = 300, 200, 77
     c = synth.make_case(layout, m, n, k, tA, tB, ld_pad=pad, dtype=dtype, seed=17)
-    out, h = _run_policy(F, c, F.FIP_PACK_ALL)
+    out, h = _run_policy(F, c, F.FIP_PACK_ALL, copies=copies)
     check_full(c, out)
     p = h.last_plan()
     ws = h.workspace
     epoch = np.uint64(h.get_attr(F.FIP_ATTR_EPOCH))
-    assert p.pack_a and p.pack_b and p.copies == F.COPIES
+    assert p.pack_a and p.pack_b and p.copies == copies
     nk = p.ksteps
     for which, ntiles, mnt, off_pack, copy_bytes, off_claim, off_flag, X, ld, t, mn in [
             ("A", p.tiles_m, p.MT, p.a_pack_offset, p.a_copy_bytes, p.a_claim_offset,
@@ -305,11 +310,11 @@ def test_packed_buffers_bit_exact(F, dtype, layout, tA, tB, pad):
              p.b_flag_offset, c.B, c.ldb, tB, n)]:
         ref = oracle.pack(X, which == "B", layout, t, mn, k, ld, mnt, p.KT)
         ref_u8 = ref.view(np.uint8)
-        claims = _ws_u64(ws, off_claim, F.COPIES * ntiles).reshape(F.COPIES, ntiles)
-        flags = _ws_u64(ws, off_flag, F.COPIES * ntiles).reshape(F.COPIES, ntiles)
+        claims = _ws_u64(ws, off_claim, p.copies * ntiles).reshape(p.copies, ntiles)
+        flags = _ws_u64(ws, off_flag, p.copies * ntiles).reshape(p.copies, ntiles)
         assert np.all((claims == epoch).any(axis=0)), f"{which}: a panel was never packed"
         panel_bytes = nk * p.KT * mnt * c.A.itemsize
-        for cp in range(F.COPIES):
+        for cp in range(p.copies):
             base = off_pack + cp * copy_bytes
             buf = ws[base: base + copy_bytes].cpu().numpy()
             for t_ in range(ntiles):

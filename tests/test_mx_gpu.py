@@ -37,11 +37,12 @@ def dev(buf):
     return to_dev(buf)
 
 
-def run_mx(F, c, policy=0, order=0, no_publish=0, h=None, stats=0, tile=-1):
+def run_mx(F, c, policy=0, order=0, no_publish=0, h=None, stats=0, tile=-1, copies=-1):
     import torch
     own = h is None
     if own:
         h = F.Handle(policy=policy)
+    h.set_attr(F.FIP_ATTR_COPIES, copies)
     h.set_attr(F.FIP_ATTR_MX_TILE, tile)
     h.set_attr(F.FIP_ATTR_ORDER, order)
     h.set_attr(F.FIP_ATTR_NO_PUBLISH, no_publish)
@@ -106,7 +107,8 @@ def test_mx_modes_bitwise(F, form, layout, tA, tB):
     for pol, order, nopub in [(F.FIP_PACK_AUTO, 0, 0), (F.FIP_PACK_ALL, 0, 0),
                               (F.FIP_PACK_ALL, 1, 0), (F.FIP_PACK_ALL, 0, 1),
                               (F.FIP_PACK_CONSUME_ONLY, 0, 0)]:
-        out, h = run_mx(F, c, pol, order=order, no_publish=nopub, stats=1)
+        out, h = run_mx(F, c, pol, order=order, no_publish=nopub, stats=1,
+                        copies=8 if order == 1 else -1)
         if pol == F.FIP_PACK_ALL and not nopub:
             p = h.last_plan()
             st = h.workspace[p.stats_offset: p.stats_offset + 32].cpu().numpy().view(np.uint64)
@@ -140,12 +142,15 @@ def test_mx_big_tile_matches_oracle(F, form, tile, layout, tA, tB, c_bf16):
                          ids=[i + "-128" for i in FORM_IDS] + ["bf16-256"])
 @pytest.mark.parametrize("layout,tA,tB", [(COL, "N", "N"), (COL, "T", "T"), (ROW, "N", "T"),
                                           (ROW, "T", "N")])
-def test_mx_packed_buffers_bit_exact(F, form, tile, layout, tA, tB):
+@pytest.mark.parametrize("copies", [1, 8], ids=["shared", "per-xcd"])
+def test_mx_packed_buffers_bit_exact(F, form, tile, layout, tA, tB, copies):
     """Every claimed and published panel equals the oracle's reference pack byte for byte
-    (K-major planes; the split forms hold the bfloat16 terms)."""
-    say("mx pack bits", form, tile, layout, tA, tB)
+    (K-major planes; the split forms hold the bfloat16 terms), with one shared copy or one
+    per XCD."""
+    say("mx pack bits", form, tile, layout, tA, tB, copies)
     c = synth.make_mx_case(form, layout, 600, 400, 170, tA, tB, ld_pad=4, seed=19 + form)
-    out, h = run_mx(F, c, F.FIP_PACK_ALL, tile=tile)
+    out, h = run_mx(F, c, F.FIP_PACK_ALL, tile=tile, copies=copies)
+    assert h.last_plan().copies == copies
     check_mx(c, out)
     p = h.last_plan()
     ws = h.workspace
@@ -158,14 +163,14 @@ def test_mx_packed_buffers_bit_exact(F, form, tile, layout, tA, tB):
              p.b_flag_offset, c.B, c.ldb, tB, c.n, 1)]:
         exp = oracle.pack_mx(form, X, is_b, layout, t, mn, c.k, ld, mnt)
         assert exp.size == copy_bytes
-        packs = ws[off_pack: off_pack + F.COPIES * copy_bytes].cpu().numpy().reshape(F.COPIES, -1)
-        claims = ws[off_claim: off_claim + 8 * F.COPIES * ntiles].cpu().numpy().view(np.uint64)
-        flags = ws[off_flag: off_flag + 8 * F.COPIES * ntiles].cpu().numpy().view(np.uint64)
-        claims = claims.reshape(F.COPIES, ntiles)
-        flags = flags.reshape(F.COPIES, ntiles)
+        packs = ws[off_pack: off_pack + p.copies * copy_bytes].cpu().numpy().reshape(p.copies, -1)
+        claims = ws[off_claim: off_claim + 8 * p.copies * ntiles].cpu().numpy().view(np.uint64)
+        flags = ws[off_flag: off_flag + 8 * p.copies * ntiles].cpu().numpy().view(np.uint64)
+        claims = claims.reshape(p.copies, ntiles)
+        flags = flags.reshape(p.copies, ntiles)
         panel = exp.size // ntiles
         for tt in range(ntiles):
-            owners = [cp for cp in range(F.COPIES) if claims[cp, tt] == epoch]
+            owners = [cp for cp in range(p.copies) if claims[cp, tt] == epoch]
             assert owners, f"{which} panel {tt} packed by nobody"
             for cp in owners:
                 assert flags[cp, tt] == epoch, f"{which} copy {cp} panel {tt} unpublished"

@@ -194,11 +194,11 @@ def test_split_packed_chunks_bit_exact(F, dtype):
             ("B", p.tiles_n, p.NT, p.b_pack_offset, p.b_copy_bytes, p.b_claim_offset,
              p.b_flag_offset, c.B, c.ldb, "N", n)]:
         ref = oracle.pack(X, which == "B", c.layout, t, mn, k, ld, mnt, p.KT).view(np.uint8)
-        claims = u64(off_claim, F.COPIES * ntiles * S).reshape(F.COPIES, ntiles, S)
-        flags = u64(off_flag, F.COPIES * ntiles * S).reshape(F.COPIES, ntiles, S)
+        claims = u64(off_claim, p.copies * ntiles * S).reshape(p.copies, ntiles, S)
+        flags = u64(off_flag, p.copies * ntiles * S).reshape(p.copies, ntiles, S)
         assert np.all((claims == epoch).any(axis=0)), f"{which}: a (panel, slice) never packed"
         chunk_bytes = p.KT * mnt * c.A.itemsize
-        for cp in range(F.COPIES):
+        for cp in range(p.copies):
             buf = ws[off_pack + cp * copy_bytes: off_pack + (cp + 1) * copy_bytes].cpu().numpy()
             for t_ in range(ntiles):
                 for sl in range(S):
@@ -336,10 +336,10 @@ def test_mx_split_packed_chunks_bit_exact(F, form):
         ref = oracle.pack_mx(form, X, is_b, c.layout, t, mn, k, ld, p.MT)
         assert ref.size == copy_bytes
         chunk_bytes = copy_bytes // (ntiles * nk)
-        claims = u64(off_claim, F.COPIES * ntiles * S).reshape(F.COPIES, ntiles, S)
-        flags = u64(off_flag, F.COPIES * ntiles * S).reshape(F.COPIES, ntiles, S)
+        claims = u64(off_claim, p.copies * ntiles * S).reshape(p.copies, ntiles, S)
+        flags = u64(off_flag, p.copies * ntiles * S).reshape(p.copies, ntiles, S)
         assert np.all((claims == epoch).any(axis=0)), f"{which}: a (panel, slice) never packed"
-        for cp in range(F.COPIES):
+        for cp in range(p.copies):
             buf = ws[off_pack + cp * copy_bytes: off_pack + (cp + 1) * copy_bytes].cpu().numpy()
             for t_ in range(ntiles):
                 for sl in range(S):

@@ -74,8 +74,8 @@ def test_fringe_panels_only(F, dtype, layout, tA, tB):
         refpack = oracle.pack(X, is_b, layout, t, mn, k, ld, mnt, p.KT).view(np.uint8)
         panel = refpack.size // ntiles
         assert copy_bytes == panel
-        claims = _u64(ws, off_claim, F.COPIES * ntiles).reshape(F.COPIES, ntiles)
-        flags = _u64(ws, off_flag, F.COPIES * ntiles).reshape(F.COPIES, ntiles)
+        claims = _u64(ws, off_claim, p.copies * ntiles).reshape(p.copies, ntiles)
+        flags = _u64(ws, off_flag, p.copies * ntiles).reshape(p.copies, ntiles)
         assert not (claims[:, :first] == epoch).any(), "an interior panel was claimed"
         owners = np.flatnonzero(claims[:, first] == epoch)
         assert owners.size >= 1

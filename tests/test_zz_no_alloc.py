@@ -30,11 +30,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def _both(F, c, policy, split=-1):
+def _both(F, c, policy, split=-1, copies=-1):
     """C from fip_dgemm (a handle with its own workspace) and from fip_dgemm_noalloc."""
     import torch
     h = F.Handle(policy=policy)
     h.set_attr(F.FIP_ATTR_SPLIT_K, split)
+    h.set_attr(F.FIP_ATTR_COPIES, copies)
     A, B = to_dev(c.A), to_dev(c.B)
     C1, C2 = to_dev(c.C), to_dev(c.C)
     h.gemm(c.layout, c.m, c.n, c.k, c.alpha, A, c.lda, c.transA, B, c.ldb, c.transB, c.beta,
@@ -42,6 +43,7 @@ def _both(F, c, policy, split=-1):
     plan_ws = h.last_plan()
     h2 = F.Handle(policy=policy)
     h2.set_attr(F.FIP_ATTR_SPLIT_K, split)
+    h2.set_attr(F.FIP_ATTR_COPIES, copies)
     h2.bind_stream()
     rc = F.fip_dgemm_noalloc(h2.h, c.layout, c.m, c.n, c.k, c.alpha, A, c.lda, c.transA, B,
                              c.ldb, c.transB, c.beta, C2, c.ldc)
@@ -82,12 +84,13 @@ def test_noalloc_split_k_then_smaller(F):
 
 
 def test_noalloc_large_call_runs_unpacked_with_same_bits(F):
-    """A packed plan larger than the array (pack everything at 4096^2) runs unpacked: C equals
-    the workspace entry point's bit for bit (the policies share the kernel and k order)."""
+    """A packed plan larger than the array (pack everything at 4096^2, one copy per XCD) runs
+    unpacked: C equals the workspace entry point's bit for bit (the policies share the kernel
+    and k order)."""
     n = 4096
     c = synth.make_case(COL, n, n, 512, "N", "N", alpha=1.5, beta=0.5, dtype=np.float64, seed=85)
     say("large", n)
-    ref, got, p1, p2 = _both(F, c, 1)
+    ref, got, p1, p2 = _both(F, c, 1, copies=8)
     assert p1.workspace_bytes > F.SCRATCH_BYTES
     assert (p2.pack_a, p2.pack_b) == (0, 0)
     assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
