@@ -64,6 +64,12 @@ def lib():
         L.oracle_quantize_fp8.argtypes = [ctypes.c_int, i64, i64, vp, i64, ctypes.c_int, u8p, i64,
                                           vp]
         L.oracle_quantize_fp8.restype = None
+        L.oracle_syrk.argtypes = [ctypes.c_int, ch, ch, i64, i64, dbl, vp, i64, dbl, vp, i64,
+                                  vp, vp]
+        L.oracle_syrk.restype = None
+        L.oracle_trmm.argtypes = [ctypes.c_int, ch, ch, ch, ch, i64, i64, dbl, vp, i64, vp, i64,
+                                  dbl, vp, i64, vp, vp]
+        L.oracle_trmm.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -258,3 +264,30 @@ def mx_values(form, X, scale=None, scale_axis_len=None):
     if form == 3:
         return e4m3_decode(X)
     return np.asarray(X, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Other level-3 operations (fip_oracle_l3.c)
+
+def syrk(layout, uplo, trans, n, k, alpha, A, lda, beta, C0, ldc):
+    """(Cref, D) in C's storage: the uplo triangle of alpha op(A) op(A)^T + beta C0 (op(A)
+    n x k); every other entry of Cref is C0's (binary64), of D zero."""
+    A64, C64 = _f64(A), _f64(C0)
+    Cref = C64.copy()
+    D = np.zeros_like(C64)
+    lib().oracle_syrk(layout, _t(uplo), _t(trans), n, k, float(alpha), _ptr(A64), lda,
+                      float(beta), _ptr(C64), ldc, _ptr(Cref), _ptr(D))
+    return Cref, D
+
+
+def trmm(layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb, beta, C0, ldc):
+    """(Cref, D) in C's storage: alpha op(T) B + beta C0 (side 'L') or alpha B op(T) + beta C0
+    (side 'R'), T the uplo triangle of A (unit diagonal for diag 'U'); entries of Cref outside
+    the m x n result are C0's."""
+    A64, B64, C64 = _f64(A), _f64(B), _f64(C0)
+    Cref = C64.copy()
+    D = np.zeros_like(C64)
+    lib().oracle_trmm(layout, _t(side), _t(uplo), _t(transA), _t(diag), m, n, float(alpha),
+                      _ptr(A64), lda, _ptr(B64), ldb, float(beta), _ptr(C64), ldc, _ptr(Cref),
+                      _ptr(D))
+    return Cref, D
