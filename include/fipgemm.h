@@ -293,6 +293,62 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
              const void* A, int64_t lda, char transA, const void* B, int64_t ldb, char transB);
 
 /*
+ * Other level-3 operations through the same fused-pack tile kernel (paper
+ * Sec. 2.2: BLIS casts every level-3 operation onto one packing and
+ * microkernel layer; Sec. 5: fused packing for those operations).  binary64
+ * (d) and binary32 (s); conventions, quick returns and errors as fip_dgemm.
+ *
+ * SYRK:  C := alpha * op(A) * op(A)^T + beta * C on the uplo triangle of the
+ *        n x n matrix C ('L': row >= column, 'U': row <= column); the other
+ *        triangle is neither read nor written.  op(A) is n x k: A for trans
+ *        'N', A^T for 'T'/'C'.  Only the tiles of the triangle are launched;
+ *        both operand sides of a tile read the one op(A), whose panels are
+ *        claimed, packed and published once for both roles.
+ *        lda >= max(1, (column-major) == (trans 'N') ? n : k); ldc >= max(1, n).
+ *        Positions: layout 2, uplo 3, trans 4, n 5, k 6, alpha 7, A 8, lda 9,
+ *        beta 10, C 11, ldc 12.
+ * TRMM (out of place, with beta):
+ *        C := alpha * op(T) * B + beta * C   (side 'L', T m x m), or
+ *        C := alpha * B * op(T) + beta * C   (side 'R', T n x n),
+ *        B and C m x n; T is the uplo triangle of the stored A ('L': row >=
+ *        column, 'U': row <= column), its diagonal taken as 1 and not read when
+ *        diag is 'U'; A's other triangle is not read.  Chunks of the triangular
+ *        operand that meet the diagonal get the triangle applied in registers
+ *        (zeros elsewhere, ones on a unit diagonal), its all-zero k-steps are
+ *        skipped, and its pack holds op(T) with the triangle applied; the dense
+ *        B is never packed.  Structural zeros inside a diagonal chunk are
+ *        multiplied as +0.0 (an Inf or NaN in B meeting one gives NaN where the
+ *        BLAS definition, which never multiplies them, would not).
+ *        lda >= max(1, side 'L' ? m : n); ldb, ldc >= max(1, column-major ? m : n).
+ *        Positions: layout 2, side 3, uplo 4, transA 5, diag 6, m 7, n 8,
+ *        alpha 9, A 10, lda 11, B 12, ldb 13, beta 14, C 15, ldc 16.
+ * Packing policies: AUTO and ALL as for fip_dgemm (for AUTO, Sec. 3.3's rule
+ * on the one packable operand); NONE never packs; CONSUME_ONLY runs unpacked
+ * (there is no standalone pack for these operations).  Split k is not used.
+ */
+enum { FIP_OP_SYRK = 1, FIP_OP_TRMM = 2 };
+int fip_dsyrk(fip_handle_t handle, int layout, char uplo, char trans, int64_t n, int64_t k,
+              double alpha, const double* A, int64_t lda, double beta, double* C, int64_t ldc);
+int fip_ssyrk(fip_handle_t handle, int layout, char uplo, char trans, int64_t n, int64_t k,
+              float alpha, const float* A, int64_t lda, float beta, float* C, int64_t ldc);
+int fip_dtrmm(fip_handle_t handle, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, double alpha, const double* A, int64_t lda, const double* B,
+              int64_t ldb, double beta, double* C, int64_t ldc);
+int fip_strmm(fip_handle_t handle, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, float alpha, const float* A, int64_t lda, const float* B,
+              int64_t ldb, float beta, float* C, int64_t ldc);
+/*
+ * Plan of a SYRK (op FIP_OP_SYRK: n, k; side and diag ignored) or TRMM
+ * (FIP_OP_TRMM: m, n; k ignored) call: tile class, pack decision and
+ * workspace bytes (FIP_F64 or FIP_F32).  The plan's "A" is op(A) (SYRK; its
+ * "B" is the same pack) or the triangular matrix (TRMM).  No HIP call.
+ * Positions: op 2, dtype 3, layout 4, side 5, uplo 6, trans 7, diag 8, m 9,
+ * n 10, k 11, plan 12.
+ */
+int fip_plan_l3(fip_handle_t handle, int op, int dtype, int layout, char side, char uplo,
+                char trans, char diag, int64_t m, int64_t n, int64_t k, fip_plan_t* plan);
+
+/*
  * Mixed-precision GEMM (paper Sec. 5: the fused packing carried over to other
  * precisions; the pack is where operands are converted):
  *

@@ -18,6 +18,15 @@ enum Mode : int32_t {
     kModeUnpacked = 2,     // never pack
 };
 
+// Operations the FP64/FP32 tile kernel runs (LaunchDesc::kind).
+enum Kind : int32_t {
+    kGemm = 0,   // C := alpha op(A) op(B) + beta C
+    kSyrk = 1,   // one triangle of alpha op(A) op(A)^T + beta C: the tiles of that
+                 // triangle only; A and B sides are the same operand sharing one pack
+    kTrmm = 2,   // C := alpha op(T) B + beta C or alpha B op(T) + beta C, T triangular:
+                 // one side's chunks masked to the triangle, its zero k-steps skipped
+};
+
 // Tile rows per band of the XCD-aware tile order (see tile_coords).
 constexpr int kGroupM = 8;
 
@@ -54,6 +63,12 @@ struct LaunchDesc {
     // split k: `split` slices of `slice_ksteps` k-steps each (split = 1: none)
     int split, slice_ksteps;
     void* part;                         // slice partials [split][N][M] (column-major)
+    // level-3 operations other than GEMM (Kind), in kernel terms
+    int kind;
+    int tri_upper;     // SYRK: the stored triangle of kernel C is row <= column
+    int tri_side;      // TRMM: 1 = the kernel's A side is triangular, 2 = the B side
+    int tri_keep_ge;   // TRMM: the triangular side keeps element (x, p) with x >= p (else x <= p)
+    int tri_unit;      // TRMM: unit diagonal
     hipStream_t stream;
 };
 

@@ -148,6 +148,29 @@ struct Chunk {
         }
     }
 
+    // Triangle of a TRMM operand, applied in registers: element (x, p) of the
+    // chunk at (x0, p0) is kept when x >= p (keep_ge) or x <= p, else +0.0;
+    // with unit, the diagonal x == p inside the MN x K operand is 1 (the zero
+    // padding outside it stays +0.0).  Vector element e runs along MN
+    // (MN-major) or along k (K-major).
+    __device__ __forceinline__ void mask_tri(int64_t x0, int64_t p0, int keep_ge, int unit,
+                                             int64_t MN, int64_t K, int tid)
+    {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int o = elem_o(i, tid);
+            const int64_t xb = x0 + x_of(o), pb = p0 + p_of(o);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int64_t x = xb + (KC ? 0 : e), p = pb + (KC ? e : 0);
+                const bool keep = keep_ge ? x >= p : x <= p;
+                T v = keep ? r[i][e] : T(0);
+                if (unit && x == p && x < MN && p < K) v = T(1);
+                r[i][e] = v;
+            }
+        }
+    }
+
     // Packed source: one contiguous, zero-padded chunk; always vector loads.
     __device__ __forceinline__ void load_packed(const T* __restrict__ chunk, int tid)
     {

@@ -683,6 +683,285 @@ int gemm_mx_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, in
     }
 }
 
+// ---- other level-3 operations: SYRK and TRMM -------------------------------------
+
+bool valid_uplo(char u) { return u == 'L' || u == 'l' || u == 'U' || u == 'u'; }
+bool valid_side(char c) { return c == 'L' || c == 'l' || c == 'R' || c == 'r'; }
+bool valid_diag(char c) { return c == 'N' || c == 'n' || c == 'U' || c == 'u'; }
+bool is_lower(char u) { return u == 'L' || u == 'l'; }
+bool is_left(char c) { return c == 'L' || c == 'l'; }
+bool is_unit(char c) { return c == 'U' || c == 'u'; }
+
+// One SYRK or TRMM call in kernel terms (column-major kernel C, see the
+// operation's entry point for how the caller's storage maps onto it).
+struct L3Shape {
+    int kind;
+    int64_t M, N, K;
+    int tri_side;       // TRMM: 1 = kernel A side triangular, 2 = B side
+    int tri_keep_ge, tri_unit, tri_upper;
+    bool a_mn, b_mn;    // kernel operands MN-major
+};
+
+// Plan of a SYRK / TRMM call: the GEMM planner's tile class, no split k, and
+// Sec. 3.3's rule for the one operand that may be packed (SYRK: the single
+// operand, whose pack both sides read; TRMM: the triangular one, whose chunks
+// the pack holds with the triangle applied; the dense TRMM operand is never
+// packed, because tiles with different k-ranges read different parts of its
+// panels).  pub reports the caller's A as op(A) (SYRK) or the triangular matrix.
+void make_plan_l3(const fip_handle_s* h, int dtype, const L3Shape& ls, Plan* pl)
+{
+    memset(pl, 0, sizeof(*pl));
+    pl->elem = dtype == FIP_F64 ? 8 : 4;
+    const int cls = h->tile_override >= 0 ? h->tile_override : choose_tile_class(ls.M, ls.N);
+    const int MT = fip::tile_mt(cls), KT = fip::tile_kt(cls, pl->elem);
+    const int64_t resident = resident_tiles(cls);
+    pl->ks = KernelShape{ls.M, ls.N, false};
+    pl->tilesKM = cdiv(ls.M, MT);
+    pl->tilesKN = cdiv(ls.N, MT);
+    pl->nK = cdiv(ls.K, KT);
+    pl->split = 1;
+    pl->slice_ksteps = (int)pl->nK;
+    pl->order = 0;
+    const int64_t tiles = ls.kind == fip::kSyrk ? pl->tilesKM * (pl->tilesKM + 1) / 2
+                                                : pl->tilesKM * pl->tilesKN;
+    int policy = h->policy;
+    if ((policy == FIP_PACK_AUTO || policy == FIP_PACK_ALL) && stream_capturing(h->stream))
+        policy = FIP_PACK_NONE;
+    // the packable operand in kernel terms: SYRK and side-L TRMM the A side
+    const bool on_a = ls.kind == fip::kSyrk || ls.tri_side == 1;
+    const int64_t ext = on_a ? ls.M : ls.N, ptiles = on_a ? pl->tilesKM : pl->tilesKN;
+    int pk = 0, from = 0;
+    if (ls.K > 0 && ls.M > 0 && ls.N > 0) {
+        if (policy == FIP_PACK_ALL) {
+            pk = 1;
+        } else if (policy == FIP_PACK_AUTO) {
+            // reused by later rounds, a k-loop of at least kMinPackKsteps, and
+            // (the stride rule) only the fringe panel, whose unpacked chunks
+            // take the masked loads
+            pk = tiles > resident && pl->nK >= kMinPackKsteps && ptiles > 1 && ext % MT != 0;
+            from = (int)ptiles - 1;
+        }
+    }
+    if (!pk) from = 0;
+    pl->mode = policy == FIP_PACK_NONE ? fip::kModeUnpacked : fip::kModeFused;
+    pl->shared_copy = h->copies != fip::kCopies;
+    const int copies = pk ? (pl->shared_copy ? 1 : fip::kCopies) : 0;
+    pl->kpack_a = on_a && pk;
+    pl->kpack_b = (!on_a || ls.kind == fip::kSyrk) && pk;
+    pl->kfrom_a = pl->kfrom_b = from;
+    int64_t off = 0;
+    pl->off_stats = off; off = align256(off + 4 * 8);
+    const int64_t flags = pk ? copies * ptiles * 8 : 0;
+    pl->off_aflag = off; off = align256(off + flags);
+    pl->off_aclaim = off; off = align256(off + flags);
+    const int64_t copy_elems = pk ? (ptiles - from) * pl->nK * KT * MT : 0;
+    pl->off_apack = off; off = align256(off + copies * copy_elems * pl->elem);
+    // one set of flags, claims and pack serves whichever side is packed
+    pl->off_bflag = pl->off_aflag; pl->off_bclaim = pl->off_aclaim; pl->off_bpack = pl->off_apack;
+    pl->apack_copy_elems = pl->kpack_a ? copy_elems : 0;
+    pl->bpack_copy_elems = pl->kpack_b ? copy_elems : 0;
+    pl->off_part = off;
+
+    fip_plan_t& p = pl->pub;
+    p.dtype = dtype;
+    p.m = ls.kind == fip::kSyrk ? ls.M : 0;
+    p.k = ls.K;
+    p.MT = p.NT = MT; p.KT = KT;
+    p.tiles_m = (int32_t)pl->tilesKM; p.tiles_n = (int32_t)pl->tilesKN;
+    p.ksteps = (int32_t)pl->nK;
+    p.tile_class = cls;
+    p.pack_a = pk; p.pack_b = ls.kind == fip::kSyrk ? pk : 0;
+    p.a_pack_first = from; p.b_pack_first = ls.kind == fip::kSyrk ? from : 0;
+    p.copies = copies;
+    p.policy = policy;
+    p.a_kmajor = on_a ? !ls.a_mn : !ls.b_mn;
+    p.b_kmajor = ls.kind == fip::kSyrk ? !ls.a_mn : (on_a ? !ls.b_mn : !ls.a_mn);
+    p.a_pack_offset = pl->off_apack; p.a_copy_bytes = copy_elems * pl->elem;
+    p.b_pack_offset = pl->off_apack; p.b_copy_bytes = ls.kind == fip::kSyrk ? copy_elems * pl->elem : 0;
+    const bool fl = pk && pl->mode == fip::kModeFused;
+    p.a_flag_offset = fl ? pl->off_aflag : -1; p.b_flag_offset = p.a_flag_offset;
+    p.a_claim_offset = fl ? pl->off_aclaim : -1; p.b_claim_offset = p.a_claim_offset;
+    p.stats_offset = pl->off_stats;
+    p.workspace_bytes = pk ? off : 0;
+    p.split_k = 1;
+    p.slice_ksteps = (int32_t)pl->nK;
+    p.partial_offset = -1;
+}
+
+// SYRK in kernel terms.  Row-major storage is the column-major view of the
+// transposed matrices: op(A) keeps its strides and C's view holds the other
+// triangle (the product is symmetric).
+L3Shape syrk_shape(int layout, char uplo, char trans, int64_t n, int64_t k)
+{
+    L3Shape ls{};
+    ls.kind = fip::kSyrk;
+    ls.M = ls.N = n;
+    ls.K = k;
+    const bool lower = is_lower(uplo) != (layout == FIP_ROW_MAJOR);
+    ls.tri_upper = !lower;
+    ls.a_mn = ls.b_mn = mn_major(false, layout, trans);
+    return ls;
+}
+
+// TRMM in kernel terms.  Row-major storage is the column-major view of the
+// transposed matrices: the side and the triangle swap and m, n exchange.  On
+// the column-major views, side L computes op(T) B (T on the kernel A side,
+// element (x, p) = op(T)[x, p]) and side R computes B op(T) (T on the B side,
+// element (p, x) = op(T)[p, x]); T's stored (row, col) is (x, p) or (p, x)
+// depending on the transpose, so the kept triangle is x >= p exactly when
+// lower XOR transposed (side L), or its negation (side R).
+L3Shape trmm_shape(int layout, char side, char uplo, char transA, char diag, int64_t m, int64_t n)
+{
+    L3Shape ls{};
+    ls.kind = fip::kTrmm;
+    const bool row = layout == FIP_ROW_MAJOR;
+    const bool left = is_left(side) != row, lower = is_lower(uplo) != row;
+    const bool tr = is_trans(transA);
+    ls.M = row ? n : m;
+    ls.N = row ? m : n;
+    ls.K = left ? ls.M : ls.N;
+    ls.tri_side = left ? 1 : 2;
+    ls.tri_keep_ge = left ? (lower != tr) : !(lower != tr);
+    ls.tri_unit = is_unit(diag);
+    // kernel operands: T (column-major view, element (r, c) at A[r + c*lda]) and
+    // B's column-major view (element (r, c) at B[r + c*ldb])
+    if (left) {
+        ls.a_mn = !tr;   // op(T)[x, p]: A[x + p*lda] ('N'), A[p + x*lda] ('T')
+        ls.b_mn = false; // B[p + x*ldb]: K-major
+    } else {
+        ls.a_mn = true;  // B[x + p*ldb]: MN-major
+        ls.b_mn = tr;    // op(T)[p, x]: A[p + x*lda] ('N', K-major), A[x + p*lda] ('T')
+    }
+    return ls;
+}
+
+template <typename T>
+int run_l3(fip_handle_t h, int dtype, const L3Shape& ls, T alpha, const T* A, int64_t lda,
+           const T* B, int64_t ldb, T beta, T* C, int64_t ldc)
+{
+    const bool no_ab = alpha == T(0) || ls.K == 0;
+    L3Shape run = ls;
+    if (no_ab) run.K = 0;   // C := beta*C on the computed entries, A and B not read
+    Plan pl;
+    make_plan_l3(h, dtype, run, &pl);
+    if (const int ws = prepare_workspace(h, pl); ws) return ws;
+    fip::LaunchDesc d;
+    memset(&d, 0, sizeof(d));
+    d.elem = sizeof(T);
+    d.tile_class = pl.pub.tile_class;
+    d.mode = pl.mode;
+    d.pack_a = pl.kpack_a; d.pack_b = pl.kpack_b;
+    d.a_pack_from = pl.kfrom_a; d.b_pack_from = pl.kfrom_b;
+    d.shared_copy = pl.shared_copy;
+    d.no_publish = h->no_publish;
+    d.stats = h->stats;
+    d.order = 0;
+    d.M = run.M; d.N = run.N; d.K = run.K;
+    auto set = [](bool mn, const void* X, int64_t ld, const void** P, int64_t* smn, int64_t* sk,
+                  int* kmajor) {
+        *P = X; *smn = mn ? 1 : ld; *sk = mn ? ld : 1; *kmajor = !mn;
+    };
+    if (ls.kind == fip::kSyrk) {
+        set(ls.a_mn, A, lda, &d.A, &d.a_smn, &d.a_sk, &d.a_kmajor);
+        set(ls.b_mn, A, lda, &d.B, &d.b_smn, &d.b_sk, &d.b_kmajor);
+    } else if (ls.tri_side == 1) {
+        set(ls.a_mn, A, lda, &d.A, &d.a_smn, &d.a_sk, &d.a_kmajor);
+        set(ls.b_mn, B, ldb, &d.B, &d.b_smn, &d.b_sk, &d.b_kmajor);
+    } else {
+        set(ls.a_mn, B, ldb, &d.A, &d.a_smn, &d.a_sk, &d.a_kmajor);
+        set(ls.b_mn, A, lda, &d.B, &d.b_smn, &d.b_sk, &d.b_kmajor);
+    }
+    d.C = C; d.ldc = ldc;
+    d.alpha = (double)alpha; d.beta = (double)beta;
+    d.split = 1;
+    d.slice_ksteps = (int)pl.nK;
+    d.kind = ls.kind;
+    d.tri_upper = ls.tri_upper;
+    d.tri_side = ls.tri_side;
+    d.tri_keep_ge = ls.tri_keep_ge;
+    d.tri_unit = ls.tri_unit;
+    if (pl.pub.workspace_bytes > 0) {
+        fill_workspace(h->ws, pl, &d);
+        if (pl.mode == fip::kModeFused) d.epoch = h->epoch = next_epoch();
+    } else {
+        d.stats = 0;
+    }
+    d.stream = h->stream;
+    if (const hipError_t e = fip::launch_gemm(d); e != hipSuccess) return launch_failed(h, e);
+    h->last = pl.pub;
+    h->has_last = 1;
+    return 0;
+}
+
+template <typename T>
+int syrk_impl(fip_handle_t h, int dtype, int layout, char uplo, char trans, int64_t n, int64_t k,
+              T alpha, const T* A, int64_t lda, T beta, T* C, int64_t ldc)
+{
+    try {
+        if (!valid_handle(h)) return FIP_ERR_HANDLE;
+        // positions: layout 2, uplo 3, trans 4, n 5, k 6, alpha 7, A 8, lda 9, beta 10,
+        // C 11, ldc 12
+        if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 2;
+        if (!valid_uplo(uplo)) return 3;
+        if (!valid_trans(trans)) return 4;
+        if (n < 0) return 5;
+        if (k < 0) return 6;
+        const bool reads_a = n > 0 && k > 0 && alpha != T(0);
+        if (reads_a && A == nullptr) return 8;
+        const bool col = layout == FIP_COL_MAJOR;
+        if (lda < max1(col != is_trans(trans) ? n : k)) return 9;
+        if (n > 0 && !(beta == T(1) && !reads_a) && C == nullptr) return 11;
+        if (ldc < max1(n)) return 12;
+        if (n == 0) return 0;
+        if (!reads_a && beta == T(1)) return 0;
+        return run_l3<T>(h, dtype, syrk_shape(layout, uplo, trans, n, k), alpha, A, lda, nullptr,
+                         1, beta, C, ldc);
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+template <typename T>
+int trmm_impl(fip_handle_t h, int dtype, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, T alpha, const T* A, int64_t lda, const T* B, int64_t ldb,
+              T beta, T* C, int64_t ldc)
+{
+    try {
+        if (!valid_handle(h)) return FIP_ERR_HANDLE;
+        // positions: layout 2, side 3, uplo 4, transA 5, diag 6, m 7, n 8, alpha 9, A 10,
+        // lda 11, B 12, ldb 13, beta 14, C 15, ldc 16
+        if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 2;
+        if (!valid_side(side)) return 3;
+        if (!valid_uplo(uplo)) return 4;
+        if (!valid_trans(transA)) return 5;
+        if (!valid_diag(diag)) return 6;
+        if (m < 0) return 7;
+        if (n < 0) return 8;
+        const int64_t ka = is_left(side) ? m : n;
+        const bool reads_ab = m > 0 && n > 0 && alpha != T(0);
+        if (reads_ab && A == nullptr) return 10;
+        if (lda < max1(ka)) return 11;
+        if (reads_ab && B == nullptr) return 12;
+        const bool col = layout == FIP_COL_MAJOR;
+        if (ldb < max1(col ? m : n)) return 13;
+        if (m > 0 && n > 0 && !(beta == T(1) && !reads_ab) && C == nullptr) return 15;
+        if (ldc < max1(col ? m : n)) return 16;
+        if (m == 0 || n == 0) return 0;
+        if (!reads_ab && beta == T(1)) return 0;
+        if (!reads_ab) {
+            const KernelShape ks = kernel_shape(layout, m, n);
+            if (const hipError_t e = fip::launch_scale(sizeof(T), ks.M, ks.N, C, ldc, (double)beta,
+                                                       h->stream); e != hipSuccess)
+                return launch_failed(h, e);
+            return 0;
+        }
+        return run_l3<T>(h, dtype, trmm_shape(layout, side, uplo, transA, diag, m, n), alpha, A,
+                         lda, B, ldb, beta, C, ldc);
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
 // ---- batched binary32 GEMM ----------------------------------------------------
 
 constexpr int kVbDefaultSplit = 16;   // untuned: max(m, n) <= 16 -> 16 x 16 tiles
@@ -1060,6 +1339,62 @@ int fip_sgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, 
 {
     return gemm_impl<float>(handle, FIP_F32, layout, m, n, k, alpha, A, lda, transA, B, ldb,
                             transB, beta, C, ldc);
+}
+
+int fip_dsyrk(fip_handle_t handle, int layout, char uplo, char trans, int64_t n, int64_t k,
+              double alpha, const double* A, int64_t lda, double beta, double* C, int64_t ldc)
+{
+    return syrk_impl<double>(handle, FIP_F64, layout, uplo, trans, n, k, alpha, A, lda, beta, C,
+                             ldc);
+}
+
+int fip_ssyrk(fip_handle_t handle, int layout, char uplo, char trans, int64_t n, int64_t k,
+              float alpha, const float* A, int64_t lda, float beta, float* C, int64_t ldc)
+{
+    return syrk_impl<float>(handle, FIP_F32, layout, uplo, trans, n, k, alpha, A, lda, beta, C,
+                            ldc);
+}
+
+int fip_dtrmm(fip_handle_t handle, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, double alpha, const double* A, int64_t lda, const double* B,
+              int64_t ldb, double beta, double* C, int64_t ldc)
+{
+    return trmm_impl<double>(handle, FIP_F64, layout, side, uplo, transA, diag, m, n, alpha, A,
+                             lda, B, ldb, beta, C, ldc);
+}
+
+int fip_strmm(fip_handle_t handle, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, float alpha, const float* A, int64_t lda, const float* B,
+              int64_t ldb, float beta, float* C, int64_t ldc)
+{
+    return trmm_impl<float>(handle, FIP_F32, layout, side, uplo, transA, diag, m, n, alpha, A,
+                            lda, B, ldb, beta, C, ldc);
+}
+
+int fip_plan_l3(fip_handle_t handle, int op, int dtype, int layout, char side, char uplo,
+                char trans, char diag, int64_t m, int64_t n, int64_t k, fip_plan_t* plan)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    if (op != FIP_OP_SYRK && op != FIP_OP_TRMM) return 2;
+    if (dtype != FIP_F64 && dtype != FIP_F32) return 3;
+    if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 4;
+    if (op == FIP_OP_TRMM && !valid_side(side)) return 5;
+    if (!valid_uplo(uplo)) return 6;
+    if (!valid_trans(trans)) return 7;
+    if (op == FIP_OP_TRMM && !valid_diag(diag)) return 8;
+    if (m < 0) return 9;
+    if (n < 0) return 10;
+    if (k < 0) return 11;
+    if (plan == nullptr) return 12;
+    Plan pl;
+    const L3Shape ls = op == FIP_OP_SYRK ? syrk_shape(layout, uplo, trans, n, k)
+                                         : trmm_shape(layout, side, uplo, trans, diag, m, n);
+    make_plan_l3(handle, dtype, ls, &pl);
+    pl.pub.layout = layout;
+    pl.pub.m = op == FIP_OP_SYRK ? n : m;
+    pl.pub.n = n;
+    *plan = pl.pub;
+    return 0;
 }
 
 int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,

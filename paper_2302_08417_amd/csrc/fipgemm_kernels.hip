@@ -52,7 +52,30 @@ struct Params {
     int order;       // tile order inside an XCD's run: 0 grouped, 1 column-distinct rounds
     int split, slice_ksteps;  // k split into `split` slices of slice_ksteps k-steps
     T* part;                  // split partials: [split][N][M] (kernel view, column-major)
+    // Other level-3 operations on the same tile body (see LaunchDesc)
+    int kind;                 // kGemm, kSyrk, kTrmm
+    int tri_upper;            // SYRK: C's triangle is row <= column (else row >= column)
+    int tri_side;             // TRMM: 1 = A side triangular, 2 = B side
+    int tri_keep_ge;          // TRMM: element (x, p) kept when x >= p (else x <= p)
+    int tri_unit;             // TRMM: the diagonal x == p reads as 1
 };
+
+// SYRK: workgroup w -> tile (tm, tn) of the stored triangle.  XCD-contiguous
+// runs of the triangle's tiles in row order (lower: tn <= tm), so consecutive
+// tiles of an XCD share their A-side panel.
+__device__ __forceinline__ void tri_tile(int w, int t, bool upper, int& tm, int& tn)
+{
+    const int T = t * (t + 1) / 2;
+    const int xcd = w & 7, local = w >> 3;
+    const int q = T >> 3, rr = T & 7;
+    const int idx = xcd * q + (xcd < rr ? xcd : rr) + local;
+    int r = (int)((__builtin_sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > idx) --r;
+    while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+    const int c = idx - r * (r + 1) / 2;
+    tm = upper ? c : r;
+    tn = upper ? r : c;
+}
 
 template <typename T, int MT, int NT, int KT, int WM, int WN, bool AKC, bool BKC>
 __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P)
@@ -80,11 +103,26 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     const int slice = S > 1 ? (int)(blockIdx.x / (unsigned)ntiles) : 0;
     const int wt = (int)blockIdx.x - slice * ntiles;
     int tm, tn;
-    tile_coords(wt, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
+    if (P.kind == kSyrk) tri_tile(wt, P.tilesM, P.tri_upper, tm, tn);
+    else tile_coords(wt, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
     const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * NT;
     const int nK = P.nK;
-    const int q0 = slice * P.slice_ksteps;
-    const int q1 = q0 + P.slice_ksteps < nK ? q0 + P.slice_ksteps : nK;
+    int q0 = slice * P.slice_ksteps;
+    int q1 = q0 + P.slice_ksteps < nK ? q0 + P.slice_ksteps : nK;
+    // TRMM: the k-steps whose chunk of the triangular operand is not all
+    // structural zeros (rows x of the tile's panel keep p <= x, or p >= x)
+    const bool tri_a = P.kind == kTrmm && P.tri_side == 1;
+    const bool tri_b = P.kind == kTrmm && P.tri_side == 2;
+    if (tri_a || tri_b) {
+        const int64_t tx0 = tri_a ? x0a : x0b, tmn = tri_a ? MT : NT;
+        if (P.tri_keep_ge) {
+            const int64_t last = (tx0 + tmn + KT - 1) / KT;   // chunks holding p < tx0 + tmn
+            if (last < q1) q1 = (int)last;
+        } else {
+            const int64_t first = tx0 / KT;
+            if (first > q0) q0 = (int)first;
+        }
+    }
     const int nKfull = (int)(P.K / KT);  // chunks with all KT k-values present
     const uint64_t epoch = P.epoch;
 
@@ -122,6 +160,9 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         apanel = P.apack + (int64_t)copy * P.apack_copy + (int64_t)(tm - P.a_pack_from) * nK * KT * MT;
     if (useB || consume)
         bpanel = P.bpack + (int64_t)copy * P.bpack_copy + (int64_t)(tn - P.b_pack_from) * nK * KT * NT;
+    // (SYRK: the host points the B side's pack, flags and claims at the A
+    // side's, so a panel is claimed, packed and read once for both roles; the
+    // diagonal tile's B-side claim then finds its own A-side claim.)
     // One completion flag and one claim per (copy, panel, k-slice): a slice's
     // chunks of a panel are packed by the first workgroup of that slice.
     const int64_t aslot = ((int64_t)copy * P.tilesM + tm) * S + slice;
@@ -164,6 +205,13 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     unsigned long long n_prod = 0, n_pk = 0, n_unpk = 0, n_polls = 0;
     ChA ra;
     ChB rb;
+    // Whether chunk c of a triangular operand's panel (rows [tx0, tx0 + tmn))
+    // holds both kept and dropped entries, or diagonal ones: not entirely
+    // strictly inside the kept triangle.
+    auto tri_meets = [&](int64_t tx0, int64_t tmn, int c) -> bool {
+        const int64_t p0 = (int64_t)c * KT;
+        return P.tri_keep_ge ? p0 + KT - 1 >= tx0 : p0 <= tx0 + tmn - 1;
+    };
     // Packed chunks and interior unpacked chunks are read by one and the same
     // vector-load sequence: only the base pointer and the per-lane offsets
     // differ (packed element o sits o*sizeof(T) bytes into its chunk).
@@ -191,6 +239,13 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         } else {
             rb.load_edge(P.B, ldb, P.N, P.K, x0b, (int64_t)c * KT, P.b_vec, tid);
         }
+        // TRMM: an unpacked chunk that meets the diagonal gets the triangle
+        // applied in registers (zeros outside it, ones on a unit diagonal)
+        // before it reaches LDS or the pack; a packed chunk already holds it.
+        if (tri_a && !apk && tri_meets(x0a, MT, c))
+            ra.mask_tri(x0a, (int64_t)c * KT, P.tri_keep_ge, P.tri_unit, P.M, P.K, tid);
+        if (tri_b && !bpk && tri_meets(x0b, NT, c))
+            rb.mask_tri(x0b, (int64_t)c * KT, P.tri_keep_ge, P.tri_unit, P.N, P.K, tid);
         if (P.do_stats && tid == 0) {
             n_prod += (int)prodA + (int)prodB;
             n_pk += (int)(wantA && apk) + (int)(wantB && bpk) + (consume ? 2 : 0);
@@ -312,7 +367,8 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     // r = 0..3 (see mfma16).  Interior tiles read all of their C first, then
     // write it back, with no masks.
     const T alpha = P.alpha, beta = P.beta;
-    const bool c_in = x0a + MT <= P.M && x0b + NT <= P.N;
+    const bool diag_tile = P.kind == kSyrk && tm == tn;
+    const bool c_in = x0a + MT <= P.M && x0b + NT <= P.N && !diag_tile;
     auto di = [&](int r) -> int { return sizeof(T) == 8 ? (lane & 15) : 4 * (lane >> 4) + r; };
     auto dj = [&](int r) -> int { return sizeof(T) == 8 ? 4 * r + (lane >> 4) : (lane & 15); };
     const int64_t r0w = x0a + wm * WTM, c0w = x0b + wn * WTN;
@@ -366,7 +422,8 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t i = r0w + a * 16 + di(r), j = c0w + b * 16 + dj(r);
-                    if (i < P.M && j < P.N) {
+                    const bool in_tri = !diag_tile || (P.tri_upper ? i <= j : i >= j);
+                    if (i < P.M && j < P.N && in_tri) {
                         T* cp = P.C + i + j * P.ldc;
                         *cp = beta != T(0) ? axpby(alpha, acc[a][b][r], beta, *cp)
                                            : alpha * acc[a][b][r];
@@ -479,6 +536,11 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.split = d.split > 1 ? d.split : 1;
     P.slice_ksteps = d.split > 1 ? d.slice_ksteps : P.nK;
     P.part = static_cast<T*>(d.part);
+    P.kind = d.kind;
+    P.tri_upper = d.tri_upper;
+    P.tri_side = d.tri_side;
+    P.tri_keep_ge = d.tri_keep_ge;
+    P.tri_unit = d.tri_unit;
     return P;
 }
 
@@ -488,7 +550,9 @@ hipError_t launch_tile(const LaunchDesc& d)
     constexpr int KT = sizeof(T) == 8 ? 16 : 32;
     const Params<T> P = make_params<T>(d, MT, NT, KT);
     const bool akc = d.a_kmajor, bkc = d.b_kmajor;
-    const dim3 grid((unsigned)((int64_t)P.tilesM * P.tilesN * P.split)), block(WM * WN * 64);
+    const int64_t tiles = d.kind == kSyrk ? (int64_t)P.tilesM * (P.tilesM + 1) / 2
+                                          : (int64_t)P.tilesM * P.tilesN;
+    const dim3 grid((unsigned)(tiles * P.split)), block(WM * WN * 64);
     if (!akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, false><<<grid, block, 0, d.stream>>>(P);
     else if (!akc && bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, true><<<grid, block, 0, d.stream>>>(P);
     else if (akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, true, false><<<grid, block, 0, d.stream>>>(P);

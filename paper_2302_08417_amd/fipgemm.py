@@ -90,6 +90,16 @@ _SIGS = {
                   ctypes.c_float, _vp, _i64],
     "fip_pack": [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _ch, _vp, _i64, _ch],
     "fip_xcc_map": [_vp, _vp, _i64],
+    "fip_dsyrk": [_vp, _i32, _ch, _ch, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double,
+                  _vp, _i64],
+    "fip_ssyrk": [_vp, _i32, _ch, _ch, _i64, _i64, ctypes.c_float, _vp, _i64, ctypes.c_float,
+                  _vp, _i64],
+    "fip_dtrmm": [_vp, _i32, _ch, _ch, _ch, _ch, _i64, _i64, ctypes.c_double, _vp, _i64, _vp,
+                  _i64, ctypes.c_double, _vp, _i64],
+    "fip_strmm": [_vp, _i32, _ch, _ch, _ch, _ch, _i64, _i64, ctypes.c_float, _vp, _i64, _vp,
+                  _i64, ctypes.c_float, _vp, _i64],
+    "fip_plan_l3": [_vp, _i32, _i32, _i32, _ch, _ch, _ch, _ch, _i64, _i64, _i64,
+                    ctypes.POINTER(fip_plan_t)],
     "fip_tile_map": [_i64, _i64, _i32, _vp, _vp],
     "fip_gemm_mx": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64,
                     _ch, ctypes.c_float, _vp, _i64, _i32, _vp, _vp],
@@ -192,6 +202,36 @@ def fip_sgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C
 def fip_pack(h, dtype, layout, m, n, k, A, lda, transA, B, ldb, transB):
     return _lib.fip_pack(h, dtype, layout, m, n, k, _addr(A), lda, _trans(transA), _addr(B), ldb,
                          _trans(transB))
+
+
+FIP_OP_SYRK, FIP_OP_TRMM = 1, 2
+
+
+def fip_dsyrk(h, layout, uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
+    return _lib.fip_dsyrk(h, layout, _trans(uplo), _trans(trans), n, k, alpha, _addr(A), lda,
+                          beta, _addr(C), ldc)
+
+
+def fip_ssyrk(h, layout, uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
+    return _lib.fip_ssyrk(h, layout, _trans(uplo), _trans(trans), n, k, alpha, _addr(A), lda,
+                          beta, _addr(C), ldc)
+
+
+def fip_dtrmm(h, layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb, beta, C, ldc):
+    return _lib.fip_dtrmm(h, layout, _trans(side), _trans(uplo), _trans(transA), _trans(diag), m,
+                          n, alpha, _addr(A), lda, _addr(B), ldb, beta, _addr(C), ldc)
+
+
+def fip_strmm(h, layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb, beta, C, ldc):
+    return _lib.fip_strmm(h, layout, _trans(side), _trans(uplo), _trans(transA), _trans(diag), m,
+                          n, alpha, _addr(A), lda, _addr(B), ldb, beta, _addr(C), ldc)
+
+
+def fip_plan_l3(h, op, dtype, layout, side, uplo, trans, diag, m, n, k):
+    p = fip_plan_t()
+    rc = _lib.fip_plan_l3(h, op, dtype, layout, _trans(side), _trans(uplo), _trans(trans),
+                          _trans(diag), m, n, k, ctypes.byref(p))
+    return rc, p
 
 
 def fip_tile_map(tiles_m, tiles_n, order):
@@ -350,6 +390,29 @@ class Handle:
         self._check("fip_gemm_mx", fip_gemm_mx(self.h, dtype, layout, m, n, k, alpha, A, lda,
                                                transA, B, ldb, transB, beta, C, ldc, c_type,
                                                a_scale, b_scale))
+
+    def syrk(self, layout, uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
+        """fip_dsyrk / fip_ssyrk by C's dtype."""
+        import torch
+        dt = FIP_F64 if C.dtype == torch.float64 else FIP_F32
+        self.bind_stream()
+        rc, p = fip_plan_l3(self.h, FIP_OP_SYRK, dt, layout, "L", uplo, trans, "N", n, n, k)
+        self._check("fip_plan_l3", rc)
+        self.ensure_workspace(p.workspace_bytes)
+        fn = fip_dsyrk if dt == FIP_F64 else fip_ssyrk
+        self._check(fn.__name__, fn(self.h, layout, uplo, trans, n, k, alpha, A, lda, beta, C, ldc))
+
+    def trmm(self, layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb, beta, C, ldc):
+        """fip_dtrmm / fip_strmm by C's dtype."""
+        import torch
+        dt = FIP_F64 if C.dtype == torch.float64 else FIP_F32
+        self.bind_stream()
+        rc, p = fip_plan_l3(self.h, FIP_OP_TRMM, dt, layout, side, uplo, transA, diag, m, n, 0)
+        self._check("fip_plan_l3", rc)
+        self.ensure_workspace(p.workspace_bytes)
+        fn = fip_dtrmm if dt == FIP_F64 else fip_strmm
+        self._check(fn.__name__, fn(self.h, layout, side, uplo, transA, diag, m, n, alpha, A, lda,
+                                    B, ldb, beta, C, ldc))
 
     def quantize_fp8(self, layout, rows, cols, X, ldx, axis, Q, ldq, scales):
         self.bind_stream()

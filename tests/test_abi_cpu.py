@@ -455,3 +455,51 @@ def test_tile_map_is_one_to_one_and_matches_replica():
             for w in range(0, tM * tN, max(1, tM * tN // 97)):
                 assert (tm[w], tn[w]) == _tile_of(w, tM, tN, order), (tM, tN, order, w)
     assert F.fip_tile_map(4, 4, 2)[0] == 3
+
+
+def test_l3_argument_positions_and_plans(h):
+    """SYRK / TRMM: argument errors by position before any HIP call; plans: one packable
+    operand, SYRK's B side is the same pack, TRMM never packs the dense operand."""
+    A = 0x1000   # never dereferenced: every call below fails its checks first
+    assert F.fip_dsyrk(h, 5, "L", "N", 4, 4, 1.0, A, 4, 0.0, A, 4) == 2
+    assert F.fip_dsyrk(h, 0, "X", "N", 4, 4, 1.0, A, 4, 0.0, A, 4) == 3
+    assert F.fip_dsyrk(h, 0, "L", "Q", 4, 4, 1.0, A, 4, 0.0, A, 4) == 4
+    assert F.fip_dsyrk(h, 0, "L", "N", -1, 4, 1.0, A, 4, 0.0, A, 4) == 5
+    assert F.fip_dsyrk(h, 0, "L", "N", 4, -1, 1.0, A, 4, 0.0, A, 4) == 6
+    assert F.fip_dsyrk(h, 0, "L", "N", 4, 4, 1.0, None, 4, 0.0, A, 4) == 8
+    assert F.fip_dsyrk(h, 0, "L", "N", 5, 4, 1.0, A, 4, 0.0, A, 5) == 9     # col N: lda >= n
+    assert F.fip_dsyrk(h, 1, "L", "N", 5, 6, 1.0, A, 5, 0.0, A, 5) == 9     # row N: lda >= k
+    assert F.fip_ssyrk(h, 0, "U", "T", 4, 4, 1.0, A, 4, 0.0, None, 4) == 11
+    assert F.fip_ssyrk(h, 0, "U", "T", 4, 4, 1.0, A, 4, 0.0, A, 3) == 12
+    assert F.fip_dtrmm(h, 0, "X", "L", "N", "N", 4, 4, 1.0, A, 4, A, 4, 0.0, A, 4) == 3
+    assert F.fip_dtrmm(h, 0, "L", "X", "N", "N", 4, 4, 1.0, A, 4, A, 4, 0.0, A, 4) == 4
+    assert F.fip_dtrmm(h, 0, "L", "L", "X", "N", 4, 4, 1.0, A, 4, A, 4, 0.0, A, 4) == 5
+    assert F.fip_dtrmm(h, 0, "L", "L", "N", "X", 4, 4, 1.0, A, 4, A, 4, 0.0, A, 4) == 6
+    assert F.fip_dtrmm(h, 0, "L", "L", "N", "N", -1, 4, 1.0, A, 4, A, 4, 0.0, A, 4) == 7
+    assert F.fip_dtrmm(h, 0, "R", "L", "N", "N", 4, 6, 1.0, A, 5, A, 4, 0.0, A, 4) == 11
+    assert F.fip_strmm(h, 1, "L", "L", "N", "N", 4, 6, 1.0, A, 4, A, 5, 0.0, A, 6) == 13
+    assert F.fip_strmm(h, 1, "L", "L", "N", "N", 4, 6, 1.0, A, 4, A, 6, 0.0, A, 5) == 16
+    # quick returns make no HIP call: n = 0; alpha = 0 and beta = 1
+    assert F.fip_dsyrk(h, 0, "L", "N", 0, 4, 1.0, None, 1, 0.0, None, 1) == 0
+    assert F.fip_dtrmm(h, 0, "L", "L", "N", "N", 4, 4, 0.0, None, 4, None, 4, 1.0, A, 4) == 0
+    try:
+        for pol in (F.FIP_PACK_ALL, F.FIP_PACK_NONE, F.FIP_PACK_AUTO):
+            assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, pol) == 0
+            rc, p = F.fip_plan_l3(h, F.FIP_OP_SYRK, F.FIP_F64, 0, "L", "L", "N", "N", 0, 8192,
+                                  8192)
+            assert rc == 0 and p.split_k == 1 and p.tiles_m == p.tiles_n == 64
+            if pol == F.FIP_PACK_ALL:
+                assert p.pack_a and p.pack_b and p.a_pack_offset == p.b_pack_offset
+                assert p.workspace_bytes >= p.a_pack_offset + p.a_copy_bytes
+            else:  # NONE, and AUTO on a multiple of the tile (the stride rule)
+                assert (p.pack_a, p.pack_b, p.workspace_bytes) == (0, 0, 0)
+            rc, p = F.fip_plan_l3(h, F.FIP_OP_TRMM, F.FIP_F32, 1, "R", "U", "T", "U", 4096,
+                                  4000, 0)
+            assert rc == 0 and p.b_copy_bytes == 0 and p.b_pack_first == 0
+            if pol == F.FIP_PACK_ALL:
+                assert p.pack_a and p.a_copy_bytes == p.ksteps * p.KT * p.MT * 4 * \
+                    -(-4000 // p.MT)
+        assert F.fip_plan_l3(h, 3, 0, 0, "L", "L", "N", "N", 4, 4, 4)[0] == 2
+        assert F.fip_plan_l3(h, F.FIP_OP_TRMM, 0, 0, "Q", "L", "N", "N", 4, 4, 4)[0] == 5
+    finally:
+        F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO)
