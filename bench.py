@@ -513,6 +513,53 @@ def ldim_section(F, torch):
     return out
 
 
+def l3_section(F, torch, sizes=(4096, 8192)):
+    """SYRK (C := 1.5 A A^T + 0.5 C, lower, column-major 'N', k = n) and TRMM (C := 1.5 T B +
+    0.5 C, side L, lower, no transpose, non-unit) through the fused-pack tile kernel in FP64 and
+    FP32: fused (AUTO) against unpacked (NONE) and fused with every panel packed (ALL).  flops:
+    n^2 k for SYRK (one triangle), m^2 n for TRMM (half the square)."""
+    import statistics
+    from paper_2302_08417_amd import synth
+    out = []
+    for dt in ("f64", "f32"):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        for n in sizes:
+            g = torch.Generator(device="cuda").manual_seed(synth.BASE_SEED + n)
+            A = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
+            B = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
+            C = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
+            for op in ("syrk", "trmm"):
+                hs = {key: F.Handle(policy=pol) for key, pol in
+                      (("fused", F.FIP_PACK_AUTO), ("no_pack", F.FIP_PACK_NONE),
+                       ("fused_all", F.FIP_PACK_ALL))}
+
+                def mk(h):
+                    if op == "syrk":
+                        return lambda: h.syrk(0, "L", "N", n, n, 1.5, A, n, 0.5, C, n)
+                    return lambda: h.trmm(0, "L", "L", "N", "N", n, n, 1.5, A, n, B, n, 0.5, C, n)
+                calls = {key: mk(h) for key, h in hs.items()}
+                for c in calls.values():
+                    c()
+                torch.cuda.synchronize()
+                fl = float(n) ** 3
+                est = fl / (60e12 if dt == "f64" else 120e12)
+                med = _median_times(torch, calls, 5, max(1, min(20, int(0.02 / est))))
+                row = {"op": op, "dtype": dt, "n": n, "k_or_m": n}
+                for key in calls:
+                    row[key + "_us"] = round(med[key] * 1e3, 1)
+                row["fused_tflops"] = round(fl / (med["fused"] * 1e-3) / 1e12, 2)
+                row["fused_pct_peak"] = round(100 * row["fused_tflops"] / PEAK_TFLOPS[dt], 2)
+                p = hs["fused"].last_plan()
+                row["fused_pack"] = [p.pack_a, p.a_pack_first]
+                log(f"[l3] {row}")
+                out.append(row)
+                for h in hs.values():
+                    h.close()
+            del A, B, C
+            torch.cuda.empty_cache()
+    return out
+
+
 def plain_dgemm_section(F, torch):
     """C := A B + C, m = n = k = 256, column-major NN, alpha = beta = 1 (FP64)."""
     from paper_2302_08417_amd import synth
@@ -661,6 +708,9 @@ def compact_summary(result, full):
             r["form"]: {"n": big, "pct_peak": r["fused_pct_mfma_peak"],
                         "vs_ptc": round(r["pack_then_compute_us"] / r["fused_us"], 3)}
             for r in full["mixed_precision"] if r["m"] == big}
+    if "syrk_trmm" in full:
+        s["syrk_trmm_pct_peak"] = {f"{r['op']}_{r['dtype']}_{r['n']}": r["fused_pct_peak"]
+                                   for r in full["syrk_trmm"] if r["n"] == 8192}
     if "autograd" in full:
         s["autograd"] = {k: full["autograd"][k] for k in ("ms_per_step", "pct_bf16_mfma_peak")}
     if "batched" in full:
@@ -688,6 +738,7 @@ def main():
     ap.add_argument("--no-mx", action="store_true", help="skip the mixed-precision section")
     ap.add_argument("--mx-sizes", default="1024,4096,16384")
     ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--no-l3", action="store_true", help="skip the SYRK / TRMM section")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--results", default=os.path.join("gpurun_out", "bench_full.json"),
                     help="file that receives every section's rows (the stdout line carries\n"
@@ -793,6 +844,8 @@ def main():
     if not args.no_mx:
         full["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
         full["mixed_precision_deep_k"] = mx_deep_k_section(F, torch)
+    if not args.no_l3:
+        full["syrk_trmm"] = l3_section(F, torch)
     if not args.no_autograd:
         full["autograd"] = autograd_section(F, torch)
     if not args.no_batched:

@@ -52,13 +52,33 @@ struct Params {
     int order;       // tile order inside an XCD's run: 0 grouped, 1 column-distinct rounds
     int split, slice_ksteps;  // k split into `split` slices of slice_ksteps k-steps
     T* part;                  // split partials: [split][N][M] (kernel view, column-major)
-    // Other level-3 operations on the same tile body (see LaunchDesc)
-    int kind;                 // kGemm, kSyrk, kTrmm
+    // Other level-3 operations on the same tile body (see LaunchDesc; the
+    // operation itself is the kernel's KIND parameter)
     int tri_upper;            // SYRK: C's triangle is row <= column (else row >= column)
     int tri_side;             // TRMM: 1 = A side triangular, 2 = B side
     int tri_keep_ge;          // TRMM: element (x, p) kept when x >= p (else x <= p)
     int tri_unit;             // TRMM: the diagonal x == p reads as 1
 };
+
+// TRMM: workgroup w -> tile, longest k-range first.  A tile's k-range is set
+// by its row (triangular A side) or column (triangular B side) of tiles, and
+// runs from 1 to all k-steps, so the tiles are issued in order of decreasing
+// k-range, consecutive workgroups (which go to different XCDs) taking the
+// tiles of one row (column): every XCD gets its share of the long tiles, and
+// the short ones fill in at the end.
+__device__ __forceinline__ void trmm_tile(int w, int tilesM, int tilesN, bool tri_a, bool keep_ge,
+                                          int& tm, int& tn)
+{
+    if (tri_a) {
+        const int r = w / tilesN;
+        tn = w - r * tilesN;
+        tm = keep_ge ? tilesM - 1 - r : r;
+    } else {
+        const int c = w / tilesM;
+        tm = w - c * tilesM;
+        tn = keep_ge ? tilesN - 1 - c : c;
+    }
+}
 
 // SYRK: workgroup w -> tile (tm, tn) of the stored triangle.  XCD-contiguous
 // runs of the triangle's tiles in row order (lower: tn <= tm), so consecutive
@@ -77,7 +97,9 @@ __device__ __forceinline__ void tri_tile(int w, int t, bool upper, int& tm, int&
     tn = upper ? r : c;
 }
 
-template <typename T, int MT, int NT, int KT, int WM, int WN, bool AKC, bool BKC>
+// KIND (kGemm, kSyrk, kTrmm) is a compile-time parameter so that the GEMM
+// instantiations carry none of the triangle logic (it costs registers).
+template <typename T, int MT, int NT, int KT, int WM, int WN, bool AKC, bool BKC, int KIND>
 __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P)
 {
     constexpr int NTHR = WM * WN * 64;
@@ -103,7 +125,8 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     const int slice = S > 1 ? (int)(blockIdx.x / (unsigned)ntiles) : 0;
     const int wt = (int)blockIdx.x - slice * ntiles;
     int tm, tn;
-    if (P.kind == kSyrk) tri_tile(wt, P.tilesM, P.tri_upper, tm, tn);
+    if constexpr (KIND == kSyrk) tri_tile(wt, P.tilesM, P.tri_upper, tm, tn);
+    else if constexpr (KIND == kTrmm) trmm_tile(wt, P.tilesM, P.tilesN, P.tri_side == 1, P.tri_keep_ge, tm, tn);
     else tile_coords(wt, P.tilesM, P.tilesN, P.group_m, P.order, tm, tn);
     const int64_t x0a = (int64_t)tm * MT, x0b = (int64_t)tn * NT;
     const int nK = P.nK;
@@ -111,8 +134,8 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     int q1 = q0 + P.slice_ksteps < nK ? q0 + P.slice_ksteps : nK;
     // TRMM: the k-steps whose chunk of the triangular operand is not all
     // structural zeros (rows x of the tile's panel keep p <= x, or p >= x)
-    const bool tri_a = P.kind == kTrmm && P.tri_side == 1;
-    const bool tri_b = P.kind == kTrmm && P.tri_side == 2;
+    const bool tri_a = KIND == kTrmm && P.tri_side == 1;
+    const bool tri_b = KIND == kTrmm && P.tri_side == 2;
     if (tri_a || tri_b) {
         const int64_t tx0 = tri_a ? x0a : x0b, tmn = tri_a ? MT : NT;
         if (P.tri_keep_ge) {
@@ -367,7 +390,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     // r = 0..3 (see mfma16).  Interior tiles read all of their C first, then
     // write it back, with no masks.
     const T alpha = P.alpha, beta = P.beta;
-    const bool diag_tile = P.kind == kSyrk && tm == tn;
+    const bool diag_tile = KIND == kSyrk && tm == tn;
     const bool c_in = x0a + MT <= P.M && x0b + NT <= P.N && !diag_tile;
     auto di = [&](int r) -> int { return sizeof(T) == 8 ? (lane & 15) : 4 * (lane >> 4) + r; };
     auto dj = [&](int r) -> int { return sizeof(T) == 8 ? 4 * r + (lane >> 4) : (lane & 15); };
@@ -536,12 +559,20 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.split = d.split > 1 ? d.split : 1;
     P.slice_ksteps = d.split > 1 ? d.slice_ksteps : P.nK;
     P.part = static_cast<T*>(d.part);
-    P.kind = d.kind;
     P.tri_upper = d.tri_upper;
     P.tri_side = d.tri_side;
     P.tri_keep_ge = d.tri_keep_ge;
     P.tri_unit = d.tri_unit;
     return P;
+}
+
+template <typename T, int MT, int NT, int KT, int WM, int WN, int KIND>
+void launch_oriented(bool akc, bool bkc, dim3 grid, dim3 block, hipStream_t st, const Params<T>& P)
+{
+    if (!akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, false, KIND><<<grid, block, 0, st>>>(P);
+    else if (!akc && bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, true, KIND><<<grid, block, 0, st>>>(P);
+    else if (akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, true, false, KIND><<<grid, block, 0, st>>>(P);
+    else gemm_kernel<T, MT, NT, KT, WM, WN, true, true, KIND><<<grid, block, 0, st>>>(P);
 }
 
 template <typename T, int MT, int NT, int WM, int WN>
@@ -553,10 +584,9 @@ hipError_t launch_tile(const LaunchDesc& d)
     const int64_t tiles = d.kind == kSyrk ? (int64_t)P.tilesM * (P.tilesM + 1) / 2
                                           : (int64_t)P.tilesM * P.tilesN;
     const dim3 grid((unsigned)(tiles * P.split)), block(WM * WN * 64);
-    if (!akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, false><<<grid, block, 0, d.stream>>>(P);
-    else if (!akc && bkc) gemm_kernel<T, MT, NT, KT, WM, WN, false, true><<<grid, block, 0, d.stream>>>(P);
-    else if (akc && !bkc) gemm_kernel<T, MT, NT, KT, WM, WN, true, false><<<grid, block, 0, d.stream>>>(P);
-    else gemm_kernel<T, MT, NT, KT, WM, WN, true, true><<<grid, block, 0, d.stream>>>(P);
+    if (d.kind == kSyrk) launch_oriented<T, MT, NT, KT, WM, WN, kSyrk>(akc, bkc, grid, block, d.stream, P);
+    else if (d.kind == kTrmm) launch_oriented<T, MT, NT, KT, WM, WN, kTrmm>(akc, bkc, grid, block, d.stream, P);
+    else launch_oriented<T, MT, NT, KT, WM, WN, kGemm>(akc, bkc, grid, block, d.stream, P);
     if (P.split > 1) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
