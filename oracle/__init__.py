@@ -70,6 +70,14 @@ def lib():
         L.oracle_trmm.argtypes = [ctypes.c_int, ch, ch, ch, ch, i64, i64, dbl, vp, i64, vp, i64,
                                   dbl, vp, i64, vp, vp]
         L.oracle_trmm.restype = None
+        L.oracle_zgemm.argtypes = [ctypes.c_int, i64, i64, i64, dbl, dbl, vp, i64, ch, vp, i64,
+                                   ch, dbl, dbl, vp, i64, vp, vp]
+        L.oracle_zgemm.restype = None
+        L.oracle_zgemm_entries.argtypes = [ctypes.c_int, i64, dbl, dbl, vp, i64, ch, vp, i64, ch,
+                                           dbl, dbl, vp, i64, i64, vp, vp, vp, vp]
+        L.oracle_zgemm_entries.restype = None
+        L.oracle_expand_1m.argtypes = [ctypes.c_int, ctypes.c_int, ch, i64, i64, vp, i64, vp]
+        L.oracle_expand_1m.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -291,3 +299,63 @@ def trmm(layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb, beta, C0
                       _ptr(A64), lda, _ptr(B64), ldb, float(beta), _ptr(C64), ldc, _ptr(Cref),
                       _ptr(D))
     return Cref, D
+
+
+# ---------------------------------------------------------------------------
+# Complex GEMM (fip_oracle_cx.c)
+
+def _c128(x):
+    """Interleaved (re, im) binary64 buffer of a complex array (or of interleaved reals)."""
+    a = np.asarray(x)
+    if np.iscomplexobj(a):
+        a = np.ascontiguousarray(a.reshape(-1), dtype=np.complex128).view(np.float64)
+    return np.ascontiguousarray(a.reshape(-1), dtype=np.float64)
+
+
+def zgemm(layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C0, ldc):
+    """(Cref, D): Cref complex128 in C's storage (entries outside the m x n result are C0's),
+    D binary64, one bound per complex entry (zero outside the result)."""
+    A64, B64, C64 = _c128(A), _c128(B), _c128(C0)
+    Cref = C64.copy()
+    D = np.zeros(C64.size // 2, dtype=np.float64)
+    al, be = complex(alpha), complex(beta)
+    lib().oracle_zgemm(layout, m, n, k, al.real, al.imag, _ptr(A64), lda, _t(transA), _ptr(B64),
+                       ldb, _t(transB), be.real, be.imag, _ptr(C64), ldc, _ptr(Cref), _ptr(D))
+    return Cref.view(np.complex128), D
+
+
+def zgemm_entries(layout, k, alpha, A, lda, transA, B, ldb, transB, beta, C0, ldc, rows, cols):
+    """Reference values (complex128) and bounds at the entries (rows[t], cols[t])."""
+    A64, B64, C64 = _c128(A), _c128(B), _c128(C0)
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    c = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.empty(2 * max(r.size, 1), dtype=np.float64)
+    d = np.empty(max(r.size, 1), dtype=np.float64)
+    al, be = complex(alpha), complex(beta)
+    lib().oracle_zgemm_entries(layout, k, al.real, al.imag, _ptr(A64), lda, _t(transA), _ptr(B64),
+                               ldb, _t(transB), be.real, be.imag, _ptr(C64), ldc, r.size, _ptr(r),
+                               _ptr(c), _ptr(out), _ptr(d))
+    return out[: 2 * r.size].view(np.complex128), d[: r.size]
+
+
+def expand_1m(X, is_b, layout, trans, mn, k, ld):
+    """The 1m expansion of op(X) as a real binary64 array: A1e (2mn x 2k) for is_b = 0,
+    B1r (2k x mn) for is_b = 1."""
+    X64 = _c128(X)
+    rows, cols = (2 * mn, 2 * k) if not is_b else (2 * k, mn)
+    out = np.empty(max(rows * cols, 1), dtype=np.float64)
+    lib().oracle_expand_1m(int(bool(is_b)), layout, _t(trans), mn, k, _ptr(X64), ld, _ptr(out))
+    return out[: rows * cols].reshape(cols, rows).T.copy()
+
+
+def pack_1m(X, is_b, layout, trans, mn, k, ld, MNT, KT, dtype=np.float64):
+    """Reference pack of a complex operand for the 1m method: the real tile layout of its
+    1m expansion (A1e with MN extent 2mn and k extent 2k; B1r with k extent 2k and MN extent
+    mn), each block in the orientation the complex operand has in storage.  Elements are
+    converted to dtype (binary32 data widened to binary64 and back is exact)."""
+    E = expand_1m(X, is_b, layout, trans, mn, k, ld).astype(dtype)
+    kmajor = 0 if mn_contiguous(is_b, layout, trans) else 1
+    emn, ek = (2 * mn, 2 * k) if not is_b else (mn, 2 * k)
+    # E is column-major op(X1m): rows x cols with op 'N'
+    return pack_oriented(E.reshape(-1, order="F"), is_b, COL, "N", emn, ek, E.shape[0], MNT, KT,
+                         kmajor)

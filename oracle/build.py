@@ -8,7 +8,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRCS = [os.path.join(HERE, "fip_oracle.c"), os.path.join(HERE, "fip_oracle_mx.c"),
-        os.path.join(HERE, "fip_oracle_l3.c")]
+        os.path.join(HERE, "fip_oracle_l3.c"), os.path.join(HERE, "fip_oracle_cx.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

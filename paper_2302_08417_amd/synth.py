@@ -134,6 +134,64 @@ def sample_entries(m: int, n: int, count: int, seed: int):
 
 
 # ---------------------------------------------------------------------------
+# Complex operands (complex GEMM): real and imaginary parts drawn independently
+# with the real recipe; stored as complex128 or complex64 arrays (interleaved
+# re, im), ld padding filled with NaN + NaN i.
+
+@dataclass
+class CxCase:
+    layout: int
+    m: int
+    n: int
+    k: int
+    transA: str
+    transB: str
+    lda: int
+    ldb: int
+    ldc: int
+    alpha: complex
+    beta: complex
+    A: np.ndarray
+    B: np.ndarray
+    C: np.ndarray
+    dtype: type
+
+
+def make_cx_case(layout=COL, m=64, n=64, k=64, transA="N", transB="N", ld_pad=0,
+                 alpha=1.5 - 0.5j, beta=0.5 + 0.25j, dtype=np.complex128, seed=BASE_SEED,
+                 dist="uniform", int_range=8) -> CxCase:
+    """dist: "uniform" -> re, im ~ U[-1, 1]; "int" -> integers in [-int_range, int_range]."""
+    g = rng(seed)
+
+    def draw(shape):
+        if dist == "uniform":
+            return g.uniform(-1.0, 1.0, size=shape) + 1j * g.uniform(-1.0, 1.0, size=shape)
+        if dist == "int":
+            return (g.integers(-int_range, int_range + 1, size=shape)
+                    + 1j * g.integers(-int_range, int_range + 1, size=shape))
+        raise ValueError(dist)
+
+    pad = complex(np.nan, np.nan)
+    sa = stored_shape(transA, m, k)
+    sb = stored_shape(transB, k, n)
+    lda = min_ld(layout, *sa) + ld_pad
+    ldb = min_ld(layout, *sb) + ld_pad
+    ldc = min_ld(layout, m, n) + ld_pad
+    A = fill_stored(layout, sa[0], sa[1], lda, draw(sa), dtype, pad)
+    B = fill_stored(layout, sb[0], sb[1], ldb, draw(sb), dtype, pad)
+    C = fill_stored(layout, m, n, ldc, draw((m, n)), dtype, pad)
+    return CxCase(layout, m, n, k, transA, transB, lda, ldb, ldc, complex(alpha), complex(beta),
+                  A, B, C, dtype)
+
+
+def cx_op_view(buf, layout, trans, rows, cols, ld):
+    """op(X) of a stored complex buffer, conjugated for 'C' (index plumbing and the
+    definition of op; no product arithmetic)."""
+    v = op_view(buf, layout, trans, rows, cols, ld)
+    return np.conj(v) if trans in "Cc" else v
+
+
+# ---------------------------------------------------------------------------
 # Mixed-precision operands.  Entries are U[-1, 1] with every row of op(A) and
 # every column of op(B) scaled by 2^u, u ~ U[-8, 8] (rows and columns of very
 # different magnitude).  Operand storage: bfloat16 bit patterns (uint16),
