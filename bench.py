@@ -560,6 +560,113 @@ def l3_section(F, torch, sizes=(4096, 8192)):
     return out
 
 
+def dma_section(F, torch, sizes=(2048, 4096, 8192)):
+    """Direct global -> LDS loads (FIP_ATTR_DMA) against the register path, FP64 and FP32,
+    square column-major NN, alpha = 1.5, beta = 0.5: unpacked (NONE) and pack-then-compute
+    (fip_pack + a CONSUME_ONLY call that fetches the packed chunks), each with the attribute
+    off and on; every launch here is eligible, so "on" runs the DMA variant."""
+    from paper_2302_08417_amd import synth
+    out = []
+    for dt in ("f64", "f32"):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        for n in sizes:
+            g = torch.Generator(device="cuda").manual_seed(synth.BASE_SEED + 5 * n)
+            A = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
+            B = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
+            C = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
+            hs = {}
+            for pol, pname in ((F.FIP_PACK_NONE, "no_pack"), (F.FIP_PACK_CONSUME_ONLY, "pack_then_compute")):
+                for dma in (0, 1):
+                    h = F.Handle(policy=pol)
+                    h.set_attr(F.FIP_ATTR_DMA, dma)
+                    hs[f"{pname}_{'dma' if dma else 'reg'}"] = (h, pol)
+
+            def mk(h, pol):
+                def f():
+                    if pol == F.FIP_PACK_CONSUME_ONLY:
+                        h.pack(F.FIP_COL_MAJOR, n, n, n, A, n, "N", B, n, "N")
+                    h.gemm(F.FIP_COL_MAJOR, n, n, n, 1.5, A, n, "N", B, n, "N", 0.5, C, n)
+                return f
+            calls = {key: mk(h, pol) for key, (h, pol) in hs.items()}
+            for c in calls.values():
+                c()
+            torch.cuda.synchronize()
+            used = {key: h.get_attr(F.FIP_ATTR_LAST_DMA) for key, (h, _) in hs.items()}
+            fl = 2.0 * float(n) ** 3
+            est = fl / (60e12 if dt == "f64" else 120e12)
+            med = _median_times(torch, calls, 5, max(1, min(50, int(0.02 / est))))
+            row = {"dtype": dt, "n": n}
+            for key in calls:
+                row[key + "_us"] = round(med[key] * 1e3, 1)
+            row["dma_speedup_no_pack"] = round(med["no_pack_reg"] / med["no_pack_dma"], 3)
+            row["dma_speedup_pack_then_compute"] = round(
+                med["pack_then_compute_reg"] / med["pack_then_compute_dma"], 3)
+            row["dma_pct_peak_no_pack"] = round(100 * fl / (med["no_pack_dma"] * 1e-3) / 1e12 /
+                                                PEAK_TFLOPS[dt], 2)
+            row["ran_dma"] = [used[k] for k in sorted(used)]
+            log(f"[dma] {row}")
+            out.append(row)
+            for h, _ in hs.values():
+                h.close()
+            del A, B, C
+            torch.cuda.empty_cache()
+    return out
+
+
+def cx_section(F, torch, sizes=(1024, 2048, 4096)):
+    """Complex GEMM through the 1m method (fip_zgemm, fip_cgemm): C := alpha A B + beta C,
+    column-major NN, alpha = 1.5 - 0.5i, beta = 0.5 + 0.25i, re and im U[-1, 1]; fused
+    (AUTO) vs pack-then-compute (fip_pack + CONSUME_ONLY) vs unpacked.  flops: 8 m n k (a
+    complex multiply-add is 8 real flops; the 1m expansion multiplies 2m x 2k by 2k x n, the
+    same count)."""
+    from paper_2302_08417_amd import synth
+    out = []
+    al, be = 1.5 - 0.5j, 0.5 + 0.25j
+    for dt in ("z", "c"):
+        tdt = torch.complex128 if dt == "z" else torch.complex64
+        rdt = torch.float64 if dt == "z" else torch.float32
+        for n in sizes:
+            g = torch.Generator(device="cuda").manual_seed(synth.BASE_SEED + 3 * n)
+
+            def draw():
+                return torch.complex(torch.rand(n * n, device="cuda", generator=g, dtype=rdt) * 2 - 1,
+                                     torch.rand(n * n, device="cuda", generator=g, dtype=rdt) * 2 - 1)
+            A, B, C = draw().to(tdt), draw().to(tdt), draw().to(tdt)
+            hs = {key: F.Handle(policy=pol) for key, pol in
+                  (("fused", F.FIP_PACK_AUTO), ("pack_then_compute", F.FIP_PACK_CONSUME_ONLY),
+                   ("no_pack", F.FIP_PACK_NONE))}
+
+            def mk(key, h):
+                if key == "pack_then_compute":
+                    def f():
+                        h.pack(F.FIP_COL_MAJOR, n, n, n, A, n, "N", B, n, "N")
+                        h.zgemm(F.FIP_COL_MAJOR, n, n, n, al, A, n, "N", B, n, "N", be, C, n)
+                    return f
+                return lambda: h.zgemm(F.FIP_COL_MAJOR, n, n, n, al, A, n, "N", B, n, "N", be, C, n)
+            calls = {key: mk(key, h) for key, h in hs.items()}
+            for c in calls.values():
+                c()
+            torch.cuda.synchronize()
+            fl = 8.0 * float(n) ** 3
+            est = fl / (60e12 if dt == "z" else 120e12)
+            med = _median_times(torch, calls, 5, max(1, min(50, int(0.02 / est))))
+            row = {"dtype": dt, "n": n}
+            for key in calls:
+                row[key + "_us"] = round(med[key] * 1e3, 1)
+            row["fused_tflops"] = round(fl / (med["fused"] * 1e-3) / 1e12, 2)
+            row["fused_pct_peak"] = round(100 * row["fused_tflops"] / PEAK_TFLOPS["f64" if dt == "z" else "f32"], 2)
+            row["fused_vs_ptc"] = round(med["pack_then_compute"] / med["fused"], 3)
+            p = hs["fused"].last_plan()
+            row["fused_pack"] = [p.pack_a, p.pack_b]
+            log(f"[cx] {row}")
+            out.append(row)
+            for h in hs.values():
+                h.close()
+            del A, B, C
+            torch.cuda.empty_cache()
+    return out
+
+
 def plain_dgemm_section(F, torch):
     """C := A B + C, m = n = k = 256, column-major NN, alpha = beta = 1 (FP64)."""
     from paper_2302_08417_amd import synth
@@ -711,6 +818,13 @@ def compact_summary(result, full):
     if "syrk_trmm" in full:
         s["syrk_trmm_pct_peak"] = {f"{r['op']}_{r['dtype']}_{r['n']}": r["fused_pct_peak"]
                                    for r in full["syrk_trmm"] if r["n"] == 8192}
+    if "dma" in full:
+        s["dma_speedup"] = {f"{r['dtype']}_{r['n']}": [r["dma_speedup_no_pack"],
+                                                        r["dma_speedup_pack_then_compute"]]
+                            for r in full["dma"] if r["n"] == 8192}
+    if "complex_1m" in full:
+        s["complex_1m"] = {f"{r['dtype']}gemm_{r['n']}": [r["fused_pct_peak"], r["fused_vs_ptc"]]
+                           for r in full["complex_1m"] if r["n"] == 4096}
     if "autograd" in full:
         s["autograd"] = {k: full["autograd"][k] for k in ("ms_per_step", "pct_bf16_mfma_peak")}
     if "batched" in full:
@@ -739,6 +853,8 @@ def main():
     ap.add_argument("--mx-sizes", default="1024,4096,16384")
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-l3", action="store_true", help="skip the SYRK / TRMM section")
+    ap.add_argument("--no-cx", action="store_true", help="skip the complex (1m) section")
+    ap.add_argument("--no-dma", action="store_true", help="skip the LDS-DMA section")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--results", default=os.path.join("gpurun_out", "bench_full.json"),
                     help="file that receives every section's rows (the stdout line carries\n"
@@ -846,6 +962,10 @@ def main():
         full["mixed_precision_deep_k"] = mx_deep_k_section(F, torch)
     if not args.no_l3:
         full["syrk_trmm"] = l3_section(F, torch)
+    if not args.no_cx:
+        full["complex_1m"] = cx_section(F, torch)
+    if not args.no_dma:
+        full["dma"] = dma_section(F, torch)
     if not args.no_autograd:
         full["autograd"] = autograd_section(F, torch)
     if not args.no_batched:

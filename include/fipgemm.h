@@ -60,6 +60,8 @@ enum {
     FIP_E4M3 = 3,         /* OCP FP8 E4M3 operands (codes), optional power-of-two scales */
     FIP_BF16X3 = 4,       /* binary32 operands split into 3 bfloat16 terms, 6 products */
     FIP_BF16X3_FAST = 5,  /* binary32 operands split into 2 bfloat16 terms, 3 products */
+    FIP_C128 = 6,         /* complex binary64 (re, im pairs): fip_zgemm, the 1m method */
+    FIP_C64 = 7,          /* complex binary32 (re, im pairs): fip_cgemm, the 1m method */
 };
 
 /* Error codes (negative). */
@@ -128,6 +130,23 @@ enum {
        indexed by the hardware XCC id: every XCD packs its own copy of each
        panel it reads); -1 (default): 1. */
     FIP_ATTR_COPIES = 14,
+    /* Direct global-to-LDS loads.  An FP64/FP32 GEMM launch in which no
+       workgroup produces a pack (pack-then-compute's CONSUME_ONLY call, an
+       unpacked call, or a fused call whose plan packs nothing) and every chunk
+       can be fetched whole (all chunks packed; or unpacked with k a multiple
+       of the plan's KT, element-aligned operands, and m (n) a multiple of the
+       16-byte vector width when op(A) (op(B)) is stored along it) may run the
+       kernel variant that fetches each operand chunk with
+       global_load_lds_dwordx4 (no staging registers, no LDS stores; the
+       paper's Sec. 5 footnote expects DMA-fed packing to pay on GPUs).
+       1: every eligible launch; 0: none (every chunk goes through registers);
+       -1 (default): eligible binary64 launches that read their operands
+       unpacked (measured faster there; binary32 and pack-then-compute
+       consumers measured slower).  Same C bit for bit either way. */
+    FIP_ATTR_DMA = 15,
+    /* Read only: 1 if the most recent FP64/FP32 GEMM launch on the handle ran
+       the direct global-to-LDS variant (FIP_ATTR_DMA), else 0. */
+    FIP_ATTR_LAST_DMA = 16,
 };
 
 enum {
@@ -284,9 +303,48 @@ int fip_sgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, 
               char transB, float beta, float* C, int64_t ldc);
 
 /*
+ * Complex GEMM through the 1m method (paper Sec. 5: the 1m method encodes
+ * complex multiplication in the packing stage so that the real microkernel
+ * computes complex products).
+ *
+ *     C := alpha * op(A) * op(B) + beta * C     (complex; op in N, T, C where
+ *                                                'C' is the conjugate transpose)
+ *
+ * Storage: A, B and C are DEVICE arrays of (re, im) pairs (C99/C++ complex
+ * layout: binary64 pairs for fip_zgemm, binary32 for fip_cgemm), owned by the
+ * caller; lda, ldb, ldc count complex elements and obey the same minimums as
+ * fip_dgemm.  alpha and beta are HOST pointers to one (re, im) pair each,
+ * read during the call.
+ *
+ * Method: the kernel multiplies two real matrices.  Its A side is the
+ * 2m x 2k expansion of op(A) (complex element z becomes the 2 x 2 block
+ * [[re z, -im z], [im z, re z]]), its B side the 2k x n expansion of op(B)
+ * (element w becomes re w over im w), and their real product is the real view
+ * of the column-major complex C.  Row-major C runs as C^T = op(B)^T op(A)^T.
+ * The expansion is done while loading, so a first pass packs expanded chunks
+ * and later passes read them: the packed operands of fip_plan (dtype
+ * FIP_C128 / FIP_C64) are the real expanded matrices in the tile layout of the
+ * real path, and MT, KT, tiles_m, ksteps are real-expanded quantities (m, n,
+ * k stay the caller's).  Split k is not used.  Precision: binary64 (binary32)
+ * products and sums, per real component a sum of 2k products.
+ *
+ * Return codes: as fip_dgemm, with positions handle 1, layout 2, m 3, n 4,
+ * k 5, alpha 6, A 7, lda 8, transA 9, B 10, ldb 11, transB 12, beta 13, C 14,
+ * ldc 15 (a null alpha or beta is invalid).  Quick returns: m = 0 or n = 0, or
+ * (alpha = 0 or k = 0) and beta = 1: nothing; alpha = 0 or k = 0: C := beta C
+ * without reading A or B; beta = 0 never reads C.
+ */
+int fip_zgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k,
+              const double* alpha, const double* A, int64_t lda, char transA, const double* B,
+              int64_t ldb, char transB, const double* beta, double* C, int64_t ldc);
+int fip_cgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k,
+              const float* alpha, const float* A, int64_t lda, char transA, const float* B,
+              int64_t ldb, char transB, const float* beta, float* C, int64_t ldc);
+
+/*
  * Standalone pack (Sec. 2.1: conventional pack-then-compute): write copy 0 of
  * the packed op(A) and op(B) that a CONSUME_ONLY call of the same shape,
- * dtype (any FIP_F64 .. FIP_BF16X3_FAST) and tile class reads.  Both operands
+ * dtype (any FIP_F64 .. FIP_C64; complex dtypes pack the 1m expansions) and tile class reads.  Both operands
  * are packed whatever the shape.  Arguments as in fip_dgemm.
  */
 int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, int64_t k,

@@ -25,6 +25,11 @@ enum Kind : int32_t {
                  // triangle only; A and B sides are the same operand sharing one pack
     kTrmm = 2,   // C := alpha op(T) B + beta C or alpha B op(T) + beta C, T triangular:
                  // one side's chunks masked to the triangle, its zero k-steps skipped
+    k1m = 3,     // complex C := alpha op(A) op(B) + beta C through the 1m method: the
+                 // real product of the 2M x 2K expansion of the A side and the 2K x N
+                 // expansion of the B side is the real view of column-major complex C
+    kGemmDma = 4,  // (kernel variant of kGemm, chosen at launch) chunks fetched with
+                   // direct global -> LDS loads
 };
 
 // Tile rows per band of the XCD-aware tile order (see tile_coords).
@@ -69,6 +74,16 @@ struct LaunchDesc {
     int tri_side;      // TRMM: 1 = the kernel's A side is triangular, 2 = the B side
     int tri_keep_ge;   // TRMM: the triangular side keeps element (x, p) with x >= p (else x <= p)
     int tri_unit;      // TRMM: unit diagonal
+    // k1m (complex): M and K above are the real extents 2m' and 2k' of the
+    // expanded operands, A, B and C point at (re, im) pairs, the operand strides
+    // and ldc count complex elements; alpha and beta above are the real parts
+    double alpha_im, beta_im;
+    int conj_a, conj_b;   // the kernel side reads conj(X)
+    // GEMM: launches in which no tile produces a pack and every chunk can be
+    // fetched whole run the kernel variant that loads chunks with direct
+    // global -> LDS loads instead of through registers
+    int dma;
+    int* used_dma;     // out (nullable): whether the launch ran that variant
     hipStream_t stream;
 };
 

@@ -27,6 +27,8 @@ constexpr int64_t kMinSliceKCopy = 1024, kMinSliceKSplit = 256;
 // short is over before a later pass could read the pack, and its reads are
 // all first touches (each chunk is read once per tile either way).
 constexpr int64_t kMinPackKsteps = 4;
+// FIP_ATTR_DMA's default: the launch decides (see the attribute)
+constexpr int kDefaultDma = -1;
 
 // Epoch stamps of fused calls.  Claims and publish flags in a workspace are
 // compared for equality with the current call's stamp, so a stamp must never
@@ -85,6 +87,8 @@ struct fip_handle_s {
     int mx_tile;      // FIP_ATTR_MX_TILE (-1: planner's choice, 128, 256)
     int split_k;      // FIP_ATTR_SPLIT_K (-1: planner's choice, 1: off, 2..64: forced)
     int copies;       // FIP_ATTR_COPIES (-1: planner's choice, 1 or 8)
+    int dma;          // FIP_ATTR_DMA (-1, 0 or 1)
+    int last_dma;     // FIP_ATTR_LAST_DMA
     int last_hip_error;  // FIP_ATTR_LAST_HIP_ERROR
     VbState* vb;
 };
@@ -212,7 +216,11 @@ int mx_form_of(int dtype)
     }
 }
 
-bool valid_dtype(int dtype) { return dtype == FIP_F64 || dtype == FIP_F32 || mx_form_of(dtype) >= 0; }
+bool is_complex(int dtype) { return dtype == FIP_C128 || dtype == FIP_C64; }
+bool valid_dtype(int dtype)
+{
+    return dtype == FIP_F64 || dtype == FIP_F32 || is_complex(dtype) || mx_form_of(dtype) >= 0;
+}
 
 void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
                char tA, char tB, bool standalone_pack, Plan* pl, int policy_override = -1)
@@ -225,6 +233,11 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     // band once, so later rounds find them packed) measured 20-35 % faster.
     pl->order = h->order >= 0 ? h->order : (form == fip::kMxX3 || form == fip::kMxX3Fast ? 1 : 0);
     pl->ks = kernel_shape(layout, m, n);
+    // Complex calls (1m method): the kernel multiplies the 2M x 2K expansion of
+    // its A side by the 2K x N expansion of its B side, all in real terms.
+    const bool cx = is_complex(dtype);
+    if (cx) pl->ks.M *= 2;
+    const int64_t kr = cx ? 2 * k : k;
     int cls, MT, KT;
     int64_t resident;
     if (form >= 0) {
@@ -241,7 +254,7 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
         pl->elem = fip::mx_planes(form) * fip::mx_pack_bytes(form);
         resident = 256 * fip::mx_per_cu(form, MT);
     } else {
-        pl->elem = dtype == FIP_F64 ? 8 : 4;
+        pl->elem = dtype == FIP_F64 || dtype == FIP_C128 ? 8 : 4;
         cls = h->tile_override >= 0 ? h->tile_override : choose_tile_class(pl->ks.M, pl->ks.N);
         MT = fip::tile_mt(cls);
         KT = fip::tile_kt(cls, pl->elem);
@@ -250,7 +263,7 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     const int NT = MT;
     pl->tilesKM = cdiv(pl->ks.M, MT);
     pl->tilesKN = cdiv(pl->ks.N, NT);
-    pl->nK = cdiv(k, KT);
+    pl->nK = cdiv(kr, KT);
 
     // Split k: when the tiles leave most of the device idle, k is cut into
     // slices, one workgroup per (tile, slice), up to the resident count; a
@@ -266,7 +279,7 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     // the pack policy), so every policy runs the same arithmetic.
     pl->split = 1;
     pl->slice_ksteps = (int)pl->nK;
-    if ((form < 0 || MT == fip::kMxTile) && pl->nK > 1) {
+    if ((form < 0 || MT == fip::kMxTile) && pl->nK > 1 && !cx) {
         const int64_t tiles = pl->tilesKM * pl->tilesKN;
         const int64_t busy = form < 0 ? 2 : 4;
         const bool splits = form == fip::kMxX3 || form == fip::kMxX3Fast;
@@ -355,9 +368,22 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
             //    the tile) is packed: its unpacked chunks take the masked,
             //    zero-filling loads, its packed chunks are zero padded and
             //    read with the same unmasked loads as any other.
+            //  - Complex operands (1m): a chunk that keeps whole complex
+            //    elements in its vectors (the A side, a K-major B side) is
+            //    loaded raw and arranged after the step's MFMAs, as fast as a
+            //    packed read (binary64 at 4096^3: 9.74 ms unpacked, 9.78 ms
+            //    packing the A side); an MN-major B side takes one component
+            //    of two loads per vector and is arranged before its MFMAs, so
+            //    its reused panels are packed.  Fringe panels as below.
             if (split_form) {
                 pl->kpack_a = reuse_a;
                 pl->kpack_b = reuse_b;
+            } else if (cx) {
+                const bool kb_mn = pl->ks.swapped ? mn_major(false, layout, tA) : mn_major(true, layout, tB);
+                pl->kpack_a = reuse_a && pl->ks.M % MT != 0;
+                pl->kpack_b = reuse_b && (pl->ks.N % NT != 0 || kb_mn);
+                pl->kfrom_a = (int)pl->tilesKM - 1;
+                pl->kfrom_b = kb_mn ? 0 : (int)pl->tilesKN - 1;
             } else {
                 pl->kpack_a = reuse_a && pl->ks.M % MT != 0;
                 pl->kpack_b = reuse_b && pl->ks.N % NT != 0;
@@ -567,6 +593,8 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.no_publish = h->no_publish;
         d.stats = noalloc ? 0 : h->stats;   // the scratch array's counters are never cleared
         d.order = pl.order;
+        d.dma = h->dma;
+        d.used_dma = &h->last_dma;
         d.M = ks.M; d.N = ks.N; d.K = k;
         fill_operands(pl, layout, A, lda, tA, B, ldb, tB, &d);
         d.C = C; d.ldc = ldc;
@@ -575,6 +603,83 @@ int gemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64
         d.slice_ksteps = pl.slice_ksteps;
         if (pl.pub.workspace_bytes > 0) {
             fill_workspace(ws_base, pl, &d);
+            if (pl.mode == fip::kModeFused) d.epoch = h->epoch = next_epoch();
+        } else {
+            d.stats = 0;
+        }
+        d.stream = h->stream;
+        if (const hipError_t e = fip::launch_gemm(d); e != hipSuccess) return launch_failed(h, e);
+        h->last = pl.pub;
+        h->has_last = 1;
+        return 0;
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+// Complex GEMM through the 1m method (paper Sec. 5: complex multiplication
+// encoded in the packing, the real microkernel unchanged).  The tile kernel's
+// A side is the 2M x 2K real expansion of op(A) (each element a 2 x 2 block
+// [[re, -im], [im, re]]), its B side the 2K x N expansion of op(B) (each
+// element its (re, im) pair along k), and their real product is the real view
+// of column-major complex C (rows 2i, 2i + 1: re, im of row i).  Row-major C
+// is handled as C^T = op(B)^T op(A)^T like the real path: op(X)^T of a
+// conjugate transpose is conj(X), so each side carries a conjugation flag.
+// The expansion happens in the loads; a packed panel holds it.  alpha and
+// beta are (re, im) pairs on the host.
+template <typename T>
+int zgemm_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+               const T* alpha, const T* A, int64_t lda, char tA, const T* B, int64_t ldb,
+               char tB, const T* beta, T* C, int64_t ldc)
+{
+    try {
+        if (!valid_handle(h)) return FIP_ERR_HANDLE;
+        // positions: layout 2, m 3, n 4, k 5, alpha 6, A 7, lda 8, transA 9, B 10, ldb 11,
+        // transB 12, beta 13, C 14, ldc 15
+        if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 2;
+        if (alpha == nullptr) return 6;
+        if (beta == nullptr) return 13;
+        const bool a_nz = alpha[0] != T(0) || alpha[1] != T(0);
+        const bool b_one = beta[0] == T(1) && beta[1] == T(0);
+        const int bad = check_args(2, layout, m, n, k, a_nz, A, lda, tA, B, ldb, tB, true, b_one,
+                                   C, ldc);
+        if (bad) return bad;
+        if (m == 0 || n == 0) return 0;
+        if ((!a_nz || k == 0) && b_one) return 0;
+        const bool no_ab = !a_nz || k == 0;   // C := beta C, A and B not read
+        Plan pl;
+        make_plan(h, dtype, layout, m, n, no_ab ? 0 : k, tA, tB, false, &pl);
+        if (const int ws = prepare_workspace(h, pl); ws) return ws;
+        fip::LaunchDesc d;
+        memset(&d, 0, sizeof(d));
+        d.elem = sizeof(T);
+        d.kind = fip::k1m;
+        d.tile_class = pl.pub.tile_class;
+        d.mode = pl.mode;
+        d.pack_a = pl.kpack_a; d.pack_b = pl.kpack_b;
+        d.a_pack_from = pl.kfrom_a; d.b_pack_from = pl.kfrom_b;
+        d.shared_copy = pl.shared_copy;
+        d.no_publish = h->no_publish;
+        d.stats = h->stats;
+        d.order = pl.order;
+        d.M = pl.ks.M;                 // 2 x the kernel's complex rows
+        d.N = pl.ks.N;
+        d.K = no_ab ? 0 : 2 * k;
+        // operand strides in complex elements, as the real path sets them
+        fill_operands(pl, layout, A, lda, tA, B, ldb, tB, &d);
+        // conjugation per kernel side: op 'C' conjugates; on the swapped
+        // (row-major) path the side holds op(X)^T, conjugated for 'C' as well
+        const bool ca = tA == 'C' || tA == 'c', cb = tB == 'C' || tB == 'c';
+        d.conj_a = pl.ks.swapped ? cb : ca;
+        d.conj_b = pl.ks.swapped ? ca : cb;
+        d.C = C; d.ldc = ldc;
+        d.alpha = no_ab ? 0.0 : (double)alpha[0];
+        d.alpha_im = no_ab ? 0.0 : (double)alpha[1];
+        d.beta = (double)beta[0]; d.beta_im = (double)beta[1];
+        d.split = 1;
+        d.slice_ksteps = (int)pl.nK;
+        if (pl.pub.workspace_bytes > 0) {
+            fill_workspace(h->ws, pl, &d);
             if (pl.mode == fip::kModeFused) d.epoch = h->epoch = next_epoch();
         } else {
             d.stats = 0;
@@ -1179,6 +1284,7 @@ int fip_create(fip_handle_t* handle)
     h->mx_tile = -1;
     h->split_k = -1;
     h->copies = -1;
+    h->dma = kDefaultDma;
     h->vb = nullptr;
     *handle = h;
     return 0;
@@ -1240,6 +1346,10 @@ int fip_set_attr(fip_handle_t handle, int attr, int64_t value)
         if (value != -1 && value != 1 && value != fip::kCopies) return 3;
         handle->copies = (int)value;
         return 0;
+    case FIP_ATTR_DMA:
+        if (value != 0 && value != 1 && value != -1) return 3;
+        handle->dma = (int)value;
+        return 0;
     default:
         return 2;
     }
@@ -1262,6 +1372,8 @@ int fip_get_attr(fip_handle_t handle, int attr, int64_t* value)
     case FIP_ATTR_MX_TILE: *value = handle->mx_tile; return 0;
     case FIP_ATTR_SPLIT_K: *value = handle->split_k; return 0;
     case FIP_ATTR_COPIES: *value = handle->copies; return 0;
+    case FIP_ATTR_DMA: *value = handle->dma; return 0;
+    case FIP_ATTR_LAST_DMA: *value = handle->last_dma; return 0;
     case FIP_ATTR_VB_STATUS: {
         *value = 0;
         VbState* v = handle->vb;
@@ -1339,6 +1451,22 @@ int fip_sgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, 
 {
     return gemm_impl<float>(handle, FIP_F32, layout, m, n, k, alpha, A, lda, transA, B, ldb,
                             transB, beta, C, ldc);
+}
+
+int fip_zgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k,
+              const double* alpha, const double* A, int64_t lda, char transA, const double* B,
+              int64_t ldb, char transB, const double* beta, double* C, int64_t ldc)
+{
+    return zgemm_impl<double>(handle, FIP_C128, layout, m, n, k, alpha, A, lda, transA, B, ldb,
+                              transB, beta, C, ldc);
+}
+
+int fip_cgemm(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k,
+              const float* alpha, const float* A, int64_t lda, char transA, const float* B,
+              int64_t ldb, char transB, const float* beta, float* C, int64_t ldc)
+{
+    return zgemm_impl<float>(handle, FIP_C64, layout, m, n, k, alpha, A, lda, transA, B, ldb,
+                             transB, beta, C, ldc);
 }
 
 int fip_dsyrk(fip_handle_t handle, int layout, char uplo, char trans, int64_t n, int64_t k,
@@ -1432,6 +1560,13 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
         d.mode = pl.mode;
         d.M = pl.ks.M; d.N = pl.ks.N; d.K = k;
         fill_operands(pl, layout, A, lda, transA, B, ldb, transB, &d);
+        if (is_complex(dtype)) {   // the 1m expansions (see zgemm_impl)
+            d.kind = fip::k1m;
+            d.K = 2 * k;
+            const bool ca = transA == 'C' || transA == 'c', cb = transB == 'C' || transB == 'c';
+            d.conj_a = pl.ks.swapped ? cb : ca;
+            d.conj_b = pl.ks.swapped ? ca : cb;
+        }
         fill_workspace(handle->ws, pl, &d);
         d.stream = handle->stream;
         if (const hipError_t e = fip::launch_pack(d); e != hipSuccess) return launch_failed(handle, e);

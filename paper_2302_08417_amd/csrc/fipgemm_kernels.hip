@@ -58,6 +58,8 @@ struct Params {
     int tri_side;             // TRMM: 1 = A side triangular, 2 = B side
     int tri_keep_ge;          // TRMM: element (x, p) kept when x >= p (else x <= p)
     int tri_unit;             // TRMM: the diagonal x == p reads as 1
+    T alpha_im, beta_im;      // k1m: imaginary parts of alpha and beta
+    int conj_a, conj_b;       // k1m: the side reads the conjugated operand
 };
 
 // TRMM: workgroup w -> tile, longest k-range first.  A tile's k-range is set
@@ -154,15 +156,39 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     // in 32 bits).  A tile is interior along MN when it lies fully inside.
     const int64_t lda = AKC ? P.a_smn : P.a_sk, ldb = BKC ? P.b_smn : P.b_sk;
     const bool a_in = P.a_fast && x0a + MT <= P.M, b_in = P.b_fast && x0b + NT <= P.N;
-    const char* a_org = reinterpret_cast<const char*>(P.A + (AKC ? x0a * lda : x0a));
-    const char* b_org = reinterpret_cast<const char*>(P.B + (BKC ? x0b * ldb : x0b));
-    const int64_t a_step = (AKC ? KT : KT * lda) * (int64_t)sizeof(T);  // bytes per chunk
-    const int64_t b_step = (BKC ? KT : KT * ldb) * (int64_t)sizeof(T);
+    // chunk origin and bytes per chunk; k1m: in complex elements of 2 T (the
+    // A side's real row x0a is complex row x0a/2, a chunk spans KT/2 complex k)
+    constexpr bool CX = KIND == k1m;
+    constexpr int64_t ES = CX ? 2 * (int64_t)sizeof(T) : (int64_t)sizeof(T);
+    const int64_t ra0 = CX ? x0a / 2 : x0a, kstep = CX ? KT / 2 : KT;
+    const char* a_org = reinterpret_cast<const char*>(P.A) + (AKC ? ra0 * lda : ra0) * ES;
+    const char* b_org = reinterpret_cast<const char*>(P.B) + (BKC ? x0b * ldb : x0b) * ES;
+    const int64_t a_step = (AKC ? kstep : kstep * lda) * ES;
+    const int64_t b_step = (BKC ? kstep : kstep * ldb) * ES;
     uint32_t a_off[ChA::NV], b_off[ChB::NV];
+    // A fringe tile (overhanging M or N) may read its full-k chunks the same
+    // way when no vector straddles the edge: a vector outside the operand
+    // reads the chunk origin instead (a valid element).  Rows of the A side
+    // beyond M (columns of the B side beyond N) only ever reach C entries
+    // outside the matrix, which the epilogue does not store, so their values
+    // do not matter; only a packed copy must hold zeros there, so the
+    // producer of a fringe panel keeps the zero-filling loads.
+    constexpr int VEC = Types<T>::VEC;
+    const bool a_ff = P.a_fast && !a_in && (AKC || P.M % VEC == 0);
+    const bool b_ff = P.b_fast && !b_in && (BKC || P.N % VEC == 0);
+    uint32_t apar = 0, bpar = 0;   // k1m: per-vector arrangement bits
 #pragma unroll
-    for (int i = 0; i < ChA::NV; ++i) a_off[i] = ChA::fast_offset(i, tid, lda);
+    for (int i = 0; i < ChA::NV; ++i) {
+        const uint32_t o = CX ? ChA::template cx_offset<0>(i, tid, lda) : ChA::fast_offset(i, tid, lda);
+        a_off[i] = a_ff && !ChA::vec_inside(i, tid, x0a, P.M) ? 0u : o;
+        if (CX && ChA::template cx_par<0>(i, tid)) apar |= 1u << i;
+    }
 #pragma unroll
-    for (int i = 0; i < ChB::NV; ++i) b_off[i] = ChB::fast_offset(i, tid, ldb);
+    for (int i = 0; i < ChB::NV; ++i) {
+        const uint32_t o = CX ? ChB::template cx_offset<1>(i, tid, ldb) : ChB::fast_offset(i, tid, ldb);
+        b_off[i] = b_ff && !ChB::vec_inside(i, tid, x0b, P.N) ? 0u : o;
+        if (CX && ChB::template cx_par<1>(i, tid)) bpar |= 1u << i;
+    }
 
     const bool consume = P.mode == kModeConsumePacked;
     bool fused = P.mode == kModeFused;
@@ -210,6 +236,9 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
     const bool prodA = s_role & 1, prodB = s_role & 2;
     const bool producer = prodA || prodB;
     const bool wantA = useA && !prodA, wantB = useB && !prodB;  // would read a packed copy
+    // unpacked full-k chunks through the offset loader (interior tiles, and
+    // fringe tiles that do not produce a pack)
+    const bool a_fastpath = a_in || (a_ff && !prodA), b_fastpath = b_in || (b_ff && !prodB);
 
     // Later passes (Sec. 3.1) read the packed copy once its producer has
     // published the whole panel.  Packed and unpacked sources stage the same
@@ -235,12 +264,50 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         const int64_t p0 = (int64_t)c * KT;
         return P.tri_keep_ge ? p0 + KT - 1 >= tx0 : p0 <= tx0 + tmn - 1;
     };
+    // k1m: whether the chunk in registers still awaits its 1m arrangement
+    bool a_cxraw = false, b_cxraw = false;
+    auto cx_settle = [&]() {
+        if constexpr (CX) {
+            if (a_cxraw) ra.template cx_fix<0>(apar, P.conj_a);
+            if (b_cxraw) rb.template cx_fix<1>(bpar, P.conj_b);
+        }
+    };
     // Packed chunks and interior unpacked chunks are read by one and the same
     // vector-load sequence: only the base pointer and the per-lane offsets
     // differ (packed element o sits o*sizeof(T) bytes into its chunk).
     auto load_chunks = [&](int c) {
         const bool kin = c < nKfull;
-        if (apk || (a_in && kin)) {
+        if constexpr (CX) {
+            // complex operands: the packed copy holds the expanded real chunk;
+            // interior chunks that arrange in place are loaded raw and
+            // arranged by cx_settle once the step's MFMAs have been issued
+            a_cxraw = b_cxraw = false;
+            if (apk) {
+                ra.load_packed(apanel + (int64_t)c * KT * MT, tid);
+            } else if (a_fastpath && kin) {
+                if constexpr (ChA::template cx_in_place<0>()) {
+                    ra.load_at(a_org + (int64_t)c * a_step, a_off);
+                    a_cxraw = true;
+                } else {
+                    ra.template load_cx_at<0>(a_org + (int64_t)c * a_step, a_off, apar, P.conj_a);
+                }
+            } else {
+                ra.template load_cx_edge<0>(P.A, lda, P.M / 2, P.K / 2, x0a, (int64_t)c * KT, P.conj_a, tid);
+            }
+            if (bpk) {
+                rb.load_packed(bpanel + (int64_t)c * KT * NT, tid);
+            } else if (b_fastpath && kin) {
+                if constexpr (ChB::template cx_in_place<1>()) {
+                    rb.load_at(b_org + (int64_t)c * b_step, b_off);
+                    b_cxraw = true;
+                } else {
+                    rb.template load_cx_at<1>(b_org + (int64_t)c * b_step, b_off, bpar, P.conj_b);
+                }
+            } else {
+                rb.template load_cx_edge<1>(P.B, ldb, P.N, P.K / 2, x0b, (int64_t)c * KT, P.conj_b, tid);
+            }
+        } else {
+        if (apk || (a_fastpath && kin)) {
             const char* base = apk ? reinterpret_cast<const char*>(apanel + (int64_t)c * KT * MT)
                                    : a_org + (int64_t)c * a_step;
             uint32_t off[ChA::NV];
@@ -251,7 +318,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
         } else {
             ra.load_edge(P.A, lda, P.M, P.K, x0a, (int64_t)c * KT, P.a_vec, tid);
         }
-        if (bpk || (b_in && kin)) {
+        if (bpk || (b_fastpath && kin)) {
             const char* base = bpk ? reinterpret_cast<const char*>(bpanel + (int64_t)c * KT * NT)
                                    : b_org + (int64_t)c * b_step;
             uint32_t off[ChB::NV];
@@ -261,6 +328,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
             rb.load_at(base, off);
         } else {
             rb.load_edge(P.B, ldb, P.N, P.K, x0b, (int64_t)c * KT, P.b_vec, tid);
+        }
         }
         // TRMM: an unpacked chunk that meets the diagonal gets the triangle
         // applied in registers (zeros outside it, ones on a unit diagonal)
@@ -282,8 +350,56 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
 
+    // MFMAs on the chunk in LDS buffer cur.  Fragment element (row x, k-row
+    // kr) of either orientation: lane l supplies x = base + l%16, kr = 4s + l/16.
+    auto mfma_step = [&](int cur) {
+        const T* la = sA[cur] + ChA::lds_at(wm * WTM + (lane & 15), lane >> 4);
+        const T* lb = sB[cur] + ChB::lds_at(wn * WTN + (lane & 15), lane >> 4);
+#pragma unroll
+        for (int s = 0; s < KT / 4; ++s) {
+            T af[FM], bf[FN];
+#pragma unroll
+            for (int a = 0; a < FM; ++a) af[a] = la[ChA::lds_at(a * 16, 4 * s)];
+#pragma unroll
+            for (int b = 0; b < FN; ++b) bf[b] = lb[ChB::lds_at(b * 16, 4 * s)];
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(af[a], bf[b], acc[a][b]);
+        }
+    };
+    if constexpr (KIND == kGemmDma) {
+        // Direct global -> LDS loads (the paper's footnote to Sec. 5: on a GPU
+        // whose L1-level store is a DMA-fed scratchpad, packing through DMA is
+        // expected to pay).  The host launches this variant only when no tile
+        // produces a pack and every chunk can be fetched whole: all chunks
+        // packed (pack-then-compute), or unpacked with k a multiple of KT and
+        // the operands readable through the offset loaders.  Each wave fetches
+        // its share of a chunk straight into the LDS buffer: no staging
+        // registers, no LDS stores; every element lands where the register
+        // path stores it, so C is the same bit for bit.
+        auto stage = [&](int c, int buf) {
+            if (apk) ChA::dma_issue(sA[buf], reinterpret_cast<const char*>(apanel + (int64_t)c * KT * MT), -1, 0, 0, wave, lane);
+            else ChA::dma_issue(sA[buf], a_org + (int64_t)c * a_step, lda, x0a, P.M, wave, lane);
+            if (bpk) ChB::dma_issue(sB[buf], reinterpret_cast<const char*>(bpanel + (int64_t)c * KT * NT), -1, 0, 0, wave, lane);
+            else ChB::dma_issue(sB[buf], b_org + (int64_t)c * b_step, ldb, x0b, P.N, wave, lane);
+            if (P.do_stats && tid == 0) n_pk += consume ? 2 : 0;
+        };
+        stage(q0, 0);
+        wait_all_memory();
+        __syncthreads();
+        for (int q = q0; q < q1; ++q) {
+            const int cur = (q - q0) & 1;
+            // the other buffer was last read before the previous barrier
+            if (q + 1 < q1) stage(q + 1, cur ^ 1);
+            mfma_step(cur);
+            wait_all_memory();   // this wave's loads into LDS have landed
+            __syncthreads();
+        }
+    } else {
     // Prologue: stage the slice's first chunk.
     load_chunks(q0);
+    cx_settle();
     ra.store_lds(sA[0], tid);
     rb.store_lds(sB[0], tid);
     if (prodA) ra.store_pack(apanel + (int64_t)q0 * KT * MT, tid);
@@ -303,23 +419,9 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
             if (wantB && !bpk) fb = peek_flag(bdone);
         }
         if (more) load_chunks(q + 1);
-        // MFMAs on chunk q.  Fragment element (row x, k-row kr) of either
-        // orientation: lane l supplies x = base + l%16, kr = 4s + l/16.
-        const T* la = sA[cur] + ChA::lds_at(wm * WTM + (lane & 15), lane >> 4);
-        const T* lb = sB[cur] + ChB::lds_at(wn * WTN + (lane & 15), lane >> 4);
-#pragma unroll
-        for (int s = 0; s < KT / 4; ++s) {
-            T af[FM], bf[FN];
-#pragma unroll
-            for (int a = 0; a < FM; ++a) af[a] = la[ChA::lds_at(a * 16, 4 * s)];
-#pragma unroll
-            for (int b = 0; b < FN; ++b) bf[b] = lb[ChB::lds_at(b * 16, 4 * s)];
-#pragma unroll
-            for (int a = 0; a < FM; ++a)
-#pragma unroll
-                for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(af[a], bf[b], acc[a][b]);
-        }
+        mfma_step(cur);
         if (more) {
+            cx_settle();
             ra.store_lds(sA[cur ^ 1], tid);
             rb.store_lds(sB[cur ^ 1], tid);
             if (prodA) ra.store_pack(apanel + (int64_t)(q + 1) * KT * MT, tid);
@@ -334,6 +436,7 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
             if (P.do_stats && tid == 0) ++n_polls;
         }
         __syncthreads();
+    }
     }
 
     // The producer publishes its panel once every pack store of it has
@@ -380,6 +483,57 @@ __global__ void __launch_bounds__(WM * WN * 64, 2) gemm_kernel(const Params<T> P
                         const int64_t i = r0 + a * 16 + di_(r), j = c0 + b * 16 + dj_(r);
                         if (i < P.M && j < P.N) pp[i + j * P.M] = acc[a][b][r];
                     }
+                }
+            }
+        return;
+    }
+
+    if constexpr (CX) {
+        // Complex epilogue on the real view of C (a pair array with real
+        // leading dimension 2 ldc): kernel rows 2i and 2i + 1 hold re and im of
+        // complex row i.  C = alpha * acc + beta * C in complex arithmetic; C
+        // is not read when beta == 0.  A lane needs the other component of each
+        // of its entries: FP64 keeps one row per lane, so it comes from the
+        // neighbouring lane (the other parity); FP32 keeps row pairs (items
+        // r, r ^ 1) in the lane.  Each lane reads both components of C before
+        // any store of the pair.
+        const T ar = P.alpha, ai = P.alpha_im, br = P.beta, bi = P.beta_im;
+        const bool has_beta = br != T(0) || bi != T(0);
+        const int64_t ldr = 2 * P.ldc;
+        const int64_t r0c = x0a + wm * WTM, c0c = x0b + wn * WTN;
+        auto dic = [&](int r) -> int { return sizeof(T) == 8 ? (lane & 15) : 4 * (lane >> 4) + r; };
+        auto djc = [&](int r) -> int { return sizeof(T) == 8 ? 4 * r + (lane >> 4) : (lane & 15); };
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+                T v[4], w[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = acc[a][b][r];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if constexpr (sizeof(T) == 8) w[r] = __shfl_xor(v[r], 1);
+                    else w[r] = v[r ^ 1];
+                }
+                // both components of every entry are read before any store
+                // (with FP32 one lane stores both of them)
+                T o[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = r0c + a * 16 + dic(r), j = c0c + b * 16 + djc(r);
+                    const bool imr = i & 1;
+                    const T sre = imr ? w[r] : v[r], sim = imr ? v[r] : w[r];
+                    o[r] = imr ? ar * sim + ai * sre : ar * sre - ai * sim;
+                    if (has_beta && i < P.M && j < P.N) {
+                        const T cre = P.C[(i & ~(int64_t)1) + j * ldr];
+                        const T cim = P.C[(i | 1) + j * ldr];
+                        o[r] = o[r] + (imr ? br * cim + bi * cre : br * cre - bi * cim);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = r0c + a * 16 + dic(r), j = c0c + b * 16 + djc(r);
+                    if (i < P.M && j < P.N) P.C[i + j * ldr] = o[r];
                 }
             }
         return;
@@ -477,7 +631,8 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(const T* __restrict_
 // Standalone pack of both operands into copy 0 (the first half of the
 // conventional pack-then-compute baseline).  Same register mapping and
 // stores as a producer of the tile kernel, one chunk per workgroup.
-template <typename T, int MT, int NT, int KT, int NTHR, bool AKC, bool BKC>
+// CX: complex operands, packed as their 1m expansions (real chunks).
+template <typename T, int MT, int NT, int KT, int NTHR, bool AKC, bool BKC, bool CX>
 __global__ void __launch_bounds__(NTHR) pack_kernel(const Params<T> P)
 {
     const int tid = threadIdx.x;
@@ -487,13 +642,17 @@ __global__ void __launch_bounds__(NTHR) pack_kernel(const Params<T> P)
     if (b < nA) {
         const int64_t t = b / nK, q = b % nK;
         Chunk<T, MT, KT, NTHR, AKC> r;
-        r.load_edge(P.A, AKC ? P.a_smn : P.a_sk, P.M, P.K, t * MT, q * KT, P.a_vec, tid);
+        const int64_t ld = AKC ? P.a_smn : P.a_sk;
+        if constexpr (CX) r.template load_cx_edge<0>(P.A, ld, P.M / 2, P.K / 2, t * MT, q * KT, P.conj_a, tid);
+        else r.load_edge(P.A, ld, P.M, P.K, t * MT, q * KT, P.a_vec, tid);
         r.store_pack(P.apack + (t * nK + q) * KT * MT, tid);
     } else {
         const int64_t bb = b - nA;
         const int64_t t = bb / nK, q = bb % nK;
         Chunk<T, NT, KT, NTHR, BKC> r;
-        r.load_edge(P.B, BKC ? P.b_smn : P.b_sk, P.N, P.K, t * NT, q * KT, P.b_vec, tid);
+        const int64_t ld = BKC ? P.b_smn : P.b_sk;
+        if constexpr (CX) r.template load_cx_edge<1>(P.B, ld, P.N, P.K / 2, t * NT, q * KT, P.conj_b, tid);
+        else r.load_edge(P.B, ld, P.N, P.K, t * NT, q * KT, P.b_vec, tid);
         r.store_pack(P.bpack + (t * nK + q) * KT * NT, tid);
     }
 }
@@ -563,6 +722,17 @@ Params<T> make_params(const LaunchDesc& d, int MT, int NT, int KT)
     P.tri_side = d.tri_side;
     P.tri_keep_ge = d.tri_keep_ge;
     P.tri_unit = d.tri_unit;
+    P.alpha_im = (T)d.alpha_im;
+    P.beta_im = (T)d.beta_im;
+    P.conj_a = d.conj_a;
+    P.conj_b = d.conj_b;
+    if (d.kind == k1m) {
+        // complex operands: a chunk spans MT/2 (A side) or NT complex elements
+        // along MN and KT/2 along k, each of 2 T; the spans above counted real
+        // elements of the expanded extents, so twice them bounds the bytes
+        P.a_fast = P.a_vec && 2 * a_span < ((int64_t)1 << 31);
+        P.b_fast = P.b_vec && 2 * b_span < ((int64_t)1 << 31);
+    }
     return P;
 }
 
@@ -584,7 +754,24 @@ hipError_t launch_tile(const LaunchDesc& d)
     const int64_t tiles = d.kind == kSyrk ? (int64_t)P.tilesM * (P.tilesM + 1) / 2
                                           : (int64_t)P.tilesM * P.tilesN;
     const dim3 grid((unsigned)(tiles * P.split)), block(WM * WN * 64);
-    if (d.kind == kSyrk) launch_oriented<T, MT, NT, KT, WM, WN, kSyrk>(akc, bkc, grid, block, d.stream, P);
+    // GEMM through direct global -> LDS loads: only when no tile produces a
+    // pack and every chunk can be fetched whole (see kGemmDma in the kernel)
+    constexpr int VEC = Types<T>::VEC;
+    const bool no_producer = d.mode == kModeConsumePacked || d.mode == kModeUnpacked ||
+                             (d.mode == kModeFused && !d.pack_a && !d.pack_b);
+    const bool whole = d.mode == kModeConsumePacked ||
+                       (d.K % KT == 0 && P.a_fast && P.b_fast && (akc || d.M % VEC == 0) &&
+                        (bkc || d.N % VEC == 0));
+    // FIP_ATTR_DMA: 1 always, 0 never, -1 (default) where it measured faster:
+    // binary64 launches that read their operands unpacked (binary32 ran 3-5 %
+    // slower through it, binary64 pack-then-compute up to 2.6 % slower)
+    const bool want = d.dma == 1 || (d.dma == -1 && sizeof(T) == 8 && d.mode != kModeConsumePacked);
+    const bool dma = d.kind == kGemm && want && no_producer && whole;
+    if (d.used_dma) *d.used_dma = dma;
+    if (dma)
+        launch_oriented<T, MT, NT, KT, WM, WN, kGemmDma>(akc, bkc, grid, block, d.stream, P);
+    else if (d.kind == k1m) launch_oriented<T, MT, NT, KT, WM, WN, k1m>(akc, bkc, grid, block, d.stream, P);
+    else if (d.kind == kSyrk) launch_oriented<T, MT, NT, KT, WM, WN, kSyrk>(akc, bkc, grid, block, d.stream, P);
     else if (d.kind == kTrmm) launch_oriented<T, MT, NT, KT, WM, WN, kTrmm>(akc, bkc, grid, block, d.stream, P);
     else launch_oriented<T, MT, NT, KT, WM, WN, kGemm>(akc, bkc, grid, block, d.stream, P);
     if (P.split > 1) {
@@ -607,10 +794,17 @@ hipError_t launch_pack_t(const LaunchDesc& d)
     const bool akc = d.a_kmajor, bkc = d.b_kmajor;
     const int64_t blocks = ((int64_t)P.tilesM + P.tilesN) * P.nK;
     const dim3 grid((unsigned)blocks), block(NTHR);
-    if (!akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, false, false><<<grid, block, 0, d.stream>>>(P);
-    else if (!akc && bkc) pack_kernel<T, MT, NT, KT, NTHR, false, true><<<grid, block, 0, d.stream>>>(P);
-    else if (akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, true, false><<<grid, block, 0, d.stream>>>(P);
-    else pack_kernel<T, MT, NT, KT, NTHR, true, true><<<grid, block, 0, d.stream>>>(P);
+    if (d.kind == k1m) {
+        if (!akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, false, false, true><<<grid, block, 0, d.stream>>>(P);
+        else if (!akc && bkc) pack_kernel<T, MT, NT, KT, NTHR, false, true, true><<<grid, block, 0, d.stream>>>(P);
+        else if (akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, true, false, true><<<grid, block, 0, d.stream>>>(P);
+        else pack_kernel<T, MT, NT, KT, NTHR, true, true, true><<<grid, block, 0, d.stream>>>(P);
+    } else {
+        if (!akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, false, false, false><<<grid, block, 0, d.stream>>>(P);
+        else if (!akc && bkc) pack_kernel<T, MT, NT, KT, NTHR, false, true, false><<<grid, block, 0, d.stream>>>(P);
+        else if (akc && !bkc) pack_kernel<T, MT, NT, KT, NTHR, true, false, false><<<grid, block, 0, d.stream>>>(P);
+        else pack_kernel<T, MT, NT, KT, NTHR, true, true, false><<<grid, block, 0, d.stream>>>(P);
+    }
     return hipGetLastError();
 }
 

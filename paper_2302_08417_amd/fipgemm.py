@@ -30,6 +30,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 FIP_COL_MAJOR, FIP_ROW_MAJOR = 0, 1
 FIP_F64, FIP_F32, FIP_BF16, FIP_E4M3, FIP_BF16X3, FIP_BF16X3_FAST = 0, 1, 2, 3, 4, 5
+FIP_C128, FIP_C64 = 6, 7
 MX_FORMS = (FIP_BF16, FIP_E4M3, FIP_BF16X3, FIP_BF16X3_FAST)
 FIP_ERR_HANDLE, FIP_ERR_WORKSPACE, FIP_ERR_LAUNCH, FIP_ERR_UNSUPPORTED, FIP_ERR_ALLOC = -1, -2, -3, -4, -5
 FIP_ATTR_PACK_POLICY, FIP_ATTR_TILE, FIP_ATTR_NO_PUBLISH, FIP_ATTR_STATS, FIP_ATTR_EPOCH = 1, 2, 3, 4, 5
@@ -41,6 +42,8 @@ FIP_ATTR_SPLIT_K = 11
 FIP_ATTR_LAST_HIP_ERROR = 12
 FIP_ATTR_VB_STATUS = 13
 FIP_ATTR_COPIES = 14
+FIP_ATTR_DMA = 15
+FIP_ATTR_LAST_DMA = 16
 FIP_VB_GRAPH = 1
 FIP_PACK_AUTO, FIP_PACK_ALL, FIP_PACK_NONE, FIP_PACK_CONSUME_ONLY = 0, 1, 2, 3
 COPIES = 8
@@ -88,6 +91,10 @@ _SIGS = {
                           _ch, ctypes.c_double, _vp, _i64],
     "fip_sgemm": [_vp, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64, _ch,
                   ctypes.c_float, _vp, _i64],
+    "fip_zgemm": [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _i64, _ch, _vp, _i64, _ch, _vp, _vp,
+                  _i64],
+    "fip_cgemm": [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _i64, _ch, _vp, _i64, _ch, _vp, _vp,
+                  _i64],
     "fip_pack": [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _ch, _vp, _i64, _ch],
     "fip_xcc_map": [_vp, _vp, _i64],
     "fip_dsyrk": [_vp, _i32, _ch, _ch, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double,
@@ -197,6 +204,25 @@ def fip_dgemm_noalloc(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB,
 def fip_sgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
     return _lib.fip_sgemm(h, layout, m, n, k, alpha, _addr(A), lda, _trans(transA), _addr(B), ldb,
                           _trans(transB), beta, _addr(C), ldc)
+
+
+def _pair(z, ctype):
+    """A host (re, im) pair for a complex scalar argument (kept alive by the caller)."""
+    z = complex(z)
+    return (ctype * 2)(z.real, z.imag)
+
+
+def fip_zgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+    """Complex binary64 GEMM; alpha, beta: Python complex numbers (passed as host pairs)."""
+    al, be = _pair(alpha, ctypes.c_double), _pair(beta, ctypes.c_double)
+    return _lib.fip_zgemm(h, layout, m, n, k, ctypes.addressof(al), _addr(A), lda, _trans(transA),
+                          _addr(B), ldb, _trans(transB), ctypes.addressof(be), _addr(C), ldc)
+
+
+def fip_cgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+    al, be = _pair(alpha, ctypes.c_float), _pair(beta, ctypes.c_float)
+    return _lib.fip_cgemm(h, layout, m, n, k, ctypes.addressof(al), _addr(A), lda, _trans(transA),
+                          _addr(B), ldb, _trans(transB), ctypes.addressof(be), _addr(C), ldc)
 
 
 def fip_pack(h, dtype, layout, m, n, k, A, lda, transA, B, ldb, transB):
@@ -379,6 +405,17 @@ class Handle:
         rc = fn(self.h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc)
         self._check(fn.__name__, rc)
 
+    def zgemm(self, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+        """Complex GEMM by C's dtype (complex128 -> fip_zgemm, complex64 -> fip_cgemm)."""
+        import torch
+        dt = FIP_C128 if C.dtype == torch.complex128 else FIP_C64
+        self.bind_stream()
+        p = self.plan(dt, layout, m, n, k, transA, transB)
+        self.ensure_workspace(p.workspace_bytes)
+        fn = fip_zgemm if dt == FIP_C128 else fip_cgemm
+        self._check(fn.__name__, fn(self.h, layout, m, n, k, alpha, A, lda, transA, B, ldb,
+                                    transB, beta, C, ldc))
+
     def gemm_mx(self, dtype, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C,
                 ldc, a_scale=None, b_scale=None):
         """Mixed-precision form dtype (FIP_BF16 .. FIP_BF16X3_FAST); C binary32 or bfloat16."""
@@ -421,7 +458,11 @@ class Handle:
 
     def pack(self, layout, m, n, k, A, lda, transA, B, ldb, transB, dtype=None):
         import torch
-        dt = dtype if dtype is not None else (FIP_F64 if A.dtype == torch.float64 else FIP_F32)
+        if dtype is not None:
+            dt = dtype
+        else:
+            dt = {torch.float64: FIP_F64, torch.complex128: FIP_C128,
+                  torch.complex64: FIP_C64}.get(A.dtype, FIP_F32)
         old = self.get_attr(FIP_ATTR_PACK_POLICY)
         self.set_attr(FIP_ATTR_PACK_POLICY, FIP_PACK_CONSUME_ONLY)
         p = self.plan(dt, layout, m, n, k, transA, transB)

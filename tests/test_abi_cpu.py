@@ -67,10 +67,58 @@ def test_argument_positions(h, fn):
     assert call(tA="n", tB="c", ldb=5, k=6) in (0, F.FIP_ERR_LAUNCH, F.FIP_ERR_WORKSPACE)
 
 
+@pytest.mark.parametrize("fn", [F.fip_zgemm, F.fip_cgemm])
+def test_complex_argument_positions(h, fn):
+    """fip_zgemm / fip_cgemm: same positions as fip_dgemm (alpha, beta are host pairs)."""
+    def call(layout=0, m=4, n=5, k=6, alpha=1.5 - 1j, A=FAKE, lda=4, tA="N", B=FAKE, ldb=6,
+             tB="N", beta=0.5j, C=FAKE, ldc=4):
+        return fn(h, layout, m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc)
+    assert call(layout=2) == 2
+    assert call(m=-1) == 3
+    assert call(n=-1) == 4
+    assert call(k=-1) == 5
+    assert call(A=None) == 7
+    assert call(lda=3) == 8
+    assert call(tA="x") == 9
+    assert call(B=None) == 10
+    assert call(ldb=5) == 11
+    assert call(tB="Q") == 12
+    assert call(C=None) == 14
+    assert call(ldc=3) == 15
+    assert call(tA="C", lda=5) == 8                 # conjugate transpose: lda >= k = 6
+    assert call(layout=1, lda=6, ldb=5, ldc=4) == 15
+    # alpha = 0 and beta = 1: a full no-op, nothing is read
+    assert call(alpha=0, A=None, B=None, beta=1, C=None) == 0
+    assert call(m=0, A=None, B=None, C=None) == 0
+    # a null alpha or beta pointer
+    lib = ctypes.CDLL(F.LIB_PATH)
+    raw = getattr(lib, fn.__name__)
+    raw.argtypes = F._SIGS[fn.__name__]
+    beta = F._pair(0.5, ctypes.c_double if fn is F.fip_zgemm else ctypes.c_float)
+    assert raw(h, 0, 4, 5, 6, None, FAKE, 4, b"N", FAKE, 6, b"N", ctypes.addressof(beta), FAKE,
+               4) == 6
+    assert raw(h, 0, 4, 5, 6, ctypes.addressof(beta), FAKE, 4, b"N", FAKE, 6, b"N", None, FAKE,
+               4) == 13
+
+
+def test_complex_plan_is_the_expanded_real_problem(h):
+    """A complex plan covers the 2m x 2k by 2k x n real product of the 1m expansions."""
+    rc, p = F.fip_plan(h, F.FIP_C128, 0, 300, 200, 100, "N", "N")
+    assert rc == 0
+    assert (p.m, p.n, p.k) == (300, 200, 100)
+    assert p.tiles_m == -(-600 // p.MT) and p.tiles_n == -(-200 // p.NT)
+    assert p.ksteps == -(-200 // p.KT) and p.split_k == 1
+    rc, q = F.fip_plan(h, F.FIP_C64, 1, 300, 200, 100, "C", "T")
+    assert rc == 0
+    # row-major: the kernel A side is op(B)^T, so n is the expanded extent
+    assert q.tiles_n == -(-400 // q.NT) and q.tiles_m == -(-300 // q.MT)
+    assert q.KT == 32 and p.KT == 16
+
+
 def test_pack_argument_positions(h):
     def call(dtype=0, layout=0, m=4, n=5, k=6, A=FAKE, lda=4, tA="N", B=FAKE, ldb=6, tB="N"):
         return F.fip_pack(h, dtype, layout, m, n, k, A, lda, tA, B, ldb, tB)
-    assert call(dtype=7) == 2
+    assert call(dtype=8) == 2
     assert call(layout=9) == 3
     assert call(m=-1) == 4
     assert call(n=-2) == 5

@@ -246,7 +246,7 @@ TRMM_CASES = list(itertools.product([COL, ROW], "LR", "LU", "NT", "NU"))
 @pytest.mark.parametrize("layout,side,uplo,trans,diag", TRMM_CASES)
 def test_trmm_matches_oracle_all_policies_same_bits(F, dtype, layout, side, uplo, trans, diag):
     c = trmm_case(layout, side, uplo, trans, diag, 300, 200, dtype,
-                  seed=hash((layout, side, uplo, trans, diag)) & 0xFFFF)
+                  seed=TRMM_CASES.index((layout, side, uplo, trans, diag)) + 500)
     say("trmm", dtype.__name__, layout, side, uplo, trans, diag)
     ref, _ = run_trmm(F, c, F.FIP_PACK_NONE)
     check_trmm(c, ref)

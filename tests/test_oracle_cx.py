@@ -45,7 +45,7 @@ def op(c, which):
 @pytest.mark.parametrize("tA,tB", list(itertools.product(TRANS, TRANS)))
 def test_matches_numpy_complex_matmul(layout, tA, tB):
     """NumPy's complex128 matmul (another summation order) agrees within the bound."""
-    c = synth.make_cx_case(layout, 29, 23, 31, tA, tB, ld_pad=7, seed=hash((layout, tA, tB)) & 0xFFFF)
+    c = synth.make_cx_case(layout, 29, 23, 31, tA, tB, ld_pad=7, seed=100 * layout + 10 * TRANS.index(tA) + TRANS.index(tB))
     Cref, D = run(c)
     ref = c.alpha * (op(c, "A") @ op(c, "B")) + c.beta * cview(c.C, c)
     got, d = cview(Cref, c), cview(D, c)
