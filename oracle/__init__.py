@@ -70,6 +70,9 @@ def lib():
         L.oracle_trmm.argtypes = [ctypes.c_int, ch, ch, ch, ch, i64, i64, dbl, vp, i64, vp, i64,
                                   dbl, vp, i64, vp, vp]
         L.oracle_trmm.restype = None
+        L.oracle_trsm.argtypes = [ctypes.c_int, ch, ch, ch, ch, i64, i64, dbl, vp, i64, vp, i64,
+                                  vp, i64]
+        L.oracle_trsm.restype = None
         L.oracle_zgemm.argtypes = [ctypes.c_int, i64, i64, i64, dbl, dbl, vp, i64, ch, vp, i64,
                                    ch, dbl, dbl, vp, i64, vp, vp]
         L.oracle_zgemm.restype = None
@@ -299,6 +302,17 @@ def trmm(layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb, beta, C0
                       _ptr(A64), lda, _ptr(B64), ldb, float(beta), _ptr(C64), ldc, _ptr(Cref),
                       _ptr(D))
     return Cref, D
+
+
+def trsm(layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb):
+    """X (binary64, in B's storage with B's ld; entries outside m x n are B's) solving
+    op(T) X = alpha B (side 'L') or X op(T) = alpha B (side 'R'), T the uplo triangle of A
+    (unit diagonal for diag 'U')."""
+    A64, B64 = _f64(A), _f64(B)
+    X = B64.copy()
+    lib().oracle_trsm(layout, _t(side), _t(uplo), _t(transA), _t(diag), m, n, float(alpha),
+                      _ptr(A64), lda, _ptr(B64), ldb, _ptr(X), ldb)
+    return X
 
 
 # ---------------------------------------------------------------------------

@@ -20,6 +20,10 @@
  *          read when diag is 'U'; the other triangle of A is not read.  (BLAS
  *          overwrites B; here the product goes to a separate C, with beta.)
  *
+ *   TRSM   solve op(T) * X = alpha * B (side 'L', T m x m) or
+ *          X * op(T) = alpha * B (side 'R', T n x n) for X, B m x n; T as for
+ *          TRMM.  The solution is written to a separate X (BLAS overwrites B).
+ *
  * Each entry is a sequential sum in ascending p over the terms the definition
  * has (for TRMM only the referenced entries of T, so a structural zero is never
  * multiplied), then alpha * sum + beta * C0 with beta == 0 not reading C0 and
@@ -147,6 +151,56 @@ void oracle_trmm(int layout, char side, char uplo, char transA, char diag, int64
             }
             Cref[ci] = c;
             D[ci] = dd;
+        }
+    }
+}
+
+/*
+ * TRSM reference: substitution, one right-hand side at a time (a column of B
+ * for side 'L', a row for side 'R'), in the order the triangle dictates.
+ * With S the matrix acting on that right-hand side (S = op(T) for side 'L',
+ * S = op(T)^T for side 'R', since X op(T) = alpha B is op(T)^T x = alpha b for
+ * each row x of X), the unknowns are solved from the end of S's nonzero band
+ * inward:
+ *   x_r = (alpha * b_r - sum_c S[r, c] x_c) / S[r, r]
+ * where c runs over the already solved unknowns (c < r for lower S, c > r for
+ * upper S) in the order they were solved, and the division is skipped for a
+ * unit diagonal.  alpha == 0 gives X = 0 without reading A or B.  X uses B's
+ * storage convention (layout, ldx).
+ */
+void oracle_trsm(int layout, char side, char uplo, char transA, char diag, int64_t m, int64_t n,
+                 double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 double* X, int64_t ldx)
+{
+    const int left = l3_left(side);
+    const int64_t k = left ? m : n;        /* order of T */
+    const int64_t nrhs = left ? n : m;
+    /* S lower?  op(T) is lower when uplo is lower and not transposed, or upper
+       and transposed; side 'R' acts with op(T)^T, which flips it. */
+    const int op_lower = l3_lower(uplo) != l3_trans(transA);
+    const int s_lower = left ? op_lower : !op_lower;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t v = 0; v < nrhs; ++v) {
+        for (int64_t t = 0; t < k; ++t) {
+            const int64_t r = s_lower ? t : k - 1 - t;
+            const int64_t xi = left ? r : v, xj = left ? v : r;
+            if (alpha == 0.0) { X[l3_index(layout, ldx, xi, xj)] = 0.0; continue; }
+            double s = alpha * l3_stored(B, layout, ldb, xi, xj);
+            for (int64_t u = 0; u < t; ++u) {
+                const int64_t c = s_lower ? u : k - 1 - u;
+                /* S[r, c] = op(T)[r, c] (left) or op(T)[c, r] (right) */
+                double tv;
+                if (left) trmm_op(A, layout, lda, uplo, transA, diag, r, c, &tv);
+                else trmm_op(A, layout, lda, uplo, transA, diag, c, r, &tv);
+                const int64_t ci = left ? c : v, cj = left ? v : c;
+                s = s - tv * X[l3_index(layout, ldx, ci, cj)];
+            }
+            if (!l3_unit(diag)) {
+                double dv;
+                trmm_op(A, layout, lda, uplo, transA, diag, r, r, &dv);
+                s = s / dv;
+            }
+            X[l3_index(layout, ldx, xi, xj)] = s;
         }
     }
 }

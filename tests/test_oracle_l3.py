@@ -1,5 +1,5 @@
-"""Pins of the SYRK and TRMM oracle (fip_oracle_l3.c) against what mathematics fixes, each
-independent of the oracle's own loops:
+"""Pins of the SYRK, TRMM and TRSM oracle (fip_oracle_l3.c) against what mathematics fixes,
+each independent of the oracle's own loops:
 
 - small-integer operands: the result is exact, compared with Python integer arithmetic on
   triangles built by NumPy's tril / triu (SYRK: op(A) @ op(A).T; TRMM: op(T) @ B, B @ op(T));
@@ -9,7 +9,10 @@ independent of the oracle's own loops:
   the other triangle of A (nor a unit diagonal): NaN there leaves the result finite;
 - identity: a unit-diagonal T with NaN everywhere it is not read gives alpha B + beta C0;
 - storage: a row-major call equals the column-major call on the same memory with the
-  transposes swapped (index plumbing checked against a second route).
+  transposes swapped (index plumbing checked against a second route);
+- TRSM: integer systems (integer X times an integer triangle with a +-1 diagonal) solved
+  exactly, tiny diagonally dominant systems within a few roundings per step of the exact
+  rational solution (Fraction Gauss-Jordan), alpha = 0 reads nothing.
 """
 import itertools
 from fractions import Fraction
@@ -213,4 +216,108 @@ def test_trmm_row_major_is_column_major_with_sides_swapped():
         r, _ = oracle.trmm(ROW, side, uplo, trans, diag, m, n, 1.5, A, ka, B, n, 0.5, C, n)
         c, _ = oracle.trmm(COL, "R" if side == "L" else "L", "U" if uplo == "L" else "L", trans,
                            diag, n, m, 1.5, A, ka, B, n, 0.5, C, n)
+        assert np.array_equal(r.view(np.uint64), c.view(np.uint64)), (side, uplo, trans, diag)
+
+
+# ---------------------------------------------------------------- TRSM
+#
+# The oracle solves op(T) X = alpha B (side L) or X op(T) = alpha B (side R) by substitution.
+# Pins: exact solutions of integer systems built by multiplying an integer X with an integer
+# triangle of +-1 diagonal (every step of the substitution is an exact integer operation);
+# exact rational solutions (Fraction) on tiny systems; what the solve never reads; alpha = 0;
+# and the row-major / column-major identity.
+
+def _tri_system(g, ka, uplo, diag, ints=True):
+    if ints:
+        Av = g.integers(-3, 4, size=(ka, ka)).astype(np.float64)
+        np.fill_diagonal(Av, g.choice([-1.0, 1.0], size=ka))
+    else:
+        # strongly diagonally dominant: |off-diagonal row sum| < |diagonal| / 2
+        Av = g.uniform(-1, 1, (ka, ka)) / (2 * ka)
+        np.fill_diagonal(Av, g.choice([-1.0, 1.0], size=ka) * g.uniform(1, 2, size=ka))
+    return Av, tri(Av, uplo, diag)
+
+
+@pytest.mark.parametrize("layout,side,uplo,trans,diag", CASES)
+def test_trsm_integer_systems_exact(layout, side, uplo, trans, diag):
+    """alpha B = op(T) X (or X op(T)) for integer X: the oracle returns X exactly; the other
+    triangle, and a unit diagonal, are NaN (never read)."""
+    g = synth.rng(31)
+    m, n = 15, 11
+    ka = m if side == "L" else n
+    Av, T = _tri_system(g, ka, uplo, diag)
+    notref = ~(np.tril(np.ones((ka, ka), bool)) if uplo == "L" else np.triu(np.ones((ka, ka), bool)))
+    if diag == "U":
+        notref |= np.eye(ka, dtype=bool)
+    Apoison = Av.copy()
+    Apoison[notref] = np.nan
+    A, lda = stored(layout, ka, ka, Apoison, ld=ka + 3)
+    X = g.integers(-5, 6, size=(m, n)).astype(np.int64)
+    opT = (T.T if trans == "T" else T).astype(np.int64)
+    rhs = opT @ X if side == "L" else X @ opT          # = alpha B with alpha = 0.5
+    B, ldb = stored(layout, m, n, (2 * rhs).astype(np.float64), ld=(m if layout == COL else n) + 2)
+    got = oracle.trsm(layout, side, uplo, trans, diag, m, n, 0.5, A, lda, B, ldb)
+    assert np.array_equal(view(got, layout, m, n, ldb), X.astype(np.float64))
+    # the ld padding of X is B's, untouched
+    mask = np.ones(got.size, bool)
+    if layout == COL:
+        mask.reshape(n, ldb)[:, :m] = False
+    else:
+        mask.reshape(m, ldb)[:, :n] = False
+    assert np.array_equal(got[mask], B[mask], equal_nan=True)
+
+
+def test_trsm_fraction_bruteforce_tiny():
+    """Exact rational solution of every tiny diagonally dominant system: the oracle is within
+    a few roundings per step of it."""
+    g = synth.rng(32)
+    for m, n, side, uplo, trans, diag in itertools.product(range(1, 4), range(1, 4), "LR", "LU",
+                                                          "NT", "NU"):
+        ka = m if side == "L" else n
+        Av, T = _tri_system(g, ka, uplo, diag, ints=False)
+        opT = [[Fraction(v) for v in row] for row in (T.T if trans == "T" else T)]
+        Bv = g.uniform(-1, 1, (m, n))
+        A, lda = stored(COL, ka, ka, Av)
+        B, ldb = stored(COL, m, n, Bv)
+        got = view(oracle.trsm(COL, side, uplo, trans, diag, m, n, 1.25, A, lda, B, ldb),
+                   COL, m, n, ldb)
+        # exact solve, one right-hand side at a time, by Fraction elimination (Gauss-Jordan
+        # on the small dense system S x = alpha b, S = op(T) or op(T)^T)
+        S = opT if side == "L" else [list(r) for r in zip(*opT)]
+        for v in range(n if side == "L" else m):
+            b = [Fraction(1.25) * Fraction(Bv[r, v] if side == "L" else Bv[v, r]) for r in range(ka)]
+            M = [S[r][:] + [b[r]] for r in range(ka)]
+            for c in range(ka):
+                piv = M[c][c]
+                M[c] = [x / piv for x in M[c]]
+                for r in range(ka):
+                    if r != c and M[r][c] != 0:
+                        f = M[r][c]
+                        M[r] = [x - f * y for x, y in zip(M[r], M[c])]
+            exact = [M[r][ka] for r in range(ka)]
+            xmax = max(abs(x) for x in exact)
+            for r in range(ka):
+                gv = got[r, v] if side == "L" else got[v, r]
+                assert abs(Fraction(gv) - exact[r]) <= 16 * (ka + 2) * Fraction(U64) * xmax, \
+                    (m, n, side, uplo, trans, diag)
+
+
+def test_trsm_alpha_zero_reads_nothing():
+    A = np.full(25, np.nan)
+    B = np.full(5 * 4, np.nan)
+    X = oracle.trsm(COL, "L", "L", "N", "N", 5, 4, 0.0, A, 5, B, 5)
+    assert np.array_equal(X, np.zeros(20))
+
+
+def test_trsm_row_major_is_column_major_with_sides_swapped():
+    g = synth.rng(33)
+    m, n = 9, 7
+    for side, uplo, trans, diag in itertools.product("LR", "LU", "NT", "NU"):
+        ka = m if side == "L" else n
+        Av, _ = _tri_system(g, ka, uplo, diag, ints=False)
+        A = Av.reshape(-1)
+        B = g.uniform(-1, 1, m * n)
+        r = oracle.trsm(ROW, side, uplo, trans, diag, m, n, 1.5, A, ka, B, n)
+        c = oracle.trsm(COL, "R" if side == "L" else "L", "U" if uplo == "L" else "L", trans,
+                        diag, n, m, 1.5, A, ka, B, n)
         assert np.array_equal(r.view(np.uint64), c.view(np.uint64)), (side, uplo, trans, diag)
