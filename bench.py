@@ -514,10 +514,11 @@ def ldim_section(F, torch):
 
 
 def l3_section(F, torch, sizes=(4096, 8192)):
-    """SYRK (C := 1.5 A A^T + 0.5 C, lower, column-major 'N', k = n) and TRMM (C := 1.5 T B +
-    0.5 C, side L, lower, no transpose, non-unit) through the fused-pack tile kernel in FP64 and
-    FP32: fused (AUTO) against unpacked (NONE) and fused with every panel packed (ALL).  flops:
-    n^2 k for SYRK (one triangle), m^2 n for TRMM (half the square)."""
+    """SYRK (C := 1.5 A A^T + 0.5 C, lower, column-major 'N', k = n), TRMM (C := 1.5 T B +
+    0.5 C, side L, lower, no transpose, non-unit) and TRSM (T X = 1.5 C in place, side L,
+    lower, no transpose) through the fused-pack tile kernel in FP64 and FP32: fused (AUTO)
+    against unpacked (NONE) and fused with every panel packed (ALL).  flops: n^2 k for SYRK
+    (one triangle), m^2 n for TRMM and TRSM (half the square)."""
     import statistics
     from paper_2302_08417_amd import synth
     out = []
@@ -528,7 +529,12 @@ def l3_section(F, torch, sizes=(4096, 8192)):
             A = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
             B = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
             C = torch.rand(n * n, device="cuda", generator=g, dtype=tdt) * 2 - 1
-            for op in ("syrk", "trmm"):
+            # TRSM's triangle: lower, off-diagonal U[-1, 1] / 2n, diagonal 1.5 (well
+            # conditioned; with alpha = 1.5 the solution keeps B's magnitude call after call)
+            T = (A.view(n, n) / (2 * n)).clone()
+            T.diagonal().fill_(1.5)
+            T = T.reshape(-1)
+            for op in ("syrk", "trmm", "trsm"):
                 hs = {key: F.Handle(policy=pol) for key, pol in
                       (("fused", F.FIP_PACK_AUTO), ("no_pack", F.FIP_PACK_NONE),
                        ("fused_all", F.FIP_PACK_ALL))}
@@ -536,6 +542,8 @@ def l3_section(F, torch, sizes=(4096, 8192)):
                 def mk(h):
                     if op == "syrk":
                         return lambda: h.syrk(0, "L", "N", n, n, 1.5, A, n, 0.5, C, n)
+                    if op == "trsm":
+                        return lambda: h.trsm(0, "L", "L", "N", "N", n, n, 1.5, T, n, C, n)
                     return lambda: h.trmm(0, "L", "L", "N", "N", n, n, 1.5, A, n, B, n, 0.5, C, n)
                 calls = {key: mk(h) for key, h in hs.items()}
                 for c in calls.values():
@@ -815,9 +823,9 @@ def compact_summary(result, full):
             r["form"]: {"n": big, "pct_peak": r["fused_pct_mfma_peak"],
                         "vs_ptc": round(r["pack_then_compute_us"] / r["fused_us"], 3)}
             for r in full["mixed_precision"] if r["m"] == big}
-    if "syrk_trmm" in full:
-        s["syrk_trmm_pct_peak"] = {f"{r['op']}_{r['dtype']}_{r['n']}": r["fused_pct_peak"]
-                                   for r in full["syrk_trmm"] if r["n"] == 8192}
+    if "level3" in full:
+        s["l3_pct_peak"] = {f"{r['op']}_{r['dtype']}_{r['n']}": r["fused_pct_peak"]
+                                   for r in full["level3"] if r["n"] == 8192}
     if "dma" in full:
         s["dma_speedup"] = {f"{r['dtype']}_{r['n']}": [r["dma_speedup_no_pack"],
                                                         r["dma_speedup_pack_then_compute"]]
@@ -961,7 +969,7 @@ def main():
         full["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
         full["mixed_precision_deep_k"] = mx_deep_k_section(F, torch)
     if not args.no_l3:
-        full["syrk_trmm"] = l3_section(F, torch)
+        full["level3"] = l3_section(F, torch)
     if not args.no_cx:
         full["complex_1m"] = cx_section(F, torch)
     if not args.no_dma:

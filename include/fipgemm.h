@@ -384,7 +384,7 @@ int fip_pack(fip_handle_t handle, int dtype, int layout, int64_t m, int64_t n, i
  * on the one packable operand); NONE never packs; CONSUME_ONLY runs unpacked
  * (there is no standalone pack for these operations).  Split k is not used.
  */
-enum { FIP_OP_SYRK = 1, FIP_OP_TRMM = 2 };
+enum { FIP_OP_SYRK = 1, FIP_OP_TRMM = 2, FIP_OP_TRSM = 3 };
 int fip_dsyrk(fip_handle_t handle, int layout, char uplo, char trans, int64_t n, int64_t k,
               double alpha, const double* A, int64_t lda, double beta, double* C, int64_t ldc);
 int fip_ssyrk(fip_handle_t handle, int layout, char uplo, char trans, int64_t n, int64_t k,
@@ -396,10 +396,36 @@ int fip_strmm(fip_handle_t handle, int layout, char side, char uplo, char transA
               int64_t m, int64_t n, float alpha, const float* A, int64_t lda, const float* B,
               int64_t ldb, float beta, float* C, int64_t ldc);
 /*
- * Plan of a SYRK (op FIP_OP_SYRK: n, k; side and diag ignored) or TRMM
- * (FIP_OP_TRMM: m, n; k ignored) call: tile class, pack decision and
- * workspace bytes (FIP_F64 or FIP_F32).  The plan's "A" is op(A) (SYRK; its
- * "B" is the same pack) or the triangular matrix (TRMM).  No HIP call.
+ * TRSM: solve op(T) X = alpha B (side 'L', T m x m) or X op(T) = alpha B
+ * (side 'R', T n x n) for X, B m x n; T is the uplo triangle of A, with a
+ * unit diagonal (not read) for diag 'U'; the other triangle of A is never
+ * read.  X overwrites B (BLAS semantics).  Method: recursive blocking on the
+ * column-major view: op(T) is split in two at a multiple of 64 rows; the half
+ * solved first takes alpha, the rest of B becomes alpha B minus the coupling
+ * block of op(T) times the solved part, a GEMM through the fused-pack tile
+ * kernel (with the handle's pack policy and workspace), and the remaining
+ * half is solved with alpha = 1; diagonal blocks of at most 64 rows are solved
+ * by substitution, one right-hand side per thread.  The workspace must hold
+ * what the largest GEMM update needs (fip_plan_l3 with FIP_OP_TRSM reports it);
+ * otherwise FIP_ERR_WORKSPACE is returned before anything is launched.  After
+ * the call fip_last_plan reports its last GEMM update.  alpha = 0: B := 0
+ * without reading A or B.  Positions: layout 2, side 3, uplo 4, transA 5,
+ * diag 6, m 7, n 8, alpha 9, A 10, lda 11 (>= max(1, side 'L' ? m : n)),
+ * B 12, ldb 13 (>= max(1, column-major ? m : n)).
+ */
+int fip_dtrsm(fip_handle_t handle, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, double alpha, const double* A, int64_t lda, double* B,
+              int64_t ldb);
+int fip_strsm(fip_handle_t handle, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, float alpha, const float* A, int64_t lda, float* B,
+              int64_t ldb);
+/*
+ * Plan of a SYRK (op FIP_OP_SYRK: n, k; side and diag ignored), TRMM
+ * (FIP_OP_TRMM: m, n; k ignored) or TRSM (FIP_OP_TRSM: m, n; k ignored) call:
+ * tile class, pack decision and workspace bytes (FIP_F64 or FIP_F32).  The
+ * plan's "A" is op(A) (SYRK; its "B" is the same pack) or the triangular
+ * matrix (TRMM); for TRSM the plan is that of the top-level GEMM update, with
+ * workspace_bytes the largest any of its updates needs.  No HIP call.
  * Positions: op 2, dtype 3, layout 4, side 5, uplo 6, trans 7, diag 8, m 9,
  * n 10, k 11, plan 12.
  */

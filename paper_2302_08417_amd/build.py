@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfipgemm.so")
 SOURCES = ["fipgemm_kernels.hip", "fipgemm_mx.hip", "fipgemm_batched.hip", "fipgemm_scratch.hip",
-           "fipgemm_api.cpp"]
+           "fipgemm_trsm.hip", "fipgemm_api.cpp"]
 ARCH = os.environ.get("FIPGEMM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

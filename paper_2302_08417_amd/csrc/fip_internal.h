@@ -100,6 +100,23 @@ hipError_t launch_pack(const LaunchDesc& d);
 hipError_t launch_scale(int elem, int64_t M, int64_t N, void* C, int64_t ldc, double beta,
                         hipStream_t stream);
 
+// ---- Triangular solve: diagonal blocks (fipgemm_trsm.hip) --------------------
+// Rows of the largest diagonal block the blocked TRSM solves directly.
+constexpr int kTrsmBlock = 64;
+// Solve S x = alpha b in place for nrhs right-hand sides b (element e of
+// right-hand side v at B[e*s_e + v*s_v]), S the nb x nb (nb <= kTrsmBlock)
+// triangle with S(r, c) = A[r + c*lda] (s_trans = 0) or A[c + r*lda], lower
+// or upper, unit diagonal (not read) or not.
+struct TrsmBlockDesc {
+    int elem;
+    const void* A; int64_t lda;
+    int s_trans, s_lower, unit, nb;
+    void* B; int64_t s_e, s_v, nrhs;
+    double alpha;
+    hipStream_t stream;
+};
+hipError_t launch_trsm_block(const TrsmBlockDesc& d);
+
 // ---- Mixed-precision forms (fipgemm_mx.hip) --------------------------------
 // Operands stored as bfloat16 or FP8 E4M3, or binary32 split into bfloat16
 // terms while packing; binary32 accumulation; C binary32 or bfloat16.

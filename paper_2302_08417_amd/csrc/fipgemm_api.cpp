@@ -1067,6 +1067,183 @@ int trmm_impl(fip_handle_t h, int dtype, int layout, char side, char uplo, char 
     }
 }
 
+// ---- TRSM: recursive blocking onto the fused-pack GEMM --------------------------
+//
+// op(T) X = alpha B (side L) or X op(T) = alpha B (side R), in place in B.  On
+// the column-major view, op(T) is split into [T11 0; T21 T22] (lower) or
+// [T11 T12; 0 T22] (upper) at a multiple of the diagonal-block size; the block
+// solved first takes alpha, the other part of B becomes alpha B - (its
+// coupling block) times the solved X through a GEMM of the fused-pack tile
+// kernel (C := -1 * op(X) op(Y) + alpha * C), and the remaining solve runs with
+// alpha = 1.  Blocks of at most kTrsmBlock rows go to the diagonal-block
+// kernel.  A dry run walks the same recursion to size the workspace the GEMM
+// updates need, so nothing is launched unless all of them fit.
+struct TrsmCtx {
+    fip_handle_t h;
+    int dtype;
+    bool dry;
+    int64_t ws_need;
+    fip_plan_t first;   // plan of the top-level update (dry run)
+    bool have_first;
+};
+
+template <typename T>
+int trsm_rec(TrsmCtx& c, bool left, bool op_lower, bool trans, bool unit, int64_t m, int64_t n,
+             T alpha, const T* A, int64_t lda, T* B, int64_t ldb)
+{
+    const int64_t k = left ? m : n;
+    if (k <= fip::kTrsmBlock) {
+        if (c.dry) return 0;
+        fip::TrsmBlockDesc d{};
+        d.elem = sizeof(T);
+        d.A = A; d.lda = lda;
+        // the matrix acting on one right-hand side: op(T) (a column of B), or
+        // op(T)^T (a row of B)
+        d.s_trans = left ? trans : !trans;
+        d.s_lower = left ? op_lower : !op_lower;
+        d.unit = unit;
+        d.nb = (int)k;
+        d.B = B;
+        d.s_e = left ? 1 : ldb;
+        d.s_v = left ? ldb : 1;
+        d.nrhs = left ? n : m;
+        d.alpha = (double)alpha;
+        d.stream = c.h->stream;
+        if (const hipError_t e = fip::launch_trsm_block(d); e != hipSuccess) return launch_failed(c.h, e);
+        return 0;
+    }
+    const int64_t k1 = cdiv(k / 2, fip::kTrsmBlock) * fip::kTrsmBlock, k2 = k - k1;
+    const T* A11 = A;
+    const T* A22 = A + k1 + k1 * lda;
+    // op(T)[k1:, :k1] and op(T)[:k1, k1:] as stored blocks with their op
+    const char top = trans ? 'T' : 'N';
+    const T* Tlo = trans ? A + k1 * lda : A + k1;
+    const T* Tup = trans ? A + k1 : A + k1 * lda;
+    auto update = [&](int64_t gm, int64_t gn, int64_t gk, const T* X, int64_t ldx, char tx,
+                      const T* Y, int64_t ldy, char ty, T* C, int64_t ldc) -> int {
+        if (c.dry) {
+            Plan pl;
+            make_plan(c.h, c.dtype, FIP_COL_MAJOR, gm, gn, gk, tx, ty, false, &pl);
+            c.ws_need = std::max<int64_t>(c.ws_need, pl.pub.workspace_bytes);
+            if (!c.have_first) { c.first = pl.pub; c.have_first = true; }
+            return 0;
+        }
+        return gemm_impl<T>(c.h, c.dtype, FIP_COL_MAJOR, gm, gn, gk, T(-1), X, ldx, tx, Y, ldy,
+                            ty, alpha, C, ldc);
+    };
+    int rc;
+    if (left) {
+        T* B1 = B;
+        T* B2 = B + k1;
+        if (op_lower) {
+            if ((rc = trsm_rec<T>(c, left, op_lower, trans, unit, k1, n, alpha, A11, lda, B1, ldb))) return rc;
+            if ((rc = update(k2, n, k1, Tlo, lda, top, B1, ldb, 'N', B2, ldb))) return rc;
+            return trsm_rec<T>(c, left, op_lower, trans, unit, k2, n, T(1), A22, lda, B2, ldb);
+        }
+        if ((rc = trsm_rec<T>(c, left, op_lower, trans, unit, k2, n, alpha, A22, lda, B2, ldb))) return rc;
+        if ((rc = update(k1, n, k2, Tup, lda, top, B2, ldb, 'N', B1, ldb))) return rc;
+        return trsm_rec<T>(c, left, op_lower, trans, unit, k1, n, T(1), A11, lda, B1, ldb);
+    }
+    T* B1 = B;
+    T* B2 = B + k1 * ldb;
+    if (op_lower) {
+        if ((rc = trsm_rec<T>(c, left, op_lower, trans, unit, m, k2, alpha, A22, lda, B2, ldb))) return rc;
+        if ((rc = update(m, k1, k2, B2, ldb, 'N', Tlo, lda, top, B1, ldb))) return rc;
+        return trsm_rec<T>(c, left, op_lower, trans, unit, m, k1, T(1), A11, lda, B1, ldb);
+    }
+    if ((rc = trsm_rec<T>(c, left, op_lower, trans, unit, m, k1, alpha, A11, lda, B1, ldb))) return rc;
+    if ((rc = update(m, k2, k1, B1, ldb, 'N', Tup, lda, top, B2, ldb))) return rc;
+    return trsm_rec<T>(c, left, op_lower, trans, unit, m, k2, T(1), A22, lda, B2, ldb);
+}
+
+// Column-major view of a TRSM call: row-major storage is the transposed view
+// of the same memory, so the side and the stored triangle swap and m, n
+// exchange (op's transpose stays).
+struct TrsmShape {
+    bool left, op_lower, trans, unit;
+    int64_t m, n;
+};
+TrsmShape trsm_shape(int layout, char side, char uplo, char transA, char diag, int64_t m, int64_t n)
+{
+    const bool row = layout == FIP_ROW_MAJOR;
+    TrsmShape t;
+    t.left = is_left(side) != row;
+    const bool lower = is_lower(uplo) != row;
+    t.trans = is_trans(transA);
+    t.op_lower = lower != t.trans;
+    t.unit = is_unit(diag);
+    t.m = row ? n : m;
+    t.n = row ? m : n;
+    return t;
+}
+
+template <typename T>
+int trsm_impl(fip_handle_t h, int dtype, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, T alpha, const T* A, int64_t lda, T* B, int64_t ldb)
+{
+    try {
+        if (!valid_handle(h)) return FIP_ERR_HANDLE;
+        // positions: layout 2, side 3, uplo 4, transA 5, diag 6, m 7, n 8, alpha 9, A 10,
+        // lda 11, B 12, ldb 13
+        if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 2;
+        if (!valid_side(side)) return 3;
+        if (!valid_uplo(uplo)) return 4;
+        if (!valid_trans(transA)) return 5;
+        if (!valid_diag(diag)) return 6;
+        if (m < 0) return 7;
+        if (n < 0) return 8;
+        const int64_t ka = is_left(side) ? m : n;
+        const bool reads = m > 0 && n > 0 && alpha != T(0);
+        if (reads && A == nullptr) return 10;
+        if (lda < max1(ka)) return 11;
+        if (m > 0 && n > 0 && B == nullptr) return 12;
+        const bool col = layout == FIP_COL_MAJOR;
+        if (ldb < max1(col ? m : n)) return 13;
+        if (m == 0 || n == 0) return 0;
+        const TrsmShape t = trsm_shape(layout, side, uplo, transA, diag, m, n);
+        if (alpha == T(0)) {   // X = 0; neither A nor B is read
+            if (const hipError_t e = fip::launch_scale(sizeof(T), t.m, t.n, B, ldb, 0.0, h->stream);
+                e != hipSuccess)
+                return launch_failed(h, e);
+            return 0;
+        }
+        TrsmCtx c{h, dtype, true, 0, {}, false};
+        trsm_rec<T>(c, t.left, t.op_lower, t.trans, t.unit, t.m, t.n, alpha, A, lda, B, ldb);
+        if (c.ws_need > 0 && (h->ws == nullptr || (int64_t)h->ws_bytes < c.ws_need))
+            return FIP_ERR_WORKSPACE;
+        c.dry = false;
+        return trsm_rec<T>(c, t.left, t.op_lower, t.trans, t.unit, t.m, t.n, alpha, A, lda, B,
+                           ldb);
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+// Workspace plan of a TRSM: the dry run of the recursion (the largest need of
+// its GEMM updates, and the top-level update's plan for the other fields).
+int trsm_plan(fip_handle_t h, int dtype, int layout, char side, char uplo, char trans, char diag,
+              int64_t m, int64_t n, fip_plan_t* out)
+{
+    const TrsmShape t = trsm_shape(layout, side, uplo, trans, diag, m, n);
+    TrsmCtx c{h, dtype, true, 0, {}, false};
+    if (dtype == FIP_F64)
+        trsm_rec<double>(c, t.left, t.op_lower, t.trans, t.unit, t.m, t.n, 1.0, nullptr, 1,
+                         nullptr, 1);
+    else
+        trsm_rec<float>(c, t.left, t.op_lower, t.trans, t.unit, t.m, t.n, 1.0f, nullptr, 1,
+                        nullptr, 1);
+    fip_plan_t p{};
+    if (c.have_first) p = c.first;
+    p.dtype = dtype;
+    p.layout = layout;
+    p.m = m;
+    p.n = n;
+    p.k = 0;
+    p.workspace_bytes = c.ws_need;
+    *out = p;
+    return 0;
+}
+
 // ---- batched binary32 GEMM ----------------------------------------------------
 
 constexpr int kVbDefaultSplit = 16;   // untuned: max(m, n) <= 16 -> 16 x 16 tiles
@@ -1499,21 +1676,38 @@ int fip_strmm(fip_handle_t handle, int layout, char side, char uplo, char transA
                             lda, B, ldb, beta, C, ldc);
 }
 
+int fip_dtrsm(fip_handle_t handle, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, double alpha, const double* A, int64_t lda, double* B,
+              int64_t ldb)
+{
+    return trsm_impl<double>(handle, FIP_F64, layout, side, uplo, transA, diag, m, n, alpha, A,
+                             lda, B, ldb);
+}
+
+int fip_strsm(fip_handle_t handle, int layout, char side, char uplo, char transA, char diag,
+              int64_t m, int64_t n, float alpha, const float* A, int64_t lda, float* B,
+              int64_t ldb)
+{
+    return trsm_impl<float>(handle, FIP_F32, layout, side, uplo, transA, diag, m, n, alpha, A,
+                            lda, B, ldb);
+}
+
 int fip_plan_l3(fip_handle_t handle, int op, int dtype, int layout, char side, char uplo,
                 char trans, char diag, int64_t m, int64_t n, int64_t k, fip_plan_t* plan)
 {
     if (!valid_handle(handle)) return FIP_ERR_HANDLE;
-    if (op != FIP_OP_SYRK && op != FIP_OP_TRMM) return 2;
+    if (op != FIP_OP_SYRK && op != FIP_OP_TRMM && op != FIP_OP_TRSM) return 2;
     if (dtype != FIP_F64 && dtype != FIP_F32) return 3;
     if (layout != FIP_COL_MAJOR && layout != FIP_ROW_MAJOR) return 4;
-    if (op == FIP_OP_TRMM && !valid_side(side)) return 5;
+    if (op != FIP_OP_SYRK && !valid_side(side)) return 5;
     if (!valid_uplo(uplo)) return 6;
     if (!valid_trans(trans)) return 7;
-    if (op == FIP_OP_TRMM && !valid_diag(diag)) return 8;
+    if (op != FIP_OP_SYRK && !valid_diag(diag)) return 8;
     if (m < 0) return 9;
     if (n < 0) return 10;
     if (k < 0) return 11;
     if (plan == nullptr) return 12;
+    if (op == FIP_OP_TRSM) return trsm_plan(handle, dtype, layout, side, uplo, trans, diag, m, n, plan);
     Plan pl;
     const L3Shape ls = op == FIP_OP_SYRK ? syrk_shape(layout, uplo, trans, n, k)
                                          : trmm_shape(layout, side, uplo, trans, diag, m, n);

@@ -105,6 +105,10 @@ _SIGS = {
                   _i64, ctypes.c_double, _vp, _i64],
     "fip_strmm": [_vp, _i32, _ch, _ch, _ch, _ch, _i64, _i64, ctypes.c_float, _vp, _i64, _vp,
                   _i64, ctypes.c_float, _vp, _i64],
+    "fip_dtrsm": [_vp, _i32, _ch, _ch, _ch, _ch, _i64, _i64, ctypes.c_double, _vp, _i64, _vp,
+                  _i64],
+    "fip_strsm": [_vp, _i32, _ch, _ch, _ch, _ch, _i64, _i64, ctypes.c_float, _vp, _i64, _vp,
+                  _i64],
     "fip_plan_l3": [_vp, _i32, _i32, _i32, _ch, _ch, _ch, _ch, _i64, _i64, _i64,
                     ctypes.POINTER(fip_plan_t)],
     "fip_tile_map": [_i64, _i64, _i32, _vp, _vp],
@@ -230,7 +234,7 @@ def fip_pack(h, dtype, layout, m, n, k, A, lda, transA, B, ldb, transB):
                          _trans(transB))
 
 
-FIP_OP_SYRK, FIP_OP_TRMM = 1, 2
+FIP_OP_SYRK, FIP_OP_TRMM, FIP_OP_TRSM = 1, 2, 3
 
 
 def fip_dsyrk(h, layout, uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
@@ -251,6 +255,16 @@ def fip_dtrmm(h, layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb, 
 def fip_strmm(h, layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb, beta, C, ldc):
     return _lib.fip_strmm(h, layout, _trans(side), _trans(uplo), _trans(transA), _trans(diag), m,
                           n, alpha, _addr(A), lda, _addr(B), ldb, beta, _addr(C), ldc)
+
+
+def fip_dtrsm(h, layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb):
+    return _lib.fip_dtrsm(h, layout, _trans(side), _trans(uplo), _trans(transA), _trans(diag), m,
+                          n, alpha, _addr(A), lda, _addr(B), ldb)
+
+
+def fip_strsm(h, layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb):
+    return _lib.fip_strsm(h, layout, _trans(side), _trans(uplo), _trans(transA), _trans(diag), m,
+                          n, alpha, _addr(A), lda, _addr(B), ldb)
 
 
 def fip_plan_l3(h, op, dtype, layout, side, uplo, trans, diag, m, n, k):
@@ -450,6 +464,18 @@ class Handle:
         fn = fip_dtrmm if dt == FIP_F64 else fip_strmm
         self._check(fn.__name__, fn(self.h, layout, side, uplo, transA, diag, m, n, alpha, A, lda,
                                     B, ldb, beta, C, ldc))
+
+    def trsm(self, layout, side, uplo, transA, diag, m, n, alpha, A, lda, B, ldb):
+        """fip_dtrsm / fip_strsm by B's dtype (X overwrites B)."""
+        import torch
+        dt = FIP_F64 if B.dtype == torch.float64 else FIP_F32
+        self.bind_stream()
+        rc, p = fip_plan_l3(self.h, FIP_OP_TRSM, dt, layout, side, uplo, transA, diag, m, n, 0)
+        self._check("fip_plan_l3", rc)
+        self.ensure_workspace(p.workspace_bytes)
+        fn = fip_dtrsm if dt == FIP_F64 else fip_strsm
+        self._check(fn.__name__, fn(self.h, layout, side, uplo, transA, diag, m, n, alpha, A, lda,
+                                    B, ldb))
 
     def quantize_fp8(self, layout, rows, cols, X, ldx, axis, Q, ldq, scales):
         self.bind_stream()

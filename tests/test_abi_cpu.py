@@ -547,7 +547,38 @@ def test_l3_argument_positions_and_plans(h):
             if pol == F.FIP_PACK_ALL:
                 assert p.pack_a and p.a_copy_bytes == p.ksteps * p.KT * p.MT * 4 * \
                     -(-4000 // p.MT)
-        assert F.fip_plan_l3(h, 3, 0, 0, "L", "L", "N", "N", 4, 4, 4)[0] == 2
+        assert F.fip_plan_l3(h, 4, 0, 0, "L", "L", "N", "N", 4, 4, 4)[0] == 2
         assert F.fip_plan_l3(h, F.FIP_OP_TRMM, 0, 0, "Q", "L", "N", "N", 4, 4, 4)[0] == 5
+    finally:
+        F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO)
+
+
+def test_trsm_argument_positions_and_plan(h):
+    """TRSM: argument errors by position before any HIP call; the plan's workspace is the
+    largest any GEMM update of the recursion needs (none below one diagonal block)."""
+    A = 0x1000
+    for fn in (F.fip_dtrsm, F.fip_strsm):
+        assert fn(h, 2, "L", "L", "N", "N", 4, 4, 1.0, A, 4, A, 4) == 2
+        assert fn(h, 0, "X", "L", "N", "N", 4, 4, 1.0, A, 4, A, 4) == 3
+        assert fn(h, 0, "L", "X", "N", "N", 4, 4, 1.0, A, 4, A, 4) == 4
+        assert fn(h, 0, "L", "L", "X", "N", 4, 4, 1.0, A, 4, A, 4) == 5
+        assert fn(h, 0, "L", "L", "N", "X", 4, 4, 1.0, A, 4, A, 4) == 6
+        assert fn(h, 0, "L", "L", "N", "N", -1, 4, 1.0, A, 4, A, 4) == 7
+        assert fn(h, 0, "L", "L", "N", "N", 4, -1, 1.0, A, 4, A, 4) == 8
+        assert fn(h, 0, "L", "L", "N", "N", 4, 4, 1.0, None, 4, A, 4) == 10
+        assert fn(h, 0, "R", "L", "N", "N", 4, 6, 1.0, A, 5, A, 4) == 11    # side R: lda >= n
+        assert fn(h, 0, "L", "L", "N", "N", 4, 4, 1.0, A, 4, None, 4) == 12
+        assert fn(h, 1, "L", "L", "N", "N", 4, 6, 1.0, A, 4, A, 5) == 13    # row-major: ldb >= n
+        assert fn(h, 0, "L", "L", "N", "N", 0, 4, 1.0, None, 1, None, 1) == 0
+    rc, p = F.fip_plan_l3(h, F.FIP_OP_TRSM, F.FIP_F64, 0, "L", "L", "N", "N", 64, 100, 0)
+    assert rc == 0 and p.workspace_bytes == 0
+    try:
+        F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_ALL)
+        rc, p = F.fip_plan_l3(h, F.FIP_OP_TRSM, F.FIP_F64, 0, "L", "L", "N", "N", 1000, 700, 0)
+        assert rc == 0 and p.workspace_bytes > 0
+        # the top-level update: rows 512 .. 999 of op(T) times the first 512 solved rows
+        assert (p.m, p.n) == (1000, 700) and p.pack_a and p.pack_b
+        rc2, q = F.fip_plan(h, F.FIP_F64, 0, 488, 700, 512, "N", "N")
+        assert rc2 == 0 and p.workspace_bytes >= q.workspace_bytes
     finally:
         F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO)
