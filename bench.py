@@ -224,7 +224,7 @@ def _median_times(torch, calls, rounds, reps):
     return {k: statistics.median(v) for k, v in times.items()}
 
 
-def mx_section(F, torch, sizes):
+def mx_section(F, torch, sizes, forms=None):
     """Mixed-precision forms, square column-major NN, alpha = 1, beta = 0, C binary32:
     fused (AUTO) vs pack-then-compute vs unpacked, and the error of the fused result on a
     sampled 32 x 32 block of C against the binary64 oracle product of the binary32 values
@@ -235,6 +235,8 @@ def mx_section(F, torch, sizes):
     out = []
     for n in sizes:
         for name, dt, peak, prods in MX_FORMS:
+            if forms and name not in forms:
+                continue
             A, B, sa, sb, A32, B32 = synth.mx_device_operands(dt, n, seed=synth.BASE_SEED + n)
             C = torch.zeros(n, n, device="cuda")
             hs = {pol: F.Handle(policy=pol) for pol in (F.FIP_PACK_AUTO, F.FIP_PACK_CONSUME_ONLY,
@@ -859,6 +861,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mx", action="store_true", help="skip the mixed-precision section")
     ap.add_argument("--mx-sizes", default="1024,4096,16384")
+    ap.add_argument("--mx-forms", default=None,
+                    help="comma-separated subset of bf16,e4m3,bf16x3,bf16x3_fast (default: all)")
+    ap.add_argument("--no-mx-deep", action="store_true", help="skip the mixed deep-k shapes")
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-l3", action="store_true", help="skip the SYRK / TRMM section")
     ap.add_argument("--no-cx", action="store_true", help="skip the complex (1m) section")
@@ -966,8 +971,11 @@ def main():
         full["ldim2000"] = ldim_section(F, torch)
         full["cache_and_graph"] = cache_section(F, torch)
     if not args.no_mx:
-        full["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")])
-        full["mixed_precision_deep_k"] = mx_deep_k_section(F, torch)
+        forms = args.mx_forms.split(",") if args.mx_forms else None
+        full["mixed_precision"] = mx_section(F, torch, [int(x) for x in args.mx_sizes.split(",")],
+                                             forms)
+        if not args.no_mx_deep:
+            full["mixed_precision_deep_k"] = mx_deep_k_section(F, torch)
     if not args.no_l3:
         full["level3"] = l3_section(F, torch)
     if not args.no_cx:

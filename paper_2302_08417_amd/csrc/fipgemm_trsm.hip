@@ -11,7 +11,7 @@
 // sits in LDS; each thread substitutes through it with its unknowns in
 // registers (fully unrolled, so every index is a constant), in place in B:
 //   x_r = (alpha b_r - sum_c S[r, c] x_c) / S[r, r]
-// over the already solved c, ascending for lower S, descending for upper S;
+// over the already solved c (ascending for lower S, descending for upper S);
 // no division for a unit diagonal.  Only the referenced triangle of the stored
 // matrix is read (and not the diagonal when it is unit).  A block of nb < NB
 // rows is padded with identity rows and zero right-hand sides, which solve to
@@ -45,16 +45,20 @@ __global__ void __launch_bounds__(64) trsm_block_kernel(const T* __restrict__ A,
     const int64_t v = (int64_t)blockIdx.x * 64 + tid;
     if (v >= nrhs) return;
     T* b = B + v * s_v;
+    // The sum of row r is split over four accumulators (terms c = 0, 1, 2, 3
+    // mod 4 of the solved unknowns, in solve order), so four independent
+    // chains of LDS reads and FMAs are in flight instead of one.
     T x[NB];
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
         const int r = LOWER ? t : NB - 1 - t;
-        T s = r < nb ? alpha * b[r * s_e] : T(0);
+        T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int u = 0; u < t; ++u) {
             const int c = LOWER ? u : NB - 1 - u;
-            s = s - S[r][c] * x[c];
+            acc[u & 3] = acc[u & 3] + S[r][c] * x[c];
         }
+        const T s = (r < nb ? alpha * b[r * s_e] : T(0)) - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
         x[r] = unit ? s : s / S[r][r];
     }
 #pragma unroll
