@@ -103,8 +103,19 @@ template <int FORM, int MT_> struct Geo {
     // stride of 32 (mod 128) or 16 (mod 128) bytes puts them on distinct banks.
     static constexpr int PITCH_MN = MT * EB + (FORM == kMxFP8 ? 16 : 32);
     static constexpr int LDS_PLANE_MN = KT * PITCH_MN;
+    // LDS row of row p (a k index) of an MN-major chunk.  E4M3 swaps the two
+    // 2-bit fields of p = 32g + 8h + i (row 32h + 8g + i): one transposing
+    // fragment read then spans 32 consecutive rows (8 per lane group g)
+    // instead of four groups 32 rows apart, and a 144-byte pitch spreads any
+    // 16 consecutive rows over all 64 banks.  The other forms keep the order.
+    __device__ __forceinline__ static int lds_row_mn(int p)
+    {
+        if constexpr (FORM == kMxFP8) return (p & ~127) | ((p & 24) << 2) | ((p & 96) >> 2) | (p & 7);
+        else return p;
+    }
     template <bool KC> static constexpr int lds_operand() { return PL * (KC ? LDS_PLANE : LDS_PLANE_MN); }
     static_assert(KGROUPS * (MT / NR) == NTHR, "micro-blocks must cover the chunk");
+    static_assert(FORM != kMxFP8 || KT == 128, "E4M3 row permutation covers one 128-row chunk");
     static_assert(WPR == 2 || WPR == 4, "8- or 16-byte rows");
 };
 
@@ -489,7 +500,8 @@ struct Stage<FORM, false, MT> {
         for (int t = 0; t < PL; ++t)
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                char* q = lds + t * G::LDS_PLANE_MN + row_of(v, tid) * G::PITCH_MN + x_of(v, tid) * EB;
+                char* q = lds + t * G::LDS_PLANE_MN + G::lds_row_mn(row_of(v, tid)) * G::PITCH_MN +
+                          x_of(v, tid) * EB;
                 if constexpr (WPV == 4)
                     *reinterpret_cast<u4*>(q) = u4{w[t][v][0], w[t][v][1], w[t][v][2], w[t][v][3]};
                 else
@@ -548,12 +560,14 @@ struct Frag {
         if constexpr (KC) {
             return *reinterpret_cast<const i8v*>(plane + (x0 + (lane & 15)) * G::PITCH + k0 + 32 * run);
         } else {
+            // k = 32*run + 8h + c/2 (h = 0..3; k0 = 0, the k-step is one
+            // fragment deep) sits at LDS row 32h + 8*run + c/2 (lds_row_mn)
             const int c = lane & 15;
-            const char* q = plane + (k0 + 32 * run + (c >> 1)) * G::PITCH_MN + x0 + 8 * (c & 1);
+            const char* q = plane + (8 * run + (c >> 1)) * G::PITCH_MN + x0 + 8 * (c & 1);
             i8v v;
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                const i2v t = tr8(q + 8 * h * G::PITCH_MN);
+                const i2v t = tr8(q + 32 * h * G::PITCH_MN);
                 v[2 * h] = t[0];
                 v[2 * h + 1] = t[1];
             }
