@@ -203,8 +203,9 @@ def time_interleaved(g, policies, rounds=11, warmup=3, batch_s=0.01):
     return {pol: statistics.median(v) for pol, v in times.items()}, rounds * reps
 
 
-MX_FORMS = [("bf16", 2, 2516.6, 1), ("e4m3", 3, 5033.2, 1), ("bf16x3", 4, 2516.6, 6),
-            ("bf16x3_fast", 5, 2516.6, 3)]   # name, dtype code, MFMA peak (TFLOP/s), products
+# name, dtype code, MFMA peak (TFLOP/s), products, C tile (-1: the planner's choice)
+MX_FORMS = [("bf16", 2, 2516.6, 1, -1), ("e4m3", 3, 5033.2, 1, -1), ("e4m3_tile256", 3, 5033.2, 1, 256),
+            ("bf16x3", 4, 2516.6, 6, -1), ("bf16x3_fast", 5, 2516.6, 3, -1)]
 
 
 def _median_times(torch, calls, rounds, reps):
@@ -234,13 +235,17 @@ def mx_section(F, torch, sizes, forms=None):
     from paper_2302_08417_amd import synth
     out = []
     for n in sizes:
-        for name, dt, peak, prods in MX_FORMS:
+        for name, dt, peak, prods, tile in MX_FORMS:
             if forms and name not in forms:
                 continue
+            if tile == 256 and n < 4096:
+                continue      # a forced 256 tile on fewer tiles than CUs says nothing
             A, B, sa, sb, A32, B32 = synth.mx_device_operands(dt, n, seed=synth.BASE_SEED + n)
             C = torch.zeros(n, n, device="cuda")
             hs = {pol: F.Handle(policy=pol) for pol in (F.FIP_PACK_AUTO, F.FIP_PACK_CONSUME_ONLY,
                                                          F.FIP_PACK_NONE)}
+            for h in hs.values():
+                h.set_attr(F.FIP_ATTR_MX_TILE, tile)
 
             def mk(pol):
                 h = hs[pol]
@@ -272,14 +277,15 @@ def mx_section(F, torch, sizes, forms=None):
                                  np.zeros(32 * 32), 32)
             err = float(np.abs(got - ref.reshape(32, 32, order="F")).max() / D.max())
             fl = 2.0 * n ** 3
-            row = {"form": name, "m": n, "n": n, "k": n}
+            row = {"form": name, "m": n, "n": n, "k": n,
+                   "tile": hs[F.FIP_PACK_AUTO].last_plan().MT}
             for key, pol in (("fused", F.FIP_PACK_AUTO), ("pack_then_compute", F.FIP_PACK_CONSUME_ONLY),
                              ("no_pack", F.FIP_PACK_NONE)):
                 row[key + "_us"] = round(med[pol] * 1e3, 2)
                 row[key + "_tflops"] = round(fl / (med[pol] * 1e-3) / 1e12, 1)
             row["mfma_peak_tflops"] = peak
             row["fused_pct_mfma_peak"] = round(100 * row["fused_tflops"] * prods / peak, 2)
-            if dt == F.FIP_E4M3:
+            if dt == F.FIP_E4M3 and tile == -1:
                 # fip_quantize_fp8 of the binary32 operands (per row of op(A), per column of
                 # op(B); four launches each), timed on its own
                 hq = hs[F.FIP_PACK_AUTO]
@@ -318,7 +324,9 @@ def mx_deep_k_section(F, torch):
     magnitude <= 120 with unit scales."""
     out = []
     for (m, n, k) in MX_DEEP_K:
-        for name, dt, peak, prods in MX_FORMS:
+        for name, dt, peak, prods, tile in MX_FORMS:
+            if tile != -1:
+                continue
             g = torch.Generator(device="cuda").manual_seed(m + n + k + dt)
             if dt == F.FIP_E4M3:
                 A = torch.randint(0, 0x70, (m * k,), device="cuda", generator=g, dtype=torch.uint8)
@@ -824,7 +832,7 @@ def compact_summary(result, full):
         s["mixed_precision"] = {
             r["form"]: {"n": big, "pct_peak": r["fused_pct_mfma_peak"],
                         "vs_ptc": round(r["pack_then_compute_us"] / r["fused_us"], 3)}
-            for r in full["mixed_precision"] if r["m"] == big}
+            for r in full["mixed_precision"] if r["m"] == big and "tile256" not in r["form"]}
     if "level3" in full:
         s["l3_pct_peak"] = {f"{r['op']}_{r['dtype']}_{r['n']}": r["fused_pct_peak"]
                                    for r in full["level3"] if r["n"] == 8192}

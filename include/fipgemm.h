@@ -96,9 +96,10 @@ enum {
        on the device; the batch's tiles are dealt round-robin over them. */
     FIP_ATTR_VB_GRID = 9,
     /* Mixed-precision calls: C tile extent.  128: 128 x 128; 256: 256 x 256
-       (128 x 128 per wave), bfloat16 only (other forms always use 128);
-       -1 (default): 256 for bfloat16 when the call has at least 256 tiles of
-       256 x 256, else 128. */
+       (128 x 128 per wave), bfloat16 and E4M3 only (the split forms always
+       use 128); -1 (default): 256 for bfloat16 when the call has at least
+       256 tiles of 256 x 256, else 128 (E4M3 runs faster on 128 tiles, two
+       per CU, so it takes 256 only when asked). */
     FIP_ATTR_MX_TILE = 10,
     /* Split k into slices computed by separate workgroups; each slice
        writes its partial product to the workspace and a second kernel sums
@@ -193,7 +194,7 @@ enum {
  * workspace + a_pack_offset + c * a_copy_bytes.  The standalone pack
  * (fip_pack) and CONSUME_ONLY use copy 0.
  * Mixed-precision forms (dtype FIP_BF16 .. FIP_BF16X3_FAST): MT = NT = 128
- * (256 for bfloat16, see FIP_ATTR_MX_TILE), KT = 64 (bfloat16), 128 (E4M3) or
+ * (256 for bfloat16 and E4M3, see FIP_ATTR_MX_TILE), KT = 64 (bfloat16), 128 (E4M3) or
  * 32 (split forms); blocks keep the operand's storage orientation as above
  * (a_kmajor / b_kmajor), and each holds PLANES planes of MT*KT packed elements
  * one after the other (PLANES = 3 for FIP_BF16X3, 2 for FIP_BF16X3_FAST,

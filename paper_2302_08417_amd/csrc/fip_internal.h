@@ -127,14 +127,17 @@ enum MxForm : int32_t {
     kMxX3Fast = 3,   // A, B binary32, two bfloat16 terms, three products
 };
 constexpr int kMxTile = 128;                     // C tile 128 x 128, 2 x 2 waves
-constexpr int kMxTileBig = 256;                  // bfloat16 only: 128 x 128 per wave
+constexpr int kMxTileBig = 256;                  // bfloat16, E4M3: 128 x 128 per wave
 inline int mx_kt(int form) { return form == kMxBF16 ? 64 : form == kMxFP8 ? 128 : 32; }
 inline int mx_planes(int form) { return form == kMxX3 ? 3 : form == kMxX3Fast ? 2 : 1; }
 inline int mx_src_bytes(int form) { return form == kMxBF16 ? 2 : form == kMxFP8 ? 1 : 4; }
 inline int mx_pack_bytes(int form) { return form == kMxFP8 ? 1 : 2; }  // per plane element
 // Workgroups of one mixed-precision tile kernel that fit on a CU (LDS-bound).
 inline int mx_per_cu(int form, int mt) { return mt == 128 && (form == kMxBF16 || form == kMxFP8) ? 2 : 1; }
-inline bool mx_has_big(int form) { return form == kMxBF16; }
+inline bool mx_has_big(int form) { return form == kMxBF16 || form == kMxFP8; }
+// Forms whose planner default is the 256 tile once a call fills the device
+// with 256-tiles (E4M3 measures faster on the 128 tile, two per CU).
+inline bool mx_big_default(int form) { return form == kMxBF16; }
 
 struct MxLaunchDesc {
     int form;              // MxForm

@@ -241,14 +241,17 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     int cls, MT, KT;
     int64_t resident;
     if (form >= 0) {
-        // 128 x 128 tiles, or 256 x 256 (bfloat16 only); a packed element is
-        // PLANES values of the packed type.  Default: 256 once the launch
-        // fills the device with 256-tiles (one workgroup per CU, 256 tiles):
-        // measured ahead of 128 at m = n = k = 4096, 8192 and 16384.
+        // 128 x 128 tiles, or 256 x 256 (bfloat16, E4M3); a packed element is
+        // PLANES values of the packed type.  Default: 256 for bfloat16 once
+        // the launch fills the device with 256-tiles (one workgroup per CU,
+        // 256 tiles): measured ahead of 128 at m = n = k = 4096, 8192 and
+        // 16384.  E4M3 takes 256 only when asked: its 128 tile, two per CU,
+        // measured faster at 4096 and 16384.
         cls = 0;
         const int64_t big_tiles = cdiv(pl->ks.M, fip::kMxTileBig) * cdiv(pl->ks.N, fip::kMxTileBig);
         const bool big = fip::mx_has_big(form) &&
-                         (h->mx_tile == 256 || (h->mx_tile == -1 && big_tiles >= 256));
+                         (h->mx_tile == 256 ||
+                          (h->mx_tile == -1 && fip::mx_big_default(form) && big_tiles >= 256));
         MT = big ? fip::kMxTileBig : fip::kMxTile;
         KT = fip::mx_kt(form);
         pl->elem = fip::mx_planes(form) * fip::mx_pack_bytes(form);

@@ -553,17 +553,20 @@ struct Frag {
             return __builtin_bit_cast(bf8v, v);
         }
     }
-    // 32 E4M3 k-values: x = x0 + l%16, k = k0 + 32*(l/16) .. +32.
+    // 32 E4M3 k-values: x = x0 + l%16, k = k0 + 32*(l/16) .. +32 (sixteen-row
+    // form), or x = x0 + l%32, k = k0 + 32*(l/32) .. +32 (R = 32).
+    template <int R>
     __device__ __forceinline__ static i8v fp8(const char* plane, int x0, int k0, int lane)
     {
-        const int run = lane >> 4;
+        const int run = lane / R;
         if constexpr (KC) {
-            return *reinterpret_cast<const i8v*>(plane + (x0 + (lane & 15)) * G::PITCH + k0 + 32 * run);
+            return *reinterpret_cast<const i8v*>(plane + (x0 + (lane & (R - 1))) * G::PITCH + k0 + 32 * run);
         } else {
-            // k = 32*run + 8h + c/2 (h = 0..3; k0 = 0, the k-step is one
-            // fragment deep) sits at LDS row 32h + 8*run + c/2 (lds_row_mn)
+            // k = k0 + 32*run + 8h + c/2 (h = 0..3, k0 a multiple of 32) sits
+            // at LDS row 32h + 8*((k0 + 32*run) / 32) + c/2 (lds_row_mn)
             const int c = lane & 15;
-            const char* q = plane + (8 * run + (c >> 1)) * G::PITCH_MN + x0 + 8 * (c & 1);
+            const int xb = x0 + (lane & (R - 1) & ~15) + 8 * (c & 1);
+            const char* q = plane + (8 * ((k0 >> 5) + run) + (c >> 1)) * G::PITCH_MN + xb;
             i8v v;
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
@@ -647,10 +650,10 @@ struct Mma {
         if constexpr (FORM == kMxFP8) {
             i8v fb[FB];
 #pragma unroll
-            for (int b = 0; b < FB; ++b) fb[b] = FB_::fp8(sb, xb + b * 16, 0, lane);
+            for (int b = 0; b < FB; ++b) fb[b] = FB_::template fp8<16>(sb, xb + b * 16, 0, lane);
 #pragma unroll
             for (int a = 0; a < FB; ++a) {
-                const i8v fa = FA::fp8(sa, xa + a * 16, 0, lane);
+                const i8v fa = FA::template fp8<16>(sa, xa + a * 16, 0, lane);
 #pragma unroll
                 for (int b = 0; b < FB; ++b)
                     acc[0][a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
@@ -705,15 +708,17 @@ struct Mma {
     }
 };
 
-// MT = 256 (bfloat16): 32 x 32 MFMA blocks (v_mfma 32x32x16 bf16), 4 x 4
-// blocks of 16 accumulators per wave.  The 32 x 32 form keeps a wave's 256
-// accumulators in the AGPRs without the register shuffling the compiler
-// inserts around 64 separate 16 x 16 accumulators.  Fragment: lane l supplies
-// row l%32 and 8 consecutive k (16 bytes) at run l/32; output item r of lane l
-// is C[8*(r/4) + 4*(l/32) + r%4][l%32].
+// MT = 256 (bfloat16, E4M3): 32 x 32 MFMA blocks (v_mfma 32x32x16 bf16,
+// 32x32x64 f8f6f4), 4 x 4 blocks of 16 accumulators per wave.  The 32 x 32
+// form keeps a wave's 256 accumulators in the AGPRs without the register
+// shuffling the compiler inserts around 64 separate 16 x 16 accumulators.
+// Fragment: lane l supplies row l%32 and a run of consecutive k (8 bfloat16 or
+// 32 E4M3 values) at run l/32; output item r of lane l is
+// C[8*(r/4) + 4*(l/32) + r%4][l%32].
 template <int FORM>
 struct Mma<FORM, 256> {
-    static_assert(FORM == kMxBF16, "256 x 256 tiles: bfloat16 only");
+    static_assert(FORM == kMxBF16 || FORM == kMxFP8, "256 x 256 tiles: bfloat16 and E4M3");
+    static constexpr bool F8 = FORM == kMxFP8;
     typedef Geo<FORM, 256> G;
     static constexpr int NACC = 1;
     static constexpr int FB = G::WT / 32;   // 4
@@ -740,12 +745,20 @@ struct Mma<FORM, 256> {
         });
     }
 
-    // k-blocks of one MFMA: 16 k-values; NB per k-step.
-    static constexpr int KB = 16;
+    // k-blocks of one MFMA: 16 (bfloat16) or 64 (E4M3) k-values; NB per k-step.
+    static constexpr int KB = F8 ? 64 : 16;
     static constexpr int NB = G::KT / KB;
+    typedef std::conditional_t<F8, i8v, bf8v> V;
     struct Frags {
-        bf8v a[FB], b[FB];
+        V a[FB], b[FB];
     };
+
+    template <bool KC>
+    __device__ __forceinline__ static V frag(const char* plane, int x0, int k0, int lane)
+    {
+        if constexpr (F8) return Frag<FORM, 256, KC>::template fp8<32>(plane, x0, k0, lane);
+        else return Frag<FORM, 256, KC>::template bf16<32>(plane, x0, k0, lane);
+    }
 
     // Fragments of k-block s of the wave's rows (from xa) and columns (from xb).
     template <bool AKC, bool BKC>
@@ -753,11 +766,9 @@ struct Mma<FORM, 256> {
                                                 int lane, int s, Frags& f)
     {
 #pragma unroll
-        for (int b = 0; b < FB; ++b)
-            f.b[b] = Frag<FORM, 256, BKC>::template bf16<32>(sb, xb + b * 32, s * KB, lane);
+        for (int b = 0; b < FB; ++b) f.b[b] = frag<BKC>(sb, xb + b * 32, s * KB, lane);
 #pragma unroll
-        for (int a = 0; a < FB; ++a)
-            f.a[a] = Frag<FORM, 256, AKC>::template bf16<32>(sa, xa + a * 32, s * KB, lane);
+        for (int a = 0; a < FB; ++a) f.a[a] = frag<AKC>(sa, xa + a * 32, s * KB, lane);
     }
 
     __device__ __forceinline__ static void mma(const Frags& f, Acc& acc)
@@ -769,6 +780,61 @@ struct Mma<FORM, 256> {
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[a], f.b[b], acc[a][b], 0, 0, 0);
     }
 
+    // E4M3: a block's fragments are twice the bfloat16 ones (8 registers
+    // each), too many to hold two blocks beside the staged chunks, so the
+    // next block's fragments are read in place while this block's MFMAs run:
+    // A fragments one ahead of their MFMAs, each B fragment right after its
+    // last MFMA of this block.  On entry f holds the block's B fragments and
+    // its first A fragment; on exit, the next block's (when NEXT).
+    struct Frags8 {
+        i8v b[FB];
+        i8v a;
+    };
+
+    template <bool AKC, bool BKC>
+    __device__ __forceinline__ static void first8(const char* sa, const char* sb, int xa, int xb,
+                                                  int lane, int s, Frags8& f)
+    {
+#pragma unroll
+        for (int b = 0; b < FB; ++b) f.b[b] = frag<BKC>(sb, xb + b * 32, s * KB, lane);
+        f.a = frag<AKC>(sa, xa, s * KB, lane);
+    }
+
+    // Block s of the LDS buffer (sa); the next block is block ns of (na, nb).
+    // before_next() runs after the last read of this block has been issued
+    // and before the first read of the next one (the k-step's barrier goes
+    // there when the next block sits in the other buffer).
+    template <bool AKC, bool BKC, bool NEXT, class Hook>
+    __device__ __forceinline__ static void block8(const char* sa, int s, const char* na,
+                                                  const char* nb, int ns, int xa, int xb, int lane,
+                                                  Frags8& f, Acc& acc, Hook&& before_next)
+    {
+        i8v fa[2];
+        fa[0] = f.a;
+#pragma unroll
+        for (int a = 0; a < FB; ++a) {
+            if (a + 1 < FB) {
+                fa[(a + 1) & 1] = frag<AKC>(sa, xa + (a + 1) * 32, s * KB, lane);
+            } else {
+                __builtin_amdgcn_sched_barrier(0);
+                before_next();
+                __builtin_amdgcn_sched_barrier(0);
+                if constexpr (NEXT) fa[0] = frag<AKC>(na, xa, ns * KB, lane);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < FB; ++b) {
+                acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    fa[a & 1], f.b[b], acc[a][b], 0, 0, 0, 0, 0, 0);
+                if (a == FB - 1 && NEXT) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    f.b[b] = frag<BKC>(nb, xb + b * 32, ns * KB, lane);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        f.a = fa[0];
+    }
 };
 
 template <int FORM, int MT, bool AKC, bool BKC>
@@ -943,7 +1009,43 @@ gemm_mx_kernel(const MxParams P)
 
     load_chunks(q0);
     put_chunks(0, q0);
-    if constexpr (MT == 256) {
+    if constexpr (MT == 256 && FORM == kMxFP8) {
+        // E4M3 256 tile: the next block's fragments are read during this
+        // block's MFMAs (Mma::block8).  Per k-step: block 0, whose MFMAs
+        // overlap the reads of block 1; the next chunk from registers to the
+        // other LDS buffer and the global loads two k-steps ahead; block 1,
+        // whose last A fragment is read before the barrier, and whose last
+        // MFMAs overlap the reads of the next k-step's block 0 from the other
+        // buffer, after the barrier.
+        static_assert(MM::NB == 2, "two k-blocks per k-step");
+        typename MM::Frags8 f;
+        if (nK > 1) load_chunks(1);
+        __syncthreads();
+        const int xa = wm * WT, xb = wn * WT;
+        MM::template first8<AKC, BKC>(sA[0], sB[0], xa, xb, lane, 0, f);
+        auto nothing = [] {};
+        auto barrier = [] { __syncthreads(); };
+        // the last k-step is peeled off (MORE = false), as in the bfloat16 loop
+        auto kstep = [&](int q, auto more_c) {
+            constexpr bool more = decltype(more_c)::value;
+            const int cur = q & 1;
+            MM::template block8<AKC, BKC, true>(sA[cur], 0, sA[cur], sB[cur], 1, xa, xb, lane, f,
+                                                acc, nothing);
+            if constexpr (more) {
+                put_chunks(cur ^ 1, q + 1);
+                poll_issue(q);
+                if (q + 2 < nK) load_chunks(q + 2);
+                MM::template block8<AKC, BKC, true>(sA[cur], 1, sA[cur ^ 1], sB[cur ^ 1], 0, xa, xb,
+                                                    lane, f, acc, barrier);
+            } else {
+                MM::template block8<AKC, BKC, false>(sA[cur], 1, sA[cur], sB[cur], 0, xa, xb, lane,
+                                                     f, acc, nothing);
+            }
+            poll_finish();
+        };
+        for (int q = 0; q + 1 < nK; ++q) kstep(q, std::true_type{});
+        kstep(nK - 1, std::false_type{});
+    } else if constexpr (MT == 256) {
         // (no split k here: q0 = 0 and q1 = nK)
         // Software pipeline with one wave per SIMD: the fragments of k-block
         // s + 1 are read while the MFMAs of block s issue; the next chunk goes
@@ -1374,7 +1476,7 @@ hipError_t dispatch_mx(const MxLaunchDesc& d, bool pack)
     const bool big = d.mt == 256;
     switch (d.form) {
     case kMxBF16: return big ? launch_form<kMxBF16, 256>(d, pack) : launch_form<kMxBF16, 128>(d, pack);
-    case kMxFP8: return launch_form<kMxFP8, 128>(d, pack);
+    case kMxFP8: return big ? launch_form<kMxFP8, 256>(d, pack) : launch_form<kMxFP8, 128>(d, pack);
     case kMxX3: return launch_form<kMxX3, 128>(d, pack);
     case kMxX3Fast: return launch_form<kMxX3Fast, 128>(d, pack);
     default: return hipErrorInvalidValue;

@@ -357,7 +357,8 @@ def test_mx_plans(h, dtype, KT, planes, eb):
 
 
 def test_mx_tile_choice(h):
-    """256 x 256 tiles: bfloat16 only; by default once a call has >= 256 of them."""
+    """256 x 256 tiles: bfloat16 and E4M3; by default (bfloat16 only) once a call has >= 256 of
+    them."""
     def mt(dtype, n, tile=-1):
         assert F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, tile) == 0
         rc, p = F.fip_plan(h, dtype, 0, n, n, 512, "N", "N")
@@ -366,8 +367,10 @@ def test_mx_tile_choice(h):
     try:
         assert mt(F.FIP_BF16, 16384) == 256 and mt(F.FIP_BF16, 4096) == 256
         assert mt(F.FIP_BF16, 3840) == 128 and mt(F.FIP_BF16, 2048) == 128
-        assert mt(F.FIP_BF16, 2048, 256) == 256 and mt(F.FIP_BF16, 16384, 128) == 128
-        for other in (F.FIP_E4M3, F.FIP_BF16X3, F.FIP_BF16X3_FAST):
+        assert mt(F.FIP_E4M3, 16384) == 128 and mt(F.FIP_E4M3, 4096) == 128
+        for big in (F.FIP_BF16, F.FIP_E4M3):
+            assert mt(big, 2048, 256) == 256 and mt(big, 16384, 128) == 128
+        for other in (F.FIP_BF16X3, F.FIP_BF16X3_FAST):
             assert mt(other, 16384) == 128 and mt(other, 16384, 256) == 128
         assert F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, 64) == 3
     finally:
@@ -402,7 +405,7 @@ def test_split_choice(h):
     """Split k: FP64/FP32 when the tiles fill at most half of the resident workgroups (>= 16
     k-steps per slice); the mixed forms on the 128 tile when they fill at most a quarter
     (>= 256 k per slice for the split forms, >= 1024 k for bfloat16 / E4M3); never on the
-    bfloat16 256 tile; at most 32 slices, none empty."""
+    256 tile; at most 32 slices, none empty."""
     def plan(dtype, m, n, k, split=-1, tile=-1):
         assert F.fip_set_attr(h, F.FIP_ATTR_SPLIT_K, split) == 0
         assert F.fip_set_attr(h, F.FIP_ATTR_MX_TILE, tile) == 0

@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 FORMS = [synth.FORM_BF16, synth.FORM_E4M3, synth.FORM_BF16X3, synth.FORM_BF16X3_FAST]
 FORM_IDS = ["bf16", "e4m3", "bf16x3", "bf16x3f"]
 COL, ROW = synth.COL, synth.ROW
-BIG = [(synth.FORM_BF16, 256)]   # forms with 256 x 256 tiles
+BIG = [(synth.FORM_BF16, 256), (synth.FORM_E4M3, 256)]   # forms with 256 x 256 tiles
+BIG_IDS = ["bf16-256", "e4m3-256"]
 
 
 @pytest.fixture(scope="module")
@@ -91,23 +92,26 @@ def test_mx_unaligned_leading_dims(F, form, pad):
     check_mx(c, out)
 
 
-@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+@pytest.mark.parametrize("form,tile", [(f, -1) for f in FORMS] + [(synth.FORM_E4M3, 256)],
+                         ids=FORM_IDS + ["e4m3-256"])
 @pytest.mark.parametrize("layout,tA,tB", [(COL, "N", "N"), (ROW, "N", "T")])
-def test_mx_modes_bitwise(F, form, layout, tA, tB):
+def test_mx_modes_bitwise(F, form, tile, layout, tA, tB):
     """AUTO / ALL / NONE / CONSUME_ONLY / other tile order / no publishing run the same tile
     arithmetic in the same k order: C must agree bit for bit.  The launch has more tiles than
     fit on the GPU at once, so later tiles do read packed panels."""
-    say("modes", form, layout, tA, tB)
+    say("modes", form, tile, layout, tA, tB)
     # several rounds of tiles: 256 x 256 tiles (bfloat16, E4M3) need 8192^2
     m = n = 8192 if form in (synth.FORM_BF16, synth.FORM_E4M3) else 4096
     k = 160 if form != synth.FORM_E4M3 else 300
     c = synth.make_mx_case(form, layout, m, n, k, tA, tB, alpha=1.0, beta=0.5, seed=77 + form)
-    ref, _ = run_mx(F, c, F.FIP_PACK_NONE)
+    ref, h0 = run_mx(F, c, F.FIP_PACK_NONE, tile=tile)
+    if tile == 256:
+        assert h0.last_plan().MT == 256
     total_packed = 0
     for pol, order, nopub in [(F.FIP_PACK_AUTO, 0, 0), (F.FIP_PACK_ALL, 0, 0),
                               (F.FIP_PACK_ALL, 1, 0), (F.FIP_PACK_ALL, 0, 1),
                               (F.FIP_PACK_CONSUME_ONLY, 0, 0)]:
-        out, h = run_mx(F, c, pol, order=order, no_publish=nopub, stats=1,
+        out, h = run_mx(F, c, pol, order=order, no_publish=nopub, stats=1, tile=tile,
                         copies=8 if order == 1 else -1)
         if pol == F.FIP_PACK_ALL and not nopub:
             p = h.last_plan()
@@ -123,7 +127,7 @@ def test_mx_modes_bitwise(F, form, layout, tA, tB):
     assert np.abs(got - Cref).max() <= 4 * k * 2.0 ** -24 * D.max()
 
 
-@pytest.mark.parametrize("form,tile", BIG, ids=["bf16-256"])
+@pytest.mark.parametrize("form,tile", BIG, ids=BIG_IDS)
 @pytest.mark.parametrize("layout,tA,tB", [(COL, "N", "N"), (COL, "T", "N"), (ROW, "N", "T"),
                                           (ROW, "T", "T")])
 @pytest.mark.parametrize("c_bf16", [False, True], ids=["c32", "c16"])
@@ -139,7 +143,7 @@ def test_mx_big_tile_matches_oracle(F, form, tile, layout, tA, tB, c_bf16):
 
 
 @pytest.mark.parametrize("form,tile", [(f, 128) for f in FORMS] + BIG,
-                         ids=[i + "-128" for i in FORM_IDS] + ["bf16-256"])
+                         ids=[i + "-128" for i in FORM_IDS] + BIG_IDS)
 @pytest.mark.parametrize("layout,tA,tB", [(COL, "N", "N"), (COL, "T", "T"), (ROW, "N", "T"),
                                           (ROW, "T", "N")])
 @pytest.mark.parametrize("copies", [1, 8], ids=["shared", "per-xcd"])
@@ -180,7 +184,7 @@ def test_mx_packed_buffers_bit_exact(F, form, tile, layout, tA, tB, copies):
 
 
 @pytest.mark.parametrize("form,tile", [(f, 128) for f in FORMS] + BIG,
-                         ids=[i + "-128" for i in FORM_IDS] + ["bf16-256"])
+                         ids=[i + "-128" for i in FORM_IDS] + BIG_IDS)
 def test_mx_standalone_pack_bit_exact(F, form, tile):
     import torch
     say("standalone mx pack", form, tile)
