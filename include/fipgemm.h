@@ -538,6 +538,45 @@ int fip_vbatched_tune(fip_handle_t handle, int layout, int64_t count, const int3
                       const int64_t* ldc, int* split_out);
 
 /*
+ * Autotuner of the FP64 / FP32 GEMM plan (the paper's Sec. 3.3 leaves its
+ * blocking choices to tuning): times the call (a warm-up, then the median of
+ * 3 launches on the handle's stream) for every tile class (128, 64, 32), each
+ * with the planner's k split and with none (configurations that plan alike
+ * are timed once), under the handle's pack policy and other attributes.  The
+ * fastest is kept in the handle for this call shape (dtype, layout, m, n, k,
+ * transA, transB): later calls, fip_plan and workspace queries with the same
+ * shape use it while FIP_ATTR_TILE and FIP_ATTR_SPLIT_K are -1.  Writes the
+ * tile class to *tile_out and the split (-1: the planner's, 1: none) to
+ * *split_out.  C is overwritten with unspecified values (several products
+ * accumulate into it when beta != 0): pass a scratch C of the same shape.
+ * Arguments as in fip_dgemm / fip_sgemm; positions 16 tile_out, 17
+ * split_out.  Quick return (nothing timed, the planner's choice reported):
+ * m, n or k = 0, or alpha = 0.  Synchronous.
+ */
+int fip_dgemm_tune(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, double alpha,
+                   const double* A, int64_t lda, char transA, const double* B, int64_t ldb,
+                   char transB, double beta, double* C, int64_t ldc, int* tile_out,
+                   int* split_out);
+int fip_sgemm_tune(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, float alpha,
+                   const float* A, int64_t lda, char transA, const float* B, int64_t ldb,
+                   char transB, float beta, float* C, int64_t ldc, int* tile_out, int* split_out);
+
+/*
+ * Persisted tuning table (host only, no HIP call).  fip_tune_save writes
+ * every choice the handle holds (fip_dgemm_tune / fip_sgemm_tune entries and
+ * fip_vbatched_tune thresholds) to the text file at path (created or
+ * replaced): a header line "fipgemm-tune 1", then one line per entry,
+ * "gemm dtype layout m n k tA tB tile split" (tA, tB: 1 transposed) or
+ * "vb signature split".  fip_tune_load reads such a file into the handle,
+ * replacing entries with the same key and keeping the others; the file is
+ * checked whole first, so a malformed file changes nothing.  Returns 0, 1 if
+ * path is null or the file cannot be opened or written, 2 if its contents
+ * are malformed, FIP_ERR_ALLOC.
+ */
+int fip_tune_save(fip_handle_t handle, const char* path);
+int fip_tune_load(fip_handle_t handle, const char* path);
+
+/*
  * Diagnostic (host only, no HIP call): the tile that workgroup w of a launch
  * over tiles_m x tiles_n C tiles computes, for tile order 0 or 1 (see
  * FIP_ATTR_ORDER): tm[w], tn[w] for w = 0 .. tiles_m*tiles_n - 1 (host

@@ -4,8 +4,11 @@
 #include "fipgemm.h"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
+#include <map>
+#include <stdio.h>
 #include <new>
 #include <random>
 #include <string.h>
@@ -70,6 +73,14 @@ struct VbState {
     }
 };
 
+// Tile class and k split that fip_gemm_tune measured fastest for a call
+// shape (dtype, layout, m, n, k, transA, transB).
+typedef std::array<int64_t, 7> GemmKey;
+struct GemmChoice {
+    int tile;    // tile class 0, 1, 2
+    int split;   // FIP_ATTR_SPLIT_K semantics: -1 planner's, 1 none, >= 2 slices
+};
+
 struct fip_handle_s {
     uint32_t magic;
     hipStream_t stream;
@@ -91,6 +102,7 @@ struct fip_handle_s {
     int last_dma;     // FIP_ATTR_LAST_DMA
     int last_hip_error;  // FIP_ATTR_LAST_HIP_ERROR
     VbState* vb;
+    std::map<GemmKey, GemmChoice>* tuned;   // fip_gemm_tune results (null: none)
 };
 
 namespace {
@@ -222,6 +234,11 @@ bool valid_dtype(int dtype)
     return dtype == FIP_F64 || dtype == FIP_F32 || is_complex(dtype) || mx_form_of(dtype) >= 0;
 }
 
+GemmKey gemm_key(int dtype, int layout, int64_t m, int64_t n, int64_t k, char tA, char tB)
+{
+    return GemmKey{dtype, layout, m, n, k, is_trans(tA) ? 1 : 0, is_trans(tB) ? 1 : 0};
+}
+
 void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
                char tA, char tB, bool standalone_pack, Plan* pl, int policy_override = -1)
 {
@@ -233,6 +250,7 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     // band once, so later rounds find them packed) measured 20-35 % faster.
     pl->order = h->order >= 0 ? h->order : (form == fip::kMxX3 || form == fip::kMxX3Fast ? 1 : 0);
     pl->ks = kernel_shape(layout, m, n);
+    int split_attr = h->split_k;   // FIP_ATTR_SPLIT_K, or a tuned choice below
     // Complex calls (1m method): the kernel multiplies the 2M x 2K expansion of
     // its A side by the 2K x N expansion of its B side, all in real terms.
     const bool cx = is_complex(dtype);
@@ -259,6 +277,14 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
     } else {
         pl->elem = dtype == FIP_F64 || dtype == FIP_C128 ? 8 : 4;
         cls = h->tile_override >= 0 ? h->tile_override : choose_tile_class(pl->ks.M, pl->ks.N);
+        // a tuned choice for this call shape, unless the attributes force one
+        if (h->tuned != nullptr && h->tile_override < 0 && h->split_k == -1) {
+            const auto it = h->tuned->find(gemm_key(dtype, layout, m, n, k, tA, tB));
+            if (it != h->tuned->end()) {
+                cls = it->second.tile;
+                split_attr = it->second.split;
+            }
+        }
         MT = fip::tile_mt(cls);
         KT = fip::tile_kt(cls, pl->elem);
         resident = resident_tiles(cls);
@@ -289,9 +315,9 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
         const int64_t min_slice = form < 0 ? kMinSliceKsteps
                                            : std::max<int64_t>(1, (splits ? kMinSliceKSplit : kMinSliceKCopy) / KT);
         int64_t sp = 1;
-        if (h->split_k > 0) {
-            sp = h->split_k;
-        } else if (h->split_k == -1 && tiles > 0 && busy * tiles <= resident) {
+        if (split_attr > 0) {
+            sp = split_attr;
+        } else if (split_attr == -1 && tiles > 0 && busy * tiles <= resident) {
             sp = resident / tiles;
             if (sp > pl->nK / min_slice) sp = pl->nK / min_slice;
             if (sp > kMaxSplit) sp = kMaxSplit;
@@ -1466,6 +1492,7 @@ int fip_create(fip_handle_t* handle)
     h->copies = -1;
     h->dma = kDefaultDma;
     h->vb = nullptr;
+    h->tuned = nullptr;
     *handle = h;
     return 0;
 }
@@ -1475,6 +1502,7 @@ int fip_destroy(fip_handle_t handle)
     if (!valid_handle(handle)) return FIP_ERR_HANDLE;
     handle->magic = 0;
     delete handle->vb;
+    delete handle->tuned;
     delete handle;
     return 0;
 }
@@ -1922,6 +1950,188 @@ int fip_vbatched_tune(fip_handle_t handle, int layout, int64_t count, const int3
     } catch (...) {
         return FIP_ERR_LAUNCH;
     }
+}
+
+extern "C++" {
+namespace {
+
+// Time one configuration of a GEMM call: a warm-up, then the median of three
+// launches (HIP events on the handle's stream), in milliseconds.
+template <typename T>
+int time_gemm(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64_t k, T alpha,
+              const T* A, int64_t lda, char tA, const T* B, int64_t ldb, char tB, T beta, T* C,
+              int64_t ldc, hipEvent_t e0, hipEvent_t e1, float* ms)
+{
+    float t[3];
+    int rc = gemm_impl<T>(h, dtype, layout, m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc);
+    for (int r = 0; r < 3 && rc == 0; ++r) {
+        if (hipEventRecord(e0, h->stream) != hipSuccess) return FIP_ERR_LAUNCH;
+        rc = gemm_impl<T>(h, dtype, layout, m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc);
+        if (rc) break;
+        if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t[r], e0, e1) != hipSuccess)
+            return FIP_ERR_LAUNCH;
+    }
+    if (rc) return rc;
+    std::sort(t, t + 3);
+    *ms = t[1];
+    return 0;
+}
+
+template <typename T>
+int gemm_tune_impl(fip_handle_t h, int dtype, int layout, int64_t m, int64_t n, int64_t k,
+                   T alpha, const T* A, int64_t lda, char tA, const T* B, int64_t ldb, char tB,
+                   T beta, T* C, int64_t ldc, int* tile_out, int* split_out)
+{
+    try {
+        if (!valid_handle(h)) return FIP_ERR_HANDLE;
+        const int bad = check_args(2, layout, m, n, k, alpha != T(0), A, lda, tA, B, ldb, tB, true,
+                                   beta == T(1), C, ldc);
+        if (bad) return bad;
+        if (tile_out == nullptr) return 16;
+        if (split_out == nullptr) return 17;
+        // the planner's choice, reported when there is nothing to time
+        Plan pl0;
+        make_plan(h, dtype, layout, m, n, k, tA, tB, false, &pl0);
+        *tile_out = pl0.pub.tile_class;
+        *split_out = -1;
+        if (m == 0 || n == 0 || k == 0 || alpha == T(0)) return 0;
+        const int keep_tile = h->tile_override, keep_split = h->split_k;
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return FIP_ERR_LAUNCH;
+        if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FIP_ERR_LAUNCH; }
+        // candidates: every tile class, with the planner's k split and with none
+        // (configurations that plan the same tile class and split are timed once)
+        std::vector<std::pair<int, int>> seen;
+        float best_t = 1e30f;
+        GemmChoice best{pl0.pub.tile_class, -1};
+        int rc = 0;
+        for (int cls = 0; cls < fip::kNumTileClasses && rc == 0; ++cls) {
+            for (int sp : {-1, 1}) {
+                h->tile_override = cls;
+                h->split_k = sp;
+                Plan pl;
+                make_plan(h, dtype, layout, m, n, k, tA, tB, false, &pl);
+                if (std::find(seen.begin(), seen.end(), std::make_pair(cls, pl.split)) != seen.end())
+                    continue;
+                seen.emplace_back(cls, pl.split);
+                float ms = 0.f;
+                rc = time_gemm<T>(h, dtype, layout, m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C,
+                                  ldc, e0, e1, &ms);
+                if (rc) break;
+                if (ms < best_t) {
+                    best_t = ms;
+                    best = GemmChoice{cls, sp};
+                }
+            }
+        }
+        h->tile_override = keep_tile;
+        h->split_k = keep_split;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        if (h->tuned == nullptr) {
+            h->tuned = new (std::nothrow) std::map<GemmKey, GemmChoice>;
+            if (h->tuned == nullptr) return FIP_ERR_ALLOC;
+        }
+        (*h->tuned)[gemm_key(dtype, layout, m, n, k, tA, tB)] = best;
+        *tile_out = best.tile;
+        *split_out = best.split;
+        return 0;
+    } catch (...) {
+        return FIP_ERR_LAUNCH;
+    }
+}
+
+constexpr const char* kTuneHeader = "fipgemm-tune 1";
+
+}  // namespace
+}  // extern "C++"
+
+int fip_dgemm_tune(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, double alpha,
+                   const double* A, int64_t lda, char transA, const double* B, int64_t ldb,
+                   char transB, double beta, double* C, int64_t ldc, int* tile_out,
+                   int* split_out)
+{
+    return gemm_tune_impl<double>(handle, FIP_F64, layout, m, n, k, alpha, A, lda, transA, B, ldb,
+                                  transB, beta, C, ldc, tile_out, split_out);
+}
+
+int fip_sgemm_tune(fip_handle_t handle, int layout, int64_t m, int64_t n, int64_t k, float alpha,
+                   const float* A, int64_t lda, char transA, const float* B, int64_t ldb,
+                   char transB, float beta, float* C, int64_t ldc, int* tile_out, int* split_out)
+{
+    return gemm_tune_impl<float>(handle, FIP_F32, layout, m, n, k, alpha, A, lda, transA, B, ldb,
+                                 transB, beta, C, ldc, tile_out, split_out);
+}
+
+int fip_tune_save(fip_handle_t handle, const char* path)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    if (path == nullptr) return 1;
+    FILE* f = fopen(path, "w");
+    if (f == nullptr) return 1;
+    bool ok = fprintf(f, "%s\n", kTuneHeader) > 0;
+    if (handle->tuned != nullptr)
+        for (const auto& e : *handle->tuned)
+            ok = ok && fprintf(f, "gemm %lld %lld %lld %lld %lld %lld %lld %d %d\n",
+                               (long long)e.first[0], (long long)e.first[1], (long long)e.first[2],
+                               (long long)e.first[3], (long long)e.first[4], (long long)e.first[5],
+                               (long long)e.first[6], e.second.tile, e.second.split) > 0;
+    if (handle->vb != nullptr)
+        for (const auto& e : handle->vb->tuned)
+            ok = ok && fprintf(f, "vb %llu %d\n", (unsigned long long)e.first, e.second) > 0;
+    ok = (fclose(f) == 0) && ok;
+    return ok ? 0 : 1;
+}
+
+int fip_tune_load(fip_handle_t handle, const char* path)
+{
+    if (!valid_handle(handle)) return FIP_ERR_HANDLE;
+    if (path == nullptr) return 1;
+    FILE* f = fopen(path, "r");
+    if (f == nullptr) return 1;
+    // parse the whole file first: a malformed file changes nothing
+    std::vector<std::pair<GemmKey, GemmChoice>> g;
+    std::vector<std::pair<uint64_t, int>> v;
+    char line[512];
+    bool ok = fgets(line, sizeof line, f) != nullptr && strncmp(line, kTuneHeader, strlen(kTuneHeader)) == 0;
+    while (ok && fgets(line, sizeof line, f) != nullptr) {
+        long long a[7];
+        int tile, split;
+        unsigned long long sig;
+        char tail;
+        if (sscanf(line, "gemm %lld %lld %lld %lld %lld %lld %lld %d %d %c", &a[0], &a[1], &a[2],
+                   &a[3], &a[4], &a[5], &a[6], &tile, &split, &tail) == 9) {
+            ok = valid_dtype((int)a[0]) && mx_form_of((int)a[0]) < 0 &&
+                 (a[1] == FIP_COL_MAJOR || a[1] == FIP_ROW_MAJOR) && a[2] >= 0 && a[3] >= 0 &&
+                 a[4] >= 0 && (a[5] == 0 || a[5] == 1) && (a[6] == 0 || a[6] == 1) && tile >= 0 &&
+                 tile < fip::kNumTileClasses && (split == -1 || (split >= 1 && split <= kMaxSplit));
+            g.emplace_back(GemmKey{a[0], a[1], a[2], a[3], a[4], a[5], a[6]}, GemmChoice{tile, split});
+        } else if (sscanf(line, "vb %llu %d %c", &sig, &split, &tail) == 2) {
+            ok = split >= 0;
+            v.emplace_back((uint64_t)sig, split);
+        } else {
+            ok = line[0] == '\n' || line[0] == '#';
+        }
+    }
+    fclose(f);
+    if (!ok) return 2;
+    try {
+        if (!g.empty() && handle->tuned == nullptr) {
+            handle->tuned = new (std::nothrow) std::map<GemmKey, GemmChoice>;
+            if (handle->tuned == nullptr) return FIP_ERR_ALLOC;
+        }
+        if (!v.empty() && handle->vb == nullptr) {
+            handle->vb = new (std::nothrow) VbState;
+            if (handle->vb == nullptr) return FIP_ERR_ALLOC;
+        }
+        for (const auto& e : g) (*handle->tuned)[e.first] = e.second;
+        for (const auto& e : v) handle->vb->tuned[e.first] = e.second;
+    } catch (...) {
+        return FIP_ERR_ALLOC;
+    }
+    return 0;
 }
 
 int fip_tile_map(int64_t tiles_m, int64_t tiles_n, int order, int32_t* tm, int32_t* tn)

@@ -15,9 +15,11 @@
 // the partial sum over its columns c = q + 8i of S[r, c] x_c, minus alpha b_r
 // on the lane that owns r; three DPP butterfly steps add the eight partials
 // (every lane ends with the same bits, the additions commute), and
-//   x_r = (alpha b_r - sum_c S[r, c] x_c) / S[r, r]
+//   x_r = (alpha b_r - sum_c S[r, c] x_c) * (1 / S[r, r])
 // over the already solved c (ascending r for lower S, descending for upper
-// S); no division for a unit diagonal.  Unsolved x_c are zero and so are the
+// S), with the reciprocals of the diagonal formed once per block, as BLIS
+// packs them for its TRSM microkernel, so no division sits on the chain from
+// one unknown to the next; nothing for a unit diagonal.  Unsolved x_c are zero and so are the
 // entries of S outside the triangle, so terms that fall outside add exact
 // zeros.  Only the referenced triangle of the stored matrix is read (and not
 // the diagonal when it is unit).  A block of nb < NB rows is padded with
@@ -59,6 +61,7 @@ __global__ void __launch_bounds__(kThreads) trsm_block_kernel(const T* __restric
     constexpr int NI = NB / kLanes;     // rows owned per lane
     static_assert(NB % kLanes == 0, "rows split evenly over the lanes");
     __shared__ T S[NB][NB + 1];
+    __shared__ T Dinv[NB];   // 1 / S[r, r]
     const int tid = threadIdx.x;
     for (int idx = tid; idx < NB * NB; idx += kThreads) {
         // consecutive threads walk contiguous memory of A
@@ -73,6 +76,7 @@ __global__ void __launch_bounds__(kThreads) trsm_block_kernel(const T* __restric
             v = T(1);   // padding rows: identity
         }
         S[r][c] = v;
+        if (r == c) Dinv[r] = T(1) / v;
     }
     __syncthreads();
     // a group of eight lanes shares its right-hand side, so a group is live
@@ -105,7 +109,7 @@ __global__ void __launch_bounds__(kThreads) trsm_block_kernel(const T* __restric
         acc = acc + dpp<kDppXor1>(acc);
         acc = acc + dpp<kDppXor2>(acc);
         acc = acc + dpp<kDppHalfMirror>(acc);
-        const T x = UNIT ? -acc : -acc / S[r][r];
+        const T x = UNIT ? -acc : -acc * Dinv[r];
         if (q == (r & (kLanes - 1))) xq[own] = x;
     }
 #pragma unroll

@@ -91,6 +91,12 @@ _SIGS = {
                           _ch, ctypes.c_double, _vp, _i64],
     "fip_sgemm": [_vp, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64, _ch,
                   ctypes.c_float, _vp, _i64],
+    "fip_dgemm_tune": [_vp, _i32, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _ch, _vp, _i64,
+                       _ch, ctypes.c_double, _vp, _i64, _vp, _vp],
+    "fip_sgemm_tune": [_vp, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _ch, _vp, _i64,
+                       _ch, ctypes.c_float, _vp, _i64, _vp, _vp],
+    "fip_tune_save": [_vp, ctypes.c_char_p],
+    "fip_tune_load": [_vp, ctypes.c_char_p],
     "fip_zgemm": [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _i64, _ch, _vp, _i64, _ch, _vp, _vp,
                   _i64],
     "fip_cgemm": [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _i64, _ch, _vp, _i64, _ch, _vp, _vp,
@@ -208,6 +214,36 @@ def fip_dgemm_noalloc(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB,
 def fip_sgemm(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
     return _lib.fip_sgemm(h, layout, m, n, k, alpha, _addr(A), lda, _trans(transA), _addr(B), ldb,
                           _trans(transB), beta, _addr(C), ldc)
+
+
+def _tune(fn, h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+    tile, split = ctypes.c_int(-2), ctypes.c_int(-2)
+    rc = fn(h, layout, m, n, k, alpha, _addr(A), lda, _trans(transA), _addr(B), ldb,
+            _trans(transB), beta, _addr(C), ldc, ctypes.byref(tile), ctypes.byref(split))
+    return rc, tile.value, split.value
+
+
+def fip_dgemm_tune(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+    """Returns (rc, tile class, split): see the header."""
+    return _tune(_lib.fip_dgemm_tune, h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB,
+                 beta, C, ldc)
+
+
+def fip_sgemm_tune(h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+    return _tune(_lib.fip_sgemm_tune, h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB,
+                 beta, C, ldc)
+
+
+def _path(path):
+    return None if path is None else os.fsencode(path)
+
+
+def fip_tune_save(h, path):
+    return _lib.fip_tune_save(h, _path(path))
+
+
+def fip_tune_load(h, path):
+    return _lib.fip_tune_load(h, _path(path))
 
 
 def _pair(z, ctype):
@@ -418,6 +454,36 @@ class Handle:
         fn = fip_dgemm if dt == FIP_F64 else fip_sgemm
         rc = fn(self.h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc)
         self._check(fn.__name__, rc)
+
+    def tune(self, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
+        """fip_dgemm_tune / fip_sgemm_tune by C's dtype, with a workspace large enough for
+        every candidate it times; returns (tile class, split).  C is overwritten."""
+        import torch
+        dt = FIP_F64 if C.dtype == torch.float64 else FIP_F32
+        self.bind_stream()
+        keep = (self.get_attr(FIP_ATTR_TILE), self.get_attr(FIP_ATTR_SPLIT_K))
+        need = 0
+        try:
+            for tile in range(3):
+                for split in (-1, 1):
+                    self.set_attr(FIP_ATTR_TILE, tile)
+                    self.set_attr(FIP_ATTR_SPLIT_K, split)
+                    need = max(need, self.plan(dt, layout, m, n, k, transA, transB).workspace_bytes)
+        finally:
+            self.set_attr(FIP_ATTR_TILE, keep[0])
+            self.set_attr(FIP_ATTR_SPLIT_K, keep[1])
+        self.ensure_workspace(need)
+        fn = fip_dgemm_tune if dt == FIP_F64 else fip_sgemm_tune
+        rc, tile, split = fn(self.h, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta,
+                             C, ldc)
+        self._check(fn.__name__, rc)
+        return tile, split
+
+    def tune_save(self, path):
+        self._check("fip_tune_save", fip_tune_save(self.h, path))
+
+    def tune_load(self, path):
+        self._check("fip_tune_load", fip_tune_load(self.h, path))
 
     def zgemm(self, layout, m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc):
         """Complex GEMM by C's dtype (complex128 -> fip_zgemm, complex64 -> fip_cgemm)."""

@@ -585,3 +585,81 @@ def test_trsm_argument_positions_and_plan(h):
         assert rc2 == 0 and p.workspace_bytes >= q.workspace_bytes
     finally:
         F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO)
+
+
+def test_tune_argument_checks(h):
+    """fip_dgemm_tune / fip_sgemm_tune check their arguments like fip_dgemm (same positions)
+    and their outputs (16, 17) before any HIP call."""
+    for fn in (F.fip_dgemm_tune, F.fip_sgemm_tune):
+        assert fn(None, 0, 4, 5, 6, 1.0, FAKE, 4, "N", FAKE, 6, "N", 0.0, FAKE, 4)[0] == F.FIP_ERR_HANDLE
+        assert fn(h, 0, 4, 5, 6, 1.0, FAKE, 3, "N", FAKE, 6, "N", 0.0, FAKE, 4)[0] == 8
+        assert fn(h, 0, 4, 5, 6, 1.0, FAKE, 4, "N", FAKE, 6, "N", 0.0, FAKE, 3)[0] == 15
+        raw = getattr(F._lib, fn.__name__)
+        tile = ctypes.c_int()
+        assert raw(h, 0, 4, 5, 6, 1.0, FAKE, 4, b"N", FAKE, 6, b"N", 0.0, FAKE, 4, None,
+                   ctypes.byref(tile)) == 16
+        assert raw(h, 0, 4, 5, 6, 1.0, FAKE, 4, b"N", FAKE, 6, b"N", 0.0, FAKE, 4,
+                   ctypes.byref(tile), None) == 17
+
+
+def test_tune_table_load_save(h, tmp_path):
+    """A loaded tuning entry steers the plan of its call shape (tile class, k split) unless
+    FIP_ATTR_TILE / FIP_ATTR_SPLIT_K force one; other shapes keep the planner's choice; save
+    writes what the handle holds; a malformed or missing file changes nothing."""
+    rc, p0 = F.fip_plan(h, F.FIP_F64, 0, 5000, 5000, 512, "N", "N")
+    assert rc == 0 and p0.tile_class == 0
+    rc, q0 = F.fip_plan(h, F.FIP_F32, 1, 300, 200, 4000, "T", "N")
+    assert rc == 0
+    good = tmp_path / "good.txt"
+    good.write_text("fipgemm-tune 1\n"
+                    f"gemm {F.FIP_F64} 0 5000 5000 512 0 0 2 1\n"
+                    f"gemm {F.FIP_F32} 1 300 200 4000 1 0 1 -1\n"
+                    "vb 12345 16\n")
+    assert F.fip_tune_load(h, str(good)) == 0
+    rc, p = F.fip_plan(h, F.FIP_F64, 0, 5000, 5000, 512, "N", "N")
+    assert rc == 0 and (p.tile_class, p.split_k) == (2, 1)
+    rc, q = F.fip_plan(h, F.FIP_F32, 1, 300, 200, 4000, "T", "N")
+    assert rc == 0 and q.tile_class == 1
+    # another shape, or another transpose, is not affected
+    rc, p2 = F.fip_plan(h, F.FIP_F64, 0, 5000, 5000, 512, "T", "N")
+    assert rc == 0 and p2.tile_class == p0.tile_class
+    # attributes win over the table
+    try:
+        assert F.fip_set_attr(h, F.FIP_ATTR_TILE, 0) == 0
+        rc, p3 = F.fip_plan(h, F.FIP_F64, 0, 5000, 5000, 512, "N", "N")
+        assert rc == 0 and p3.tile_class == 0
+    finally:
+        F.fip_set_attr(h, F.FIP_ATTR_TILE, -1)
+    saved = tmp_path / "saved.txt"
+    assert F.fip_tune_save(h, str(saved)) == 0
+    lines = saved.read_text().splitlines()
+    assert lines[0] == "fipgemm-tune 1"
+    assert f"gemm {F.FIP_F64} 0 5000 5000 512 0 0 2 1" in lines
+    assert f"gemm {F.FIP_F32} 1 300 200 4000 1 0 1 -1" in lines
+    assert "vb 12345 16" in lines
+    # round trip into a fresh handle
+    rc, h2 = F.fip_create()
+    assert rc == 0
+    try:
+        assert F.fip_tune_load(h2, str(saved)) == 0
+        rc, p4 = F.fip_plan(h2, F.FIP_F64, 0, 5000, 5000, 512, "N", "N")
+        assert rc == 0 and (p4.tile_class, p4.split_k) == (2, 1)
+    finally:
+        F.fip_destroy(h2)
+    # malformed files (bad header, bad tile class, a mixed-precision dtype, junk): rc 2,
+    # nothing changes
+    for text in ["not-a-table\n",
+                 f"fipgemm-tune 1\ngemm {F.FIP_F64} 0 64 64 64 0 0 7 -1\n",
+                 f"fipgemm-tune 1\ngemm {F.FIP_BF16} 0 64 64 64 0 0 0 -1\n",
+                 f"fipgemm-tune 1\ngemm {F.FIP_F64} 0 64 64 64 0 0 1 -1\nrubbish\n"]:
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text)
+        assert F.fip_tune_load(h, str(bad)) == 2, text
+    rc, p5 = F.fip_plan(h, F.FIP_F64, 0, 64, 64, 64, "N", "N")
+    assert rc == 0 and p5.tile_class == F.fip_plan(h2 := F.fip_create()[1], F.FIP_F64, 0, 64, 64,
+                                                   64, "N", "N")[1].tile_class
+    F.fip_destroy(h2)
+    assert F.fip_tune_load(h, str(tmp_path / "missing.txt")) == 1
+    assert F.fip_tune_load(h, None) == 1
+    assert F.fip_tune_save(h, None) == 1
+    assert F.fip_tune_load(None, str(good)) == F.FIP_ERR_HANDLE
