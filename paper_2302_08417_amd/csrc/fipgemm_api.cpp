@@ -234,6 +234,28 @@ bool valid_dtype(int dtype)
     return dtype == FIP_F64 || dtype == FIP_F32 || is_complex(dtype) || mx_form_of(dtype) >= 0;
 }
 
+// The one exception to packing only fringe panels (binary64 measurements at
+// m = n = k = 8192, 8 rounds of 512 resident workgroups): when both operands
+// reach the kernel in the same orientation (both K-major or both MN-major),
+// the unpacked reads of the two run 1.8-3.2 % slower than packed ones, and
+// packing every reused panel on first touch beats both the unpacked launch
+// and pack-then-compute; with one operand of each orientation the unpacked
+// launch (direct global-to-LDS loads) stays ahead by about 1 %.  At 4096 (2
+// rounds) and in binary32 packing gained nothing.  So: binary64, at least
+// kWholePackRounds rounds of workgroups, k-loops of at least
+// kWholePackKsteps k-steps, operands of one orientation.
+constexpr int64_t kWholePackRounds = 8;
+constexpr int64_t kWholePackKsteps = 64;
+
+bool whole_panels(const Plan* pl, int layout, char tA, char tB, int64_t resident)
+{
+    if (pl->elem != 8 || pl->nK < kWholePackKsteps || !pl->shared_copy) return false;
+    if (pl->tilesKM * pl->tilesKN * pl->split < kWholePackRounds * resident) return false;
+    const bool ka_mn = pl->ks.swapped ? mn_major(true, layout, tB) : mn_major(false, layout, tA);
+    const bool kb_mn = pl->ks.swapped ? mn_major(false, layout, tA) : mn_major(true, layout, tB);
+    return ka_mn == kb_mn;
+}
+
 GemmKey gemm_key(int dtype, int layout, int64_t m, int64_t n, int64_t k, char tA, char tB)
 {
     return GemmKey{dtype, layout, m, n, k, is_trans(tA) ? 1 : 0, is_trans(tB) ? 1 : 0};
@@ -396,7 +418,9 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
             //    fringe panel (the operand's M or N extent not a multiple of
             //    the tile) is packed: its unpacked chunks take the masked,
             //    zero-filling loads, its packed chunks are zero padded and
-            //    read with the same unmasked loads as any other.
+            //    read with the same unmasked loads as any other.  Measured
+            //    exception: binary64 launches of many rounds whose operands
+            //    share one orientation pack every reused panel (whole_panels).
             //  - Complex operands (1m): a chunk that keeps whole complex
             //    elements in its vectors (the A side, a K-major B side) is
             //    loaded raw and arranged after the step's MFMAs, as fast as a
@@ -413,6 +437,13 @@ void make_plan(const fip_handle_s* h, int dtype, int layout, int64_t m, int64_t 
                 pl->kpack_b = reuse_b && (pl->ks.N % NT != 0 || kb_mn);
                 pl->kfrom_a = (int)pl->tilesKM - 1;
                 pl->kfrom_b = kb_mn ? 0 : (int)pl->tilesKN - 1;
+            } else if (whole_panels(pl, layout, tA, tB, resident)) {
+                // the reuse table itself (n > n_R, m > m_R): with one copy for
+                // the device and 8 or more rounds, every panel of an operand
+                // that several tiles read is read again in a later round
+                pl->kpack_a = pl->tilesKN > 1;
+                pl->kpack_b = pl->tilesKM > 1;
+                pl->kfrom_a = pl->kfrom_b = 0;
             } else {
                 pl->kpack_a = reuse_a && pl->ks.M % MT != 0;
                 pl->kpack_b = reuse_b && pl->ks.N % NT != 0;

@@ -663,3 +663,37 @@ def test_tune_table_load_save(h, tmp_path):
     assert F.fip_tune_load(h, None) == 1
     assert F.fip_tune_save(h, None) == 1
     assert F.fip_tune_load(None, str(good)) == F.FIP_ERR_HANDLE
+
+
+def test_whole_panel_rule(h):
+    """AUTO's one exception to fringe-only packing: binary64, at least 8 rounds of resident
+    workgroups, k-loops of at least 64 k-steps, and both operands reaching the kernel in the
+    same orientation, one copy for the device: every panel that several tiles read is packed
+    from the first one on.  One operand of each orientation, binary32, 2 rounds, a short k-loop
+    or per-XCD copies: the fringe rule (nothing here)."""
+    def pk(dtype, layout, tA, tB, n=8192, k=8192):
+        rc, p = F.fip_plan(h, dtype, layout, n, n, k, tA, tB)
+        assert rc == 0
+        return p.pack_a, p.pack_b, p.a_pack_first, p.b_pack_first, p.a_kmajor, p.b_kmajor
+    assert F.fip_set_attr(h, F.FIP_ATTR_PACK_POLICY, F.FIP_PACK_AUTO) == 0
+    for layout, tA, tB in [(0, "T", "N"), (0, "N", "T"), (1, "N", "T"), (1, "T", "N")]:
+        r = pk(F.FIP_F64, layout, tA, tB)
+        assert r[4] == r[5], (layout, tA, tB)             # one orientation
+        assert r[:4] == (1, 1, 0, 0), (layout, tA, tB)
+    for layout, tA, tB in [(0, "N", "N"), (0, "T", "T"), (1, "N", "N"), (1, "T", "T")]:
+        r = pk(F.FIP_F64, layout, tA, tB)
+        assert r[4] != r[5] and r[:2] == (0, 0), (layout, tA, tB)
+    assert pk(F.FIP_F32, 0, "T", "N")[:2] == (0, 0)           # binary32
+    assert pk(F.FIP_F64, 0, "T", "N", n=4096, k=4096)[:2] == (0, 0)   # 2 rounds
+    assert pk(F.FIP_F64, 0, "T", "N", k=1008)[:2] == (0, 0)   # 63 k-steps
+    assert pk(F.FIP_F64, 0, "T", "N", k=1024)[:2] == (1, 1)   # 64 k-steps
+    # a fringe keeps the whole-panel decision (every panel, the fringe one included)
+    rc, p = F.fip_plan(h, F.FIP_F64, 0, 8190, 8190, 8192, "T", "N")
+    assert rc == 0 and (p.pack_a, p.pack_b, p.a_pack_first, p.b_pack_first) == (1, 1, 0, 0)
+    assert p.copies == 1
+    # per-XCD copies: the fringe rule as before
+    try:
+        assert F.fip_set_attr(h, F.FIP_ATTR_COPIES, 8) == 0
+        assert pk(F.FIP_F64, 0, "T", "N")[:2] == (0, 0)
+    finally:
+        F.fip_set_attr(h, F.FIP_ATTR_COPIES, -1)

@@ -1,7 +1,8 @@
 """GPU parity of each decision of AUTO's stride rule (paper Sec. 3.3's conditions read for this
 GPU): an operand whose extent is a multiple of the tile is read unpacked; one with a fringe has
 only its fringe panel packed, on first touch, and that panel's packed bytes equal the oracle's
-reference pack; a k-loop of fewer than 4 k-steps packs nothing.  Every result is checked against
+reference pack; a k-loop of fewer than 4 k-steps packs nothing; binary64 launches of 8 or more
+rounds whose operands share one orientation pack every panel.  Every result is checked against
 the oracle and bit for bit against the unpacked path (the same kernel and k order)."""
 import sys
 
@@ -9,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gemm_util import check_full, check_mx, to_dev
+from gemm_util import check_full, check_mx, check_sampled, to_dev
 from paper_2302_08417_amd import synth
 from paper_2302_08417_amd.synth import COL, ROW
 
@@ -128,3 +129,38 @@ def test_bf16_fringe_panels_only(F):
             assert p.pack_a and p.a_pack_first == p.tiles_m - 1 and p.MT == 128
     assert np.array_equal(outs[F.FIP_PACK_AUTO].view(np.uint8), outs[F.FIP_PACK_NONE].view(np.uint8))
     check_mx(c, outs[F.FIP_PACK_AUTO])
+
+
+@pytest.mark.parametrize("layout,tA,tB", [(COL, "T", "N"), (ROW, "N", "T")])
+def test_whole_panels_same_orientation(F, layout, tA, tB):
+    """binary64, 8192 x 8192 (8 rounds of 128 x 128 tiles), k = 1024 (64 k-steps), both operands
+    K-major in the kernel: AUTO packs every panel of both on first touch; C equals the unpacked
+    launch's bit for bit and the oracle on sampled entries; the first and last panels of each
+    operand equal the oracle's reference pack."""
+    m = n = 8192
+    k = 1024
+    c = synth.make_case(layout, m, n, k, tA, tB, alpha=1.5, beta=0.5, dtype=np.float64, seed=95)
+    say("whole panels", layout, tA, tB)
+    ref, _ = run(F, c, F.FIP_PACK_NONE, tile=-1)
+    out, h = run(F, c, F.FIP_PACK_AUTO, tile=-1)
+    p = h.last_plan()
+    assert (p.pack_a, p.pack_b, p.a_pack_first, p.b_pack_first, p.copies) == (1, 1, 0, 0, 1)
+    assert p.MT == 128 and p.a_kmajor == p.b_kmajor
+    assert np.array_equal(out.view(np.uint8), ref.view(np.uint8))
+    check_sampled(c, out, count=2048)
+    ws = h.workspace
+    epoch = np.uint64(h.get_attr(F.FIP_ATTR_EPOCH))
+    for X, ld, t, mn, ntiles, off_pack, copy_bytes, off_claim, off_flag, is_b in [
+            (c.A, c.lda, tA, m, p.tiles_m, p.a_pack_offset, p.a_copy_bytes, p.a_claim_offset,
+             p.a_flag_offset, 0),
+            (c.B, c.ldb, tB, n, p.tiles_n, p.b_pack_offset, p.b_copy_bytes, p.b_claim_offset,
+             p.b_flag_offset, 1)]:
+        claims = _u64(ws, off_claim, ntiles)
+        flags = _u64(ws, off_flag, ntiles)
+        assert (claims == epoch).all() and (flags == epoch).all(), is_b
+        refpack = oracle.pack(X, is_b, layout, t, mn, k, ld, 128, p.KT).view(np.uint8)
+        panel = refpack.size // ntiles
+        assert copy_bytes == refpack.size
+        for tt in (0, ntiles - 1):
+            got = ws[off_pack + tt * panel: off_pack + (tt + 1) * panel].cpu().numpy()
+            assert np.array_equal(got, refpack[tt * panel:(tt + 1) * panel]), (is_b, tt)
