@@ -11,8 +11,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfipgemm.so")
-SOURCES = ["fipgemm_kernels.hip", "fipgemm_mx.hip", "fipgemm_batched.hip", "fipgemm_scratch.hip",
-           "fipgemm_trsm.hip", "fipgemm_api.cpp"]
+# the two mixed-precision units first: they take the longest and compile side by side
+SOURCES = ["fipgemm_mx_fp8big.hip", "fipgemm_mx.hip", "fipgemm_kernels.hip", "fipgemm_batched.hip",
+           "fipgemm_scratch.hip", "fipgemm_trsm.hip", "fipgemm_api.cpp"]
 ARCH = os.environ.get("FIPGEMM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

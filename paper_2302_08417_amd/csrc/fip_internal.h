@@ -169,6 +169,9 @@ struct MxLaunchDesc {
 hipError_t launch_gemm_mx(const MxLaunchDesc& d);
 // Standalone pack of both operands (copy 0) in the form's packed layout.
 hipError_t launch_pack_mx(const MxLaunchDesc& d);
+// The E4M3 256 x 256 tile (its own translation unit): GEMM (pack false) or
+// standalone pack (pack true) launch.
+hipError_t launch_mx_fp8_big(const MxLaunchDesc& d, bool pack);
 // FP8 quantization of a binary32 matrix with power-of-two line scales.
 hipError_t launch_quantize_fp8(int layout_col, int64_t rows, int64_t cols, const float* X,
                                int64_t ldx, int axis, uint8_t* Q, int64_t ldq, float* scales,
