@@ -723,6 +723,36 @@ def cpu_oracle_rate(n, target_s):
     return 2.0 * n * cols * n / t / 1e9, cols, t, oracle.num_threads()
 
 
+def cpu_oracle_sizes(sizes=(256, 512, 1024, 2048, 4096), batch=2000):
+    """Context for the CPU baseline: the oracle on whole square binary64 problems (column-major
+    NN, every entry of C) at each size, and on the first `batch` problems of the 10,000-problem
+    batched workload (binary32 operands, the oracle computes in binary64), all threads.  Only
+    timed here, never a reference for anything."""
+    import numpy as np
+    import oracle
+    from paper_2302_08417_amd import synth
+    out = {"threads": oracle.num_threads(), "square_gflops": {}}
+    for n in sizes:
+        c = synth.make_case(0, n, n, n, "N", "N", alpha=1.5, beta=0.5, dtype=np.float64,
+                            seed=synth.BASE_SEED + n)
+        t = time.perf_counter()
+        oracle.gemm(0, n, n, n, c.alpha, c.A, c.lda, "N", c.B, c.ldb, "N", c.beta, c.C, c.ldc)
+        dt = time.perf_counter() - t
+        out["square_gflops"][str(n)] = round(2.0 * n ** 3 / dt / 1e9, 3)
+    b = synth.make_batch(batch, synth.COL, lo=4, hi=512, seed=synth.BASE_SEED + 3)
+    fl = 0.0
+    t = time.perf_counter()
+    for i in range(batch):
+        m, n, k = int(b.m[i]), int(b.n[i]), int(b.k[i])
+        oracle.gemm(0, m, n, k, b.alpha, b.A[i], int(b.lda[i]), chr(b.transA[i]), b.B[i],
+                    int(b.ldb[i]), chr(b.transB[i]), b.beta, b.C[i], int(b.ldc[i]))
+        fl += 2.0 * m * n * k
+    dt = time.perf_counter() - t
+    out["batched_sample"] = {"problems": batch, "gflops": round(fl / dt / 1e9, 3),
+                             "seconds": round(dt, 2)}
+    return out
+
+
 def cpu_baseline(n, target_s=10.0, one_thread_s=6.0):
     """The oracle timed on the host: all the threads OpenMP gives it, and one thread (in a child
     process started with OMP_NUM_THREADS=1, so the setting cannot leak into this one)."""
@@ -998,6 +1028,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(n)
+        full["cpu_oracle_sizes"] = cpu_oracle_sizes()
+        log(f"[bench] cpu oracle sizes {full['cpu_oracle_sizes']}")
     if args.results:
         os.makedirs(os.path.dirname(os.path.abspath(args.results)), exist_ok=True)
         with open(args.results, "w") as f:
